@@ -1,0 +1,236 @@
+"""Cloaked weight layout: shuffles, virtual pages, page map, pack/unpack (oracle).
+
+What the paper fixes (CloakLM, arXiv 2606.18400):
+
+* Inter-layer randomisation: the order in which tensors are transferred and
+  mapped is permuted, so adjacent virtual regions no longer mean adjacent
+  layers (Section 4.2, "Inter-layer randomization via virtual address
+  shuffling"; Table 1a).
+* Intra-layer shuffling is named in the abstract without a mechanism.
+  Reading: a seeded permutation of each FFN's hidden neurons -- rows of gate
+  and up, columns of down -- which leaves the FFN function unchanged.
+* Physical page remapping: tensors are spread over non-contiguous,
+  non-sequential physical pages of a pool (Section 4.2, "Physical page
+  remapping"; Table 1b).  Pages are 2 MB in the paper; any power of two works.
+* Everything is drawn from the seeded generator before any weight is
+  transferred (Section 5, Implementation Details).
+
+Conventions (readings, shared by the library only through this written
+definition, never through code):
+
+* A tensor is stored as the nn.Linear array ``W[N][K]`` (output channel ``n``
+  is row ``n``, K contiguous).  Element sizes: f32 4, bf16 2, fp8-e4m3 1.
+* Tensor index ``t`` is the caller's order (layer-major).  ``sigma`` =
+  Fisher-Yates(T, tag 1): tensor ``sigma[i]`` is placed i-th in the virtual
+  page stream, each tensor starting on a fresh page.
+* ``pi[l]`` = Fisher-Yates(d_ffn, tag 2, idx l).  Shuffled storage is
+  ``gate_s[j] = gate[pi[j]]``, ``up_s[j] = up[pi[j]]``, ``down_s[:, j] =
+  down[:, pi[j]]`` (gather convention: slot ``j`` holds item ``pi[j]``).
+* ``phi`` = Fisher-Yates(P, tag 3) over all ``P = pool_bytes / page_bytes``
+  pages: virtual page ``v`` lives at physical page ``phi[v]``; virtual pages
+  ``V..P-1`` are the free pages, which hold zeros.
+* Upload order of tensor ``t``'s pages: Fisher-Yates(npages_t, tag 4, idx t).
+* With ``identity=True`` every permutation is the identity: the plain
+  contiguous, layer-ordered layout used as the uncloaked comparator.
+"""
+
+import numpy as np
+
+from . import prng
+
+KINDS = ("q", "k", "v", "o", "gate", "up", "down", "embed", "head")
+ELT_BYTES = {"f32": 4, "bf16": 2, "fp8": 1}
+STORAGE_DTYPE = {"f32": np.float32, "bf16": np.uint16, "fp8": np.uint8}
+FFN_ROW_PERMUTED = ("gate", "up")   # hidden dim is N: rows permuted
+FFN_COL_PERMUTED = ("down",)        # hidden dim is K: columns permuted
+
+
+class Shape:
+    """One weight tensor: (layer, kind, n_out, k_in, dtype)."""
+
+    def __init__(self, layer, kind, n_out, k_in, dtype):
+        if kind not in KINDS:
+            raise ValueError(f"unknown kind {kind}")
+        if dtype not in ELT_BYTES:
+            raise ValueError(f"unknown dtype {dtype}")
+        self.layer, self.kind = int(layer), kind
+        self.n_out, self.k_in, self.dtype = int(n_out), int(k_in), dtype
+
+    @property
+    def nbytes(self):
+        return self.n_out * self.k_in * ELT_BYTES[self.dtype]
+
+    def __repr__(self):
+        return f"Shape({self.layer},{self.kind},{self.n_out},{self.k_in},{self.dtype})"
+
+
+class Layout:
+    """Plain record of every layout decision (all lists of Python ints)."""
+
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+    def hidden_dim_of(self, t):
+        s = self.shapes[t]
+        if s.kind in FFN_ROW_PERMUTED:
+            return s.n_out
+        if s.kind in FFN_COL_PERMUTED:
+            return s.k_in
+        return None
+
+
+def build_layout(seed, shapes, page_bytes, pool_bytes, identity=False):
+    """Draw sigma, pi_l, the virtual page assignment and phi."""
+    if page_bytes <= 0 or pool_bytes % page_bytes != 0:
+        raise ValueError("pool_bytes must be a positive multiple of page_bytes")
+    T = len(shapes)
+    P = pool_bytes // page_bytes
+
+    # Inter-layer shuffle: the order tensors occupy the virtual page stream.
+    sigma = list(range(T)) if identity else prng.fisher_yates(
+        T, prng.substream(seed, prng.TAG_TENSOR_ORDER, 0))
+
+    # Intra-layer shuffle: one hidden-neuron permutation per FFN layer.
+    d_ffn = {}
+    seen = set()
+    for s in shapes:
+        if (s.layer, s.kind) in seen:
+            raise ValueError(f"duplicate tensor {s}")
+        seen.add((s.layer, s.kind))
+        h = s.n_out if s.kind in FFN_ROW_PERMUTED else (
+            s.k_in if s.kind in FFN_COL_PERMUTED else None)
+        if h is None:
+            continue
+        if d_ffn.setdefault(s.layer, h) != h:
+            raise ValueError(f"inconsistent hidden size in layer {s.layer}")
+    pi = {}
+    for layer, h in sorted(d_ffn.items()):
+        pi[layer] = list(range(h)) if identity else prng.fisher_yates(
+            h, prng.substream(seed, prng.TAG_HIDDEN_PERM, layer))
+
+    # Virtual pages: tensors in sigma order, each starting on a fresh page.
+    npages = [-(-s.nbytes // page_bytes) for s in shapes]
+    vbase = [0] * T
+    cursor = 0
+    for i in range(T):
+        t = sigma[i]
+        vbase[t] = cursor
+        cursor += npages[t]
+    V = cursor
+    if V > P:
+        raise MemoryError(f"layout needs {V} pages, pool has {P}")
+
+    # Physical placement: a bijection over every page of the pool.
+    phi = list(range(P)) if identity else prng.fisher_yates(
+        P, prng.substream(seed, prng.TAG_PAGE_MAP, 0))
+
+    return Layout(seed=seed, shapes=list(shapes), page_bytes=page_bytes,
+                  pool_bytes=pool_bytes, P=P, V=V, T=T, sigma=sigma, pi=pi,
+                  npages=npages, vbase=vbase, phi=phi, identity=identity)
+
+
+def upload_order(layout, t):
+    """Seeded order in which tensor t's virtual pages cross the bus."""
+    n = layout.npages[t]
+    if layout.identity:
+        return list(range(n))
+    return prng.fisher_yates(n, prng.substream(layout.seed, prng.TAG_UPLOAD_ORDER, t))
+
+
+def shuffle_tensor(layout, t, w):
+    """Logical nn.Linear array -> stored (hidden-neuron permuted) array."""
+    s = layout.shapes[t]
+    w = np.asarray(w)
+    assert w.shape == (s.n_out, s.k_in)
+    if s.kind in FFN_ROW_PERMUTED:
+        return w[np.asarray(layout.pi[s.layer]), :]
+    if s.kind in FFN_COL_PERMUTED:
+        return w[:, np.asarray(layout.pi[s.layer])]
+    return w
+
+
+def unshuffle_tensor(layout, t, ws):
+    """Inverse of shuffle_tensor (scatter back through pi)."""
+    s = layout.shapes[t]
+    out = np.empty_like(ws)
+    if s.kind in FFN_ROW_PERMUTED:
+        out[np.asarray(layout.pi[s.layer]), :] = ws
+    elif s.kind in FFN_COL_PERMUTED:
+        out[:, np.asarray(layout.pi[s.layer])] = ws
+    else:
+        out[...] = ws
+    return out
+
+
+def shuffle_scales(layout, t, scales):
+    """Per-output-channel scales follow the rows they belong to."""
+    s = layout.shapes[t]
+    scales = np.asarray(scales, dtype=np.float32)
+    if s.kind in FFN_ROW_PERMUTED:
+        return scales[np.asarray(layout.pi[s.layer])]
+    return scales
+
+
+def tensor_stream(layout, t, w):
+    """Virtual byte stream of tensor t: shuffled rows, row-major, zero padded."""
+    s = layout.shapes[t]
+    ws = np.ascontiguousarray(shuffle_tensor(layout, t, w).astype(STORAGE_DTYPE[s.dtype]))
+    raw = ws.view(np.uint8).reshape(-1)
+    out = np.zeros(layout.npages[t] * layout.page_bytes, dtype=np.uint8)
+    out[: raw.size] = raw
+    return out
+
+
+def pack(layout, weights):
+    """Pool image: virtual page v of every tensor copied to physical page phi[v].
+
+    ``weights[t]`` is the logical array of tensor t (or None to leave its
+    pages zero).  Free pages are zero.
+    """
+    B = layout.page_bytes
+    pool = np.zeros(layout.P * B, dtype=np.uint8)
+    for t, w in enumerate(weights):
+        if w is None:
+            continue
+        stream = tensor_stream(layout, t, w)
+        for i in range(layout.npages[t]):
+            p = layout.phi[layout.vbase[t] + i]
+            pool[p * B:(p + 1) * B] = stream[i * B:(i + 1) * B]
+    return pool
+
+
+def unpack(layout, pool, t):
+    """Read tensor t back from a pool image and undo the hidden shuffle."""
+    s = layout.shapes[t]
+    B = layout.page_bytes
+    pages = [pool[layout.phi[layout.vbase[t] + i] * B:(layout.phi[layout.vbase[t] + i] + 1) * B]
+             for i in range(layout.npages[t])]
+    stream = np.concatenate(pages) if pages else np.zeros(0, np.uint8)
+    raw = np.ascontiguousarray(stream[: s.nbytes])
+    ws = raw.view(STORAGE_DTYPE[s.dtype]).reshape(s.n_out, s.k_in)
+    return unshuffle_tensor(layout, t, ws)
+
+
+def virtual_to_physical(layout, t, byte_offset):
+    """Physical pool byte holding byte ``byte_offset`` of tensor t's stream."""
+    B = layout.page_bytes
+    v = layout.vbase[t] + byte_offset // B
+    return layout.phi[v] * B + byte_offset % B
+
+
+def contiguity(layout):
+    """Share of in-tensor page successions that stay physically adjacent.
+
+    The paper reports the percentage of virtual ranges backed by contiguous
+    physical pages (Table 2).  Reading: over every pair of consecutive
+    virtual pages inside one tensor, the fraction whose physical pages are
+    also consecutive.  Returns a fraction in [0, 1] (1.0 if no pairs).
+    """
+    hits = total = 0
+    for t in range(layout.T):
+        for i in range(layout.npages[t] - 1):
+            total += 1
+            a = layout.phi[layout.vbase[t] + i]
+            b = layout.phi[layout.vbase[t] + i + 1]
+            hits += (b == a + 1)
+    return 1.0 if total == 0 else hits / total

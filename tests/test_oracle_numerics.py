@@ -1,0 +1,123 @@
+"""Pins for exact weight decoding and the FP64 linear / SwiGLU references."""
+
+import os
+
+import numpy as np
+import pytest
+
+from oracle import layout as L
+from oracle import numerics as N
+from paper_2606_18400_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_bf16_decode_known_patterns():
+    bits = np.array([0x3F80, 0xC000, 0x0000, 0x8000, 0x7F80, 0xFF80, 0x0001, 0x4049], np.uint16)
+    v = N.bf16_bits_to_f64(bits)
+    assert v[0] == 1.0 and v[1] == -2.0 and v[2] == 0.0
+    assert np.signbit(v[3]) and v[3] == 0.0
+    assert v[4] == np.inf and v[5] == -np.inf
+    assert v[6] == 2.0 ** -133          # smallest bf16 subnormal
+    assert v[7] == 3.140625             # 0x4049 = 1.5703125 * 2
+
+
+def test_e4m3_decode_spec_table():
+    for line in open(os.path.join(GOLDEN, "e4m3fn_values.txt")):
+        if not line.strip() or line.startswith("#"):
+            continue
+        b, val = line.split()
+        got = N.e4m3_bits_to_f64(np.array([int(b, 16)], np.uint8))[0]
+        if val == "nan":
+            assert np.isnan(got)
+        else:
+            assert got == float(val) and np.signbit(got) == val.startswith("-")
+
+
+def test_e4m3_positive_codes_strictly_increase():
+    v = N.e4m3_bits_to_f64(np.arange(0, 0x7F, dtype=np.uint8))
+    assert np.all(np.diff(v) > 0) and v[-1] == 448.0
+
+
+def test_fp8_weights_scale_rows():
+    q = np.array([[0x38, 0x40], [0xB8, 0x00]], np.uint8)
+    s = np.array([0.5, 3.0], np.float32)
+    assert np.array_equal(N.weights_f64(q, "fp8", s), np.array([[0.5, 1.0], [-3.0, 0.0]]))
+
+
+def test_linear_exact_on_small_integers_vs_triple_loop():
+    rng = np.random.Generator(np.random.PCG64(1))
+    x = rng.integers(-8, 9, (3, 7)).astype(np.float64)
+    w = rng.integers(-8, 9, (5, 7)).astype(np.float64)
+    y = N.linear(x, w)
+    for m in range(3):
+        for n in range(5):
+            assert y[m, n] == sum(x[m, k] * w[n, k] for k in range(7))
+
+
+def test_silu_closed_forms():
+    z = np.linspace(-30, 30, 601)
+    s = N.silu(z)
+    assert N.silu(0.0) == 0.0
+    np.testing.assert_allclose(s - N.silu(-z), z, rtol=0, atol=1e-12)   # x*sig(x) + x*sig(-x) = x
+    assert abs(N.silu(40.0) - 40.0) < 1e-15 * 40 + 1e-12
+    assert abs(N.silu(1.0) - 1.0 / (1.0 + np.exp(-1.0))) < 1e-16
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_ffn_invariant_under_hidden_permutation(seed):
+    d, f, M = 32, 48, 5
+    shapes = [L.Shape(0, "gate", f, d, "f32"), L.Shape(0, "up", f, d, "f32"),
+              L.Shape(0, "down", d, f, "f32")]
+    lay = L.build_layout(seed, shapes, 256, 256 * 128)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    wg, wu, wd = (rng.standard_normal((s.n_out, s.k_in)) for s in shapes)
+    x = rng.standard_normal((M, d))
+    y, h = N.swiglu_ffn(x, wg, wu, wd)
+    # the FFN evaluated directly on the stored (shuffled) arrays
+    gs, us, ds = (L.shuffle_tensor(lay, t, w) for t, w in enumerate((wg, wu, wd)))
+    ys, hs = N.swiglu_ffn(x, gs, us, ds)
+    assert N.normwise_err(ys, y) <= 1e-12
+    # hidden activations come out in permuted order: hs[:, j] == h[:, pi[j]]
+    assert np.array_equal(hs, h[:, lay.pi[0]])
+    assert lay.pi[0] != list(range(f))
+
+
+def test_normwise_err():
+    assert N.normwise_err([1.0, -2.0], [1.0, -2.0]) == 0.0
+    assert N.normwise_err([1.0, -2.5], [1.0, -2.0]) == 0.25
+    assert N.normwise_err([0.0], [0.0]) == 0.0
+
+
+def test_bf16_rne_ties_and_overflow():
+    f = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, -1 - 2 ** -9,
+                  np.float32(3.4028235e38), np.nan], np.float32)
+    b = N.f32_to_bf16_bits_rne(f)
+    assert list(b[:5]) == [0x3F80, 0x3F80, 0x3F82, 0xBF80, 0x7F80]
+    assert (int(b[5]) & 0x7F80) == 0x7F80 and (int(b[5]) & 0x7F)
+
+
+def test_synth_bf16_rounding_agrees_with_oracle_rne():
+    x = np.random.Generator(np.random.PCG64(0)).standard_normal(100000).astype(np.float32)
+    assert np.array_equal(synth.f32_to_bf16_rne(x), N.f32_to_bf16_bits_rne(x))
+
+
+def test_synth_fp8_quantiser_is_nearest_even_saturating():
+    # Brute force against every finite E4M3 code (decoded by the oracle).
+    codes = np.array([c for c in range(256) if (c & 0x7F) != 0x7F], np.uint8)
+    vals = N.e4m3_bits_to_f64(codes)
+    rng = np.random.Generator(np.random.PCG64(2))
+    xs = np.concatenate([rng.standard_normal(4000) * 100, rng.standard_normal(2000) * 0.01,
+                         vals, (vals[:-1] + vals[1:]) / 2, [500.0, -1e6, 0.0]])
+    q = synth.f32_to_e4m3_rne(xs)
+    got = N.e4m3_bits_to_f64(q)
+    for x, g, qb in zip(xs, got, q):
+        if abs(x) >= 448:
+            assert g == np.copysign(448.0, x)
+            continue
+        d = np.abs(vals - x)
+        best = d.min()
+        assert abs(g - x) == best
+        ties = codes[d == best]
+        if len(ties) > 1 and best > 0:   # exact tie: even mantissa wins
+            assert (int(qb) & 1) == 0

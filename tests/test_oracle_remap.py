@@ -1,0 +1,70 @@
+"""Pins for the oracle's remap: involution, zero-scratch moves, gather invariance."""
+
+import numpy as np
+import pytest
+
+from oracle import layout as L
+from oracle import prng
+from oracle import remap as R
+from test_oracle_layout import random_weights, tiny_shapes
+
+
+@pytest.mark.parametrize("P", [1, 2, 7, 64, 257])
+def test_matching_is_an_involution(P):
+    tau = R.matching(42, P)
+    assert sorted(tau) == list(range(P))
+    assert all(tau[tau[p]] == p for p in range(P))
+    fixed = sum(tau[p] == p for p in range(P))
+    assert fixed == P % 2
+
+
+def test_matching_pairs_consecutive_draws():
+    P = 10
+    s = prng.fisher_yates(P, prng.substream(5, prng.TAG_REMAP, 0))
+    tau = R.matching(5, P)
+    for i in range(P // 2):
+        assert tau[s[2 * i]] == s[2 * i + 1]
+
+
+@pytest.mark.parametrize("remap_seed", [1, 2, 3])
+def test_remap_preserves_every_tensor(remap_seed):
+    shapes = tiny_shapes("bf16")
+    lay = L.build_layout(8, shapes, 64, 64 * 256)
+    ws = random_weights(shapes, 3)
+    pool = L.pack(lay, ws)
+    pool2, phi2 = R.remap(pool, lay.phi, remap_seed, 64)
+    assert sorted(phi2) == list(range(lay.P))
+    lay2 = L.Layout(**{**lay.__dict__, "phi": phi2})
+    for t in range(lay.T):
+        assert np.array_equal(L.unpack(lay2, pool2, t), ws[t])
+    # bytes are only moved: the multiset of pages is unchanged
+    B = 64
+    pages = sorted(bytes(pool[p * B:(p + 1) * B]) for p in range(lay.P))
+    pages2 = sorted(bytes(pool2[p * B:(p + 1) * B]) for p in range(lay.P))
+    assert pages == pages2
+
+
+def test_remap_moves_each_page_to_its_partner_brute_force():
+    P, B = 16, 8
+    pool = np.arange(P * B, dtype=np.uint64).astype(np.uint8)
+    phi = list(range(P))
+    tau = R.matching(9, P)
+    out, phi2 = R.remap(pool, phi, 9, B)
+    for p in range(P):
+        for i in range(B):
+            assert out[tau[p] * B + i] == pool[p * B + i]
+    assert phi2 == tau
+
+
+def test_two_remaps_compose():
+    shapes = tiny_shapes("f32")
+    lay = L.build_layout(2, shapes, 128, 128 * 128)
+    ws = random_weights(shapes, 4)
+    pool = L.pack(lay, ws)
+    p1, f1 = R.remap(pool, lay.phi, 1, 128)
+    p2, f2 = R.remap(p1, f1, 2, 128)
+    t1, t2 = R.matching(1, lay.P), R.matching(2, lay.P)
+    assert f2 == [t2[t1[v]] for v in lay.phi]
+    lay2 = L.Layout(**{**lay.__dict__, "phi": f2})
+    for t in range(lay.T):
+        assert np.array_equal(L.unpack(lay2, p2, t), ws[t])
