@@ -1,0 +1,222 @@
+/*
+ * cloak.h -- C-ABI of libcloak, the MI355X (gfx950) cloaked linear layer.
+ *
+ * CloakLM (arXiv 2606.18400) hides where model weights sit in accelerator
+ * memory: tensors are placed in a seeded random order (inter-layer shuffle,
+ * Section 4.2 and Table 1a), each FFN's hidden neurons are permuted
+ * (intra-layer shuffle, named in the abstract), and the resulting byte
+ * streams are cut into pages scattered over a pool through a seeded
+ * virtual->physical page map that is re-randomised periodically (Section 4.2,
+ * "Physical page remapping", Table 1b).  All randomness is drawn from one seed
+ * before any weight is transferred (Section 5, Implementation Details).
+ *
+ * In this library the page map is resolved in software, inside the kernels
+ * that stream the weights (GEMV, GEMM, fused SwiGLU FFN), and the remap is a
+ * device kernel that swaps page pairs in place.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Weights are nn.Linear arrays W[N][K] (row n = output channel n, K
+ *   contiguous); y[M][N] = x[M][K] . W^T.  Activations x and results y are
+ *   row-major with leading dimension K (resp. the output width).
+ * - Element types: CLOAK_F32 weights take f32 activations and give f32
+ *   results; CLOAK_BF16 and CLOAK_FP8_E4M3 weights take bf16 activations and
+ *   give bf16 results (rounded to nearest even).  FP8 weights carry one f32
+ *   scale per output row: W[n][k] = e4m3(q[n][k]) * s[n] (OCP E4M3, max 448).
+ *   Accumulation is always f32.
+ * - Pointers named h_* are host memory, d_* device memory of the device that
+ *   cloak_layout_to_device() was called on.  `stream` is a hipStream_t passed
+ *   as void* (NULL = the null stream).
+ * - Ownership: the caller owns every large device buffer (the pool, x, y,
+ *   workspaces).  The library owns the layout and its small device tables
+ *   (page map, hidden permutations, FP8 scales), freed by cloak_layout_free().
+ * - Errors: every int-returning call returns CLOAK_OK (0) or a negative
+ *   cloak_status; arguments are checked before anything is launched, no call
+ *   aborts, and cloak_last_error() gives a message for the calling thread.
+ * - Asynchrony: device calls enqueue on `stream` and return; only
+ *   cloak_load() and cloak_unload() synchronise (they stage host memory).
+ *   Read-only calls may run concurrently on several streams; cloak_remap()
+ *   moves pages, so the caller must order it after every kernel that reads
+ *   the pool and before every later one (the paper's synchronisation point).
+ *
+ * Layout definition (every library and oracle implementation follows this)
+ * ----------------------------------------------------------------------
+ * Generator: SplitMix64 (Steele, Lea, Flood, OOPSLA 2014).  Sub-stream for
+ * (seed, tag, idx) starts from mix64(seed ^ mix64((tag << 32) | idx)).  Tags:
+ * 1 tensor order, 2 hidden permutation of layer idx, 3 page map, 4 upload
+ * order of tensor idx, 5 remap matching (keyed by the remap seed).
+ * bounded(n) rejects the (2^64 mod n) lowest outputs and returns r mod n;
+ * permutations are Fisher-Yates (Durstenfeld), i from n-1 down to 1 swapping
+ * a[i] with a[bounded(i+1)]; gather convention (slot j holds a[j]).
+ *   sigma   = FY(T, tag 1)           tensor sigma[i] is i-th in the page stream
+ *   pi_l    = FY(d_ffn, tag 2, l)    gate_s[j] = gate[pi[j]], up_s[j] = up[pi[j]],
+ *                                    down_s[:, j] = down[:, pi[j]]
+ *   vbase   each tensor starts on a fresh virtual page, tensors in sigma order,
+ *           npages = ceil(N*K*elt / page_bytes), zero padded
+ *   phi     = FY(P, tag 3) over all P = pool_bytes/page_bytes pages; virtual
+ *           page v lives at physical page phi[v]; pages V..P-1 are free
+ *   remap   s = FY(P, tag 5); pair (s[2i], s[2i+1]); each pair swaps contents;
+ *           phi' = tau o phi
+ */
+#ifndef CLOAK_H
+#define CLOAK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cloak_layout cloak_layout; /* opaque, owned by the library */
+
+typedef enum {
+  CLOAK_OK = 0,
+  CLOAK_EINVAL = -1, /* bad argument (null pointer, out-of-range index, bad size) */
+  CLOAK_ENOMEM = -2, /* pool too small for the layout, or host/device allocation failed */
+  CLOAK_EHIP = -3,   /* a HIP runtime call failed; cloak_last_error() has its message */
+  CLOAK_ESHAPE = -4, /* shapes inconsistent (duplicate tensor, hidden sizes disagree, K mismatch) */
+  CLOAK_EDTYPE = -5, /* dtype not supported by this call */
+  CLOAK_ESTATE = -6  /* call not valid in the layout's state (no device tables, native layout) */
+} cloak_status;
+
+typedef enum { CLOAK_F32 = 0, CLOAK_BF16 = 1, CLOAK_FP8_E4M3 = 2 } cloak_dtype;
+
+typedef enum {
+  CLOAK_Q = 0, CLOAK_K = 1, CLOAK_V = 2, CLOAK_O = 3,
+  CLOAK_GATE = 4, CLOAK_UP = 5, CLOAK_DOWN = 6,
+  CLOAK_EMBED = 7, CLOAK_HEAD = 8
+} cloak_kind;
+
+/* One weight tensor, nn.Linear orientation: n_out rows of k_in elements.
+ * `layer` groups gate/up/down under one hidden permutation (any value fits in
+ * 32 bits; embed/head conventionally use -1). */
+typedef struct {
+  int32_t layer;
+  int32_t kind;  /* cloak_kind */
+  int64_t n_out;
+  int64_t k_in;
+  int32_t dtype; /* cloak_dtype */
+  int32_t reserved;
+} cloak_shape;
+
+/* Layout flags. */
+#define CLOAK_IDENTITY 1u /* sigma, pi and phi are identities: plain contiguous layer order */
+#define CLOAK_NATIVE   2u /* with CLOAK_IDENTITY: kernels address the pool contiguously with
+                             no page translation (the uncloaked comparator); remap refused */
+
+/* cloak_query() selectors. */
+#define CLOAK_QUERY_P            1  /* int64: pages in the pool                        */
+#define CLOAK_QUERY_V            2  /* int64: virtual pages used by tensors             */
+#define CLOAK_QUERY_T            3  /* int64: number of tensors                         */
+#define CLOAK_QUERY_PAGE_BYTES   4  /* int64                                            */
+#define CLOAK_QUERY_PHI          5  /* int32[P]: current page map                       */
+#define CLOAK_QUERY_SIGMA        6  /* int32[T]: tensor order                           */
+#define CLOAK_QUERY_PI           7  /* int32[d_ffn]: hidden permutation of layer `index`*/
+#define CLOAK_QUERY_VBASE        8  /* int64[T]                                          */
+#define CLOAK_QUERY_NPAGES       9  /* int64[T]                                          */
+#define CLOAK_QUERY_CONTIGUITY  10  /* double: share of in-tensor page successions that
+                                       stay physically adjacent (Table 2 statistic)     */
+#define CLOAK_QUERY_UPLOAD_ORDER 11 /* int32[npages of tensor `index`]                  */
+#define CLOAK_QUERY_REMAPS      12  /* int64: remaps applied since build                */
+#define CLOAK_QUERY_TENSOR      13  /* int64: index of tensor (layer = index >> 8,
+                                       kind = index & 255), or -1                        */
+#define CLOAK_QUERY_DFFN        14  /* int64: hidden size of layer `index` (0 if no FFN) */
+
+/* Workspace selectors for cloak_ws_bytes(). */
+#define CLOAK_OP_LINEAR 1
+#define CLOAK_OP_MLP    2
+
+/* Draw the layout from `seed` for `n_shapes` tensors (Section 5: all
+ * permutations and page placements are fixed before any transfer).  Host
+ * only, touches no device.  page_bytes must be a power of two >= 1024 and
+ * divide pool_bytes.  Errors: EINVAL (sizes, kinds, dtypes), ESHAPE
+ * (duplicate (layer, kind), inconsistent hidden sizes), ENOMEM (the tensors
+ * need more than P pages).  On success *out owns the layout. */
+int cloak_layout_build(uint64_t seed, const cloak_shape* shapes, int32_t n_shapes,
+                       uint64_t page_bytes, uint64_t pool_bytes, uint32_t flags,
+                       cloak_layout** out);
+
+/* Free the layout and its device tables (waits for nothing: the caller must
+ * not free while kernels that use the layout are in flight). NULL is a no-op. */
+int cloak_layout_free(cloak_layout* layout);
+
+/* Allocate and upload the device tables (page map, hidden permutations, FP8
+ * scales) on the current device; required before any device call.  Idempotent. */
+int cloak_layout_to_device(cloak_layout* layout, void* stream);
+
+/* Copy a property of the layout into `out` (out_bytes must be large enough;
+ * sizes listed with the selectors).  EINVAL on unknown selector / short buffer. */
+int cloak_query(const cloak_layout* layout, int32_t what, int64_t index, void* out,
+                uint64_t out_bytes);
+
+/* Zero the whole pool (free pages and padding hold zeros).  d_pool must be
+ * 256-byte aligned and at least pool_bytes long. */
+int cloak_pool_init(const cloak_layout* layout, void* d_pool, void* stream);
+
+/* Upload tensor `tensor` from its logical nn.Linear array h_src ([N][K] of
+ * the tensor's storage type; FP8 as raw E4M3 bytes) into the pool: apply the
+ * hidden permutation, cut the stream into pages and copy page v to physical
+ * page phi[v], pages in the seeded upload order (Section 4.2: the transfer
+ * order is permuted; Section 5: layout fixed before transfer).  h_scales
+ * ([N] f32, logical order) is required for FP8 and must be NULL otherwise.
+ * Synchronises `stream` before returning. */
+int cloak_load(cloak_layout* layout, void* d_pool, int32_t tensor, const void* h_src,
+               const float* h_scales, void* stream);
+
+/* Inverse of cloak_load (for verification): gather tensor `tensor` from the
+ * pool into the logical array h_dst.  Synchronises `stream`. */
+int cloak_unload(const cloak_layout* layout, const void* d_pool, int32_t tensor, void* h_dst,
+                 void* stream);
+
+/* Host-side image of cloak_load: write tensor `tensor`'s pages into a host
+ * buffer h_pool of pool_bytes (the same bytes cloak_load writes to the
+ * device).  No device needed.  FP8 scales are not part of the pool image. */
+int cloak_pack_host(const cloak_layout* layout, int32_t tensor, const void* h_src,
+                    void* h_pool, uint64_t h_pool_bytes);
+
+/* Bytes of device workspace `op` needs for `index` (tensor for LINEAR, layer
+ * for MLP) at M tokens.  0 if none; UINT64_MAX on bad arguments. */
+uint64_t cloak_ws_bytes(const cloak_layout* layout, int32_t op, int32_t index, int64_t M);
+
+/* y[M][N] = x[M][K] . W^T for tensor `tensor`, with x and y in LOGICAL
+ * order: for gate/up the kernel scatters stored row j to column pi[j]; for
+ * down it gathers x through pi while staging it.  Weights are read straight
+ * from the scattered pages (virtual tile -> physical page resolved in the
+ * kernel).  M = 0 is a no-op.  Workspace as reported by cloak_ws_bytes. */
+int cloak_linear(const cloak_layout* layout, const void* d_pool, int32_t tensor,
+                 const void* d_x, int64_t M, void* d_y, void* d_ws, uint64_t ws_bytes,
+                 void* stream);
+
+/* Several tensors with the same K in one launch (e.g. q, k, v): y is
+ * [M][sum N_i], tensor i's columns at offset sum_{j<i} N_j.  n <= 4. */
+int cloak_linear_fused(const cloak_layout* layout, const void* d_pool, const int32_t* tensors,
+                       int32_t n, const void* d_x, int64_t M, void* d_y, void* d_ws,
+                       uint64_t ws_bytes, void* stream);
+
+/* SwiGLU FFN of layer `layer`: y = (silu(x Wg^T) * (x Wu^T)) Wd^T, with
+ * silu(z) = z / (1 + e^-z), run directly on the shuffled weights: the hidden
+ * activations stay in permuted order (bf16 for bf16/fp8 weights, f32 for f32)
+ * in the workspace, so the permutation cancels between up/gate and down. */
+int cloak_mlp(const cloak_layout* layout, const void* d_pool, int32_t layer, const void* d_x,
+              int64_t M, void* d_y, void* d_ws, uint64_t ws_bytes, void* stream);
+
+/* Re-randomise page placement in place (Section 4.2, periodic remapping
+ * with no extra memory footprint): draw the matching tau from remap_seed,
+ * swap every page pair in the pool on `stream`, and set phi' = tau o phi on
+ * host and device.  Refused (ESTATE) on CLOAK_NATIVE layouts. */
+int cloak_remap(cloak_layout* layout, void* d_pool, uint64_t remap_seed, void* stream);
+
+/* Host-side remap of a pool image h_pool (pool_bytes) and of the layout's
+ * page map; the same result cloak_remap produces on the device.  Updates
+ * only the host copy of phi: do not mix with device calls on one layout. */
+int cloak_remap_host(cloak_layout* layout, void* h_pool, uint64_t h_pool_bytes,
+                     uint64_t remap_seed);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* cloak_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CLOAK_H */

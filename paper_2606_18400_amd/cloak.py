@@ -1,0 +1,295 @@
+"""ctypes binding of libcloak (include/cloak.h): argument marshalling only.
+
+Every function here has the name and meaning of the C entry point it wraps;
+all of the work happens in the library (host layout code and HIP kernels).
+Device buffers may be passed as torch tensors (their ``data_ptr()`` is used)
+or as raw integer addresses; host buffers are NumPy arrays.  ``stream=None``
+means torch's current stream on the current device.
+
+Importing this module fails loudly when ``libcloak.so`` has not been built;
+there is no fallback of any kind.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcloak.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_2606_18400_amd.build` "
+        "(or __graft_entry__.build()); the cloaked path has no fallback")
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---------------------------------------------------------------- constants
+CLOAK_OK, CLOAK_EINVAL, CLOAK_ENOMEM, CLOAK_EHIP, CLOAK_ESHAPE, CLOAK_EDTYPE, CLOAK_ESTATE = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESHAPE", -5: "EDTYPE", -6: "ESTATE"}
+DTYPES = {"f32": 0, "bf16": 1, "fp8": 2}
+KINDS = {"q": 0, "k": 1, "v": 2, "o": 3, "gate": 4, "up": 5, "down": 6, "embed": 7, "head": 8}
+CLOAK_IDENTITY = 1
+CLOAK_NATIVE = 2
+QUERY = dict(P=1, V=2, T=3, PAGE_BYTES=4, PHI=5, SIGMA=6, PI=7, VBASE=8, NPAGES=9, CONTIGUITY=10,
+             UPLOAD_ORDER=11, REMAPS=12, TENSOR=13, DFFN=14)
+CLOAK_OP_LINEAR, CLOAK_OP_MLP = 1, 2
+STORAGE = {"f32": np.float32, "bf16": np.uint16, "fp8": np.uint8}
+
+
+class cloak_shape(ctypes.Structure):
+    _fields_ = [("layer", ctypes.c_int32), ("kind", ctypes.c_int32), ("n_out", ctypes.c_int64),
+                ("k_in", ctypes.c_int64), ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class CloakError(RuntimeError):
+    def __init__(self, code, fn, msg):
+        super().__init__(f"{fn} failed with {STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_vp, _i32, _i64, _u64, _u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32
+_SIGS = {
+    "cloak_layout_build": ([_u64, ctypes.POINTER(cloak_shape), _i32, _u64, _u64, _u32, ctypes.POINTER(_vp)], _i32),
+    "cloak_layout_free": ([_vp], _i32),
+    "cloak_layout_to_device": ([_vp, _vp], _i32),
+    "cloak_query": ([_vp, _i32, _i64, _vp, _u64], _i32),
+    "cloak_pool_init": ([_vp, _vp, _vp], _i32),
+    "cloak_load": ([_vp, _vp, _i32, _vp, _vp, _vp], _i32),
+    "cloak_unload": ([_vp, _vp, _i32, _vp, _vp], _i32),
+    "cloak_pack_host": ([_vp, _i32, _vp, _vp, _u64], _i32),
+    "cloak_ws_bytes": ([_vp, _i32, _i32, _i64], _u64),
+    "cloak_linear": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _u64, _vp], _i32),
+    "cloak_linear_fused": ([_vp, _vp, ctypes.POINTER(_i32), _i32, _vp, _i64, _vp, _vp, _u64, _vp], _i32),
+    "cloak_mlp": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _u64, _vp], _i32),
+    "cloak_remap": ([_vp, _vp, _u64, _vp], _i32),
+    "cloak_remap_host": ([_vp, _vp, _u64, _u64], _i32),
+    "cloak_last_error": ([], ctypes.c_char_p),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes, _f.restype = _args, _res
+
+EXPORTED = tuple(_SIGS)
+
+
+def cloak_last_error():
+    return _lib.cloak_last_error().decode()
+
+
+def _check(rc, fn):
+    if rc != CLOAK_OK:
+        raise CloakError(rc, fn, cloak_last_error())
+
+
+def _ptr(obj):
+    if obj is None:
+        return None
+    if isinstance(obj, int):
+        return obj
+    if hasattr(obj, "data_ptr"):
+        return obj.data_ptr()
+    if isinstance(obj, np.ndarray):
+        if not obj.flags["C_CONTIGUOUS"]:
+            raise ValueError("host arrays must be C-contiguous")
+        return obj.ctypes.data
+    raise TypeError(f"cannot take the address of {type(obj)}")
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
+    return stream
+
+
+def _shape(s):
+    layer, kind, n, k, dtype = s
+    return cloak_shape(int(layer), KINDS[kind] if isinstance(kind, str) else int(kind), int(n), int(k),
+                       DTYPES[dtype] if isinstance(dtype, str) else int(dtype), 0)
+
+
+# ---------------------------------------------------------------- entry points
+def cloak_layout_build(seed, shapes, page_bytes, pool_bytes, flags=0):
+    arr = (cloak_shape * len(shapes))(*[_shape(s) for s in shapes])
+    out = _vp()
+    _check(_lib.cloak_layout_build(seed & ((1 << 64) - 1), arr, len(shapes), page_bytes, pool_bytes, flags,
+                                   ctypes.byref(out)), "cloak_layout_build")
+    return out.value
+
+
+def cloak_layout_free(layout):
+    _check(_lib.cloak_layout_free(layout), "cloak_layout_free")
+
+
+def cloak_layout_to_device(layout, stream=None):
+    _check(_lib.cloak_layout_to_device(layout, _stream(stream)), "cloak_layout_to_device")
+
+
+def cloak_query(layout, what, index=0):
+    """Returns an int / float, or a NumPy array for the table selectors."""
+    q = QUERY[what] if isinstance(what, str) else what
+    if q in (QUERY["P"], QUERY["V"], QUERY["T"], QUERY["PAGE_BYTES"], QUERY["REMAPS"], QUERY["TENSOR"],
+             QUERY["DFFN"]):
+        v = _i64()
+        _check(_lib.cloak_query(layout, q, index, ctypes.byref(v), 8), "cloak_query")
+        return v.value
+    if q == QUERY["CONTIGUITY"]:
+        v = ctypes.c_double()
+        _check(_lib.cloak_query(layout, q, index, ctypes.byref(v), 8), "cloak_query")
+        return v.value
+    sizes = {QUERY["PHI"]: lambda: cloak_query(layout, "P"),
+         QUERY["SIGMA"]: lambda: cloak_query(layout, "T"),
+         QUERY["VBASE"]: lambda: cloak_query(layout, "T"),
+         QUERY["NPAGES"]: lambda: cloak_query(layout, "T"),
+         QUERY["UPLOAD_ORDER"]: lambda: int(cloak_query(layout, "NPAGES")[index]),
+         QUERY["PI"]: lambda: cloak_query(layout, "DFFN", index)}
+    if q not in sizes:
+        v = _i64()   # unknown selector: let the library report it
+        _check(_lib.cloak_query(layout, q, index, ctypes.byref(v), 8), "cloak_query")
+        return v.value
+    n = sizes[q]()
+    dtype = np.int64 if q in (QUERY["VBASE"], QUERY["NPAGES"]) else np.int32
+    out = np.zeros(n, dtype=dtype)
+    _check(_lib.cloak_query(layout, q, index, out.ctypes.data, out.nbytes), "cloak_query")
+    return out
+
+
+def cloak_pool_init(layout, pool, stream=None):
+    _check(_lib.cloak_pool_init(layout, _ptr(pool), _stream(stream)), "cloak_pool_init")
+
+
+def cloak_load(layout, pool, tensor, src, scales=None, stream=None):
+    src = np.ascontiguousarray(src)
+    sc = None if scales is None else np.ascontiguousarray(scales, dtype=np.float32)
+    _check(_lib.cloak_load(layout, _ptr(pool), tensor, src.ctypes.data, None if sc is None else sc.ctypes.data,
+                           _stream(stream)), "cloak_load")
+
+
+def cloak_unload(layout, pool, tensor, dst, stream=None):
+    _check(_lib.cloak_unload(layout, _ptr(pool), tensor, _ptr(dst), _stream(stream)), "cloak_unload")
+
+
+def cloak_pack_host(layout, tensor, src, pool_image):
+    src = np.ascontiguousarray(src)
+    _check(_lib.cloak_pack_host(layout, tensor, src.ctypes.data, _ptr(pool_image), pool_image.nbytes),
+           "cloak_pack_host")
+
+
+def cloak_ws_bytes(layout, op, index, M):
+    v = _lib.cloak_ws_bytes(layout, op, index, M)
+    if v == (1 << 64) - 1:
+        raise CloakError(CLOAK_EINVAL, "cloak_ws_bytes", "bad arguments")
+    return v
+
+
+def cloak_linear(layout, pool, tensor, x, M, y, ws=None, ws_bytes=0, stream=None):
+    _check(_lib.cloak_linear(layout, _ptr(pool), tensor, _ptr(x), M, _ptr(y), _ptr(ws), ws_bytes,
+                             _stream(stream)), "cloak_linear")
+
+
+def cloak_linear_fused(layout, pool, tensors, x, M, y, ws=None, ws_bytes=0, stream=None):
+    arr = (_i32 * len(tensors))(*tensors)
+    _check(_lib.cloak_linear_fused(layout, _ptr(pool), arr, len(tensors), _ptr(x), M, _ptr(y), _ptr(ws),
+                                   ws_bytes, _stream(stream)), "cloak_linear_fused")
+
+
+def cloak_mlp(layout, pool, layer, x, M, y, ws, ws_bytes, stream=None):
+    _check(_lib.cloak_mlp(layout, _ptr(pool), layer, _ptr(x), M, _ptr(y), _ptr(ws), ws_bytes, _stream(stream)),
+           "cloak_mlp")
+
+
+def cloak_remap(layout, pool, remap_seed, stream=None):
+    _check(_lib.cloak_remap(layout, _ptr(pool), remap_seed & ((1 << 64) - 1), _stream(stream)), "cloak_remap")
+
+
+def cloak_remap_host(layout, pool_image, remap_seed):
+    _check(_lib.cloak_remap_host(layout, _ptr(pool_image), pool_image.nbytes, remap_seed & ((1 << 64) - 1)),
+           "cloak_remap_host")
+
+
+# ---------------------------------------------------------------- convenience
+class CloakedWeights:
+    """A layout, its device pool and the tensors loaded into it.
+
+    ``seed=None`` draws the layout seed from the operating system's entropy
+    source, as the paper does before deployment; tests pass fixed seeds.
+    PyTorch only allocates the pool and workspaces and supplies the stream.
+    """
+
+    def __init__(self, shapes, page_bytes, pool_bytes, seed=None, flags=0):
+        import torch
+        self.shapes = [tuple(s) for s in shapes]
+        self.seed = int.from_bytes(os.urandom(8), "little") if seed is None else int(seed)
+        self.flags = flags
+        self.layout = cloak_layout_build(self.seed, self.shapes, page_bytes, pool_bytes, flags)
+        cloak_layout_to_device(self.layout)
+        self.pool = torch.empty(pool_bytes, dtype=torch.uint8, device="cuda")
+        cloak_pool_init(self.layout, self.pool)
+        self.page_bytes, self.pool_bytes = page_bytes, pool_bytes
+        self._ws = {}
+
+    def index(self, layer, kind):
+        return cloak_query(self.layout, "TENSOR", (int(layer) << 8) | KINDS[kind])
+
+    def load(self, weights, scales=None):
+        """Upload every tensor, in the shuffled tensor order (sigma)."""
+        sigma = cloak_query(self.layout, "SIGMA")
+        for t in sigma:
+            sc = None if scales is None else scales[t]
+            cloak_load(self.layout, self.pool, int(t), weights[t], sc)
+
+    def workspace(self, nbytes):
+        import torch
+        nbytes = max(int(nbytes), 256)
+        ws = self._ws.get("mlp")
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            self._ws["mlp"] = ws
+        return ws
+
+    def linear(self, t, x, out=None):
+        import torch
+        n = self.shapes[t][2]
+        M = x.shape[0]
+        if out is None:
+            out = torch.empty((M, n), dtype=x.dtype, device=x.device)
+        cloak_linear(self.layout, self.pool, t, x, M, out)
+        return out
+
+    def linear_fused(self, ts, x, out=None):
+        import torch
+        n = sum(self.shapes[t][2] for t in ts)
+        M = x.shape[0]
+        if out is None:
+            out = torch.empty((M, n), dtype=x.dtype, device=x.device)
+        cloak_linear_fused(self.layout, self.pool, list(ts), x, M, out)
+        return out
+
+    def mlp(self, layer, x, out=None):
+        import torch
+        M = x.shape[0]
+        need = cloak_ws_bytes(self.layout, CLOAK_OP_MLP, layer, M)
+        ws = self.workspace(need)
+        if out is None:
+            out = torch.empty_like(x)
+        cloak_mlp(self.layout, self.pool, layer, x, M, out, ws, ws.numel())
+        return out
+
+    def remap(self, remap_seed=None):
+        s = int.from_bytes(os.urandom(8), "little") if remap_seed is None else int(remap_seed)
+        cloak_remap(self.layout, self.pool, s)
+
+    def close(self):
+        if self.layout:
+            import torch
+            torch.cuda.synchronize()
+            cloak_layout_free(self.layout)
+            self.layout = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

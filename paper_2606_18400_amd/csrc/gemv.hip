@@ -1,0 +1,385 @@
+// Decode GEMV over cloaked weights (CloakLM, arXiv 2606.18400, Section 4.2:
+// weights live in scattered physical pages; inference is bandwidth-bound,
+// so placement must not cost bandwidth).
+//
+// Shape of the work on gfx950:
+//  * A weight row is streamed in 1 KiB "chunks": one wave-wide load of 16 B
+//    per lane.  Rows are multiples of 16 B and pages powers of two >= 1 KiB,
+//    so a chunk that starts 1 KiB-aligned in the tensor's stream sits inside
+//    one page: the virtual->physical translation is ONE scalar load of the
+//    page map per chunk (a second one only for rows whose size is not a
+//    multiple of 1 KiB, where a chunk can cross a page boundary).
+//  * The waves of a workgroup split a row's chunks (wave w takes chunks
+//    w, w+W, ...) and every wave works on R rows at once, so each lane keeps
+//    R independent 16 B loads in flight per chunk.
+//  * The activations are gathered once per workgroup (through the hidden
+//    permutation when the tensor's K is the permuted hidden dimension) into
+//    registers: a wave only ever needs x at its own chunk positions.
+//  * Dot products: v_dot2_f32_bf16 on bf16 pairs (FP8 weights are widened to
+//    bf16 with v_cvt_scalef32_pk_bf16_fp8, exact for every E4M3 value), FMA
+//    for f32; accumulation in f32.
+//  * Reduction: a transposing butterfly over the 64 lanes (R*MT values are
+//    reduced in about R*MT + 6 shuffles instead of 6*R*MT), then a sum over
+//    the waves through LDS; the epilogue applies FP8 row scales, the output
+//    scatter of gate/up rows, or the SwiGLU product of paired gate/up rows.
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "kernels.hpp"
+
+namespace cloak {
+namespace {
+
+typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2_t;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kChunkBytes = 1024;
+constexpr int kMaxWaves = 8;
+
+template <int WT> struct WTraits;
+template <> struct WTraits<kF32> { static constexpr int EPL = 4; static constexpr int XW = 4; };
+template <> struct WTraits<kBF16> { static constexpr int EPL = 8; static constexpr int XW = 4; };
+template <> struct WTraits<kFP8> { static constexpr int EPL = 16; static constexpr int XW = 8; };
+
+__device__ inline uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+__device__ inline bf16x2_t as_bf16x2(uint32_t v) { return __builtin_bit_cast(bf16x2_t, v); }
+
+// Segment fields picked with an unrolled select so the by-value kernel
+// argument is never indexed dynamically.
+struct SegView {
+  int64_t vbase, npages;
+  const int32_t* out_perm;
+  const float* scale;
+  int32_t rows, row0, out_off;
+};
+
+__device__ inline SegView seg_view(const GemvArgs& a, int s) {
+  SegView v;
+  v.vbase = a.seg[0].vbase; v.npages = a.seg[0].npages; v.out_perm = a.seg[0].out_perm;
+  v.scale = a.seg[0].scale; v.rows = a.seg[0].rows; v.row0 = a.seg[0].row0; v.out_off = a.seg[0].out_off;
+#pragma unroll
+  for (int i = 1; i < 4; ++i) {
+    if (s == i) {
+      v.vbase = a.seg[i].vbase; v.npages = a.seg[i].npages; v.out_perm = a.seg[i].out_perm;
+      v.scale = a.seg[i].scale; v.rows = a.seg[i].rows; v.row0 = a.seg[i].row0; v.out_off = a.seg[i].out_off;
+    }
+  }
+  return v;
+}
+
+// Row r of group g -> (segment, stored row n).  Returns false past the end.
+template <int R>
+__device__ inline bool resolve_row(const GemvArgs& a, int g, int r, int& s, int& n) {
+  if (a.mode == kSwiGLU) {
+    s = r < R / 2 ? 0 : 1;
+    n = g * (R / 2) + (r % (R / 2));
+    return n < a.seg[0].rows;
+  }
+  const int row = g * R + r;
+  s = 0;
+#pragma unroll
+  for (int i = 1; i < 4; ++i)
+    if (i < a.nseg && row >= a.seg[i].row0) s = i;
+  const SegView v = seg_view(a, s);
+  n = row - v.row0;
+  return n < v.rows;
+}
+
+template <int WT>
+__device__ inline void load_x(const GemvArgs& a, int c, int m, int lane, uint32_t (&xr)[WTraits<WT>::XW]) {
+  constexpr int EPL = WTraits<WT>::EPL;
+  const int k0 = c * 64 * EPL + lane * EPL;
+  const bool tok = m < a.mcount;
+  if constexpr (WT == kF32) {
+    const float* xp = static_cast<const float*>(a.x) + int64_t(a.m0 + m) * a.ldx;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const int k = k0 + e;
+      float v = 0.f;
+      if (tok && k < a.K) v = xp[a.x_perm ? a.x_perm[k] : k];
+      xr[e] = __float_as_uint(v);
+    }
+  } else {
+    const uint16_t* xp = static_cast<const uint16_t*>(a.x) + int64_t(a.m0 + m) * a.ldx;
+#pragma unroll
+    for (int e = 0; e < EPL; e += 2) {
+      const int k = k0 + e;
+      uint32_t lo = 0, hi = 0;
+      if (tok && k < a.K) lo = xp[a.x_perm ? a.x_perm[k] : k];
+      if (tok && k + 1 < a.K) hi = xp[a.x_perm ? a.x_perm[k + 1] : k + 1];
+      xr[e / 2] = lo | (hi << 16);
+    }
+  }
+}
+
+// 16 B of stored row n, chunk c, for this lane; zero when the lane is past
+// the end of the row.
+template <bool TR>
+__device__ inline u32x4 load_w(const GemvArgs& a, const SegView& v, int n, int c, int lane, bool lane_ok) {
+  const int64_t o = int64_t(n) * a.row_bytes + int64_t(c) * kChunkBytes;
+  const int64_t page_bytes = int64_t(1) << a.log2_page;
+  const int64_t vp = o >> a.log2_page;
+  const int64_t inpage = o & (page_bytes - 1);
+  const int64_t vpage = v.vbase + vp;
+  const int64_t p0 = TR ? int64_t(a.phi[vpage]) : vpage;
+  u32x4 w = {0u, 0u, 0u, 0u};
+  if (inpage + kChunkBytes <= page_bytes) {
+    // common case: the whole chunk sits in one page, uniform base address
+    const uint8_t* base = a.pool + (p0 << a.log2_page) + inpage;
+    if (lane_ok) w = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(base) + lane);
+  } else {
+    // ragged rows only: the chunk crosses into the next virtual page
+    const int64_t p1 = (vp + 1 < v.npages) ? (TR ? int64_t(a.phi[vpage + 1]) : vpage + 1) : p0;
+    const int64_t lo = inpage + int64_t(lane) * 16;
+    const bool second = lo >= page_bytes;
+    const int64_t phys = second ? p1 : p0;
+    const uint8_t* addr = a.pool + (phys << a.log2_page) + (second ? lo - page_bytes : lo);
+    if (lane_ok) w = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(addr));
+  }
+  return w;
+}
+
+template <int WT>
+__device__ inline float dot_chunk(const u32x4 w, const uint32_t (&x)[WTraits<WT>::XW], float acc) {
+  if constexpr (WT == kF32) {
+    acc = fmaf(__uint_as_float(w.x), __uint_as_float(x[0]), acc);
+    acc = fmaf(__uint_as_float(w.y), __uint_as_float(x[1]), acc);
+    acc = fmaf(__uint_as_float(w.z), __uint_as_float(x[2]), acc);
+    acc = fmaf(__uint_as_float(w.w), __uint_as_float(x[3]), acc);
+  } else if constexpr (WT == kBF16) {
+    acc = __builtin_amdgcn_fdot2_f32_bf16(as_bf16x2(w.x), as_bf16x2(x[0]), acc, false);
+    acc = __builtin_amdgcn_fdot2_f32_bf16(as_bf16x2(w.y), as_bf16x2(x[1]), acc, false);
+    acc = __builtin_amdgcn_fdot2_f32_bf16(as_bf16x2(w.z), as_bf16x2(x[2]), acc, false);
+    acc = __builtin_amdgcn_fdot2_f32_bf16(as_bf16x2(w.w), as_bf16x2(x[3]), acc, false);
+  } else {
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const bf16x2_t lo = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(ws[i], 1.0f, false);
+      const bf16x2_t hi = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(ws[i], 1.0f, true);
+      acc = __builtin_amdgcn_fdot2_f32_bf16(lo, as_bf16x2(x[2 * i]), acc, false);
+      acc = __builtin_amdgcn_fdot2_f32_bf16(hi, as_bf16x2(x[2 * i + 1]), acc, false);
+    }
+  }
+  return acc;
+}
+
+// Transposing butterfly: on entry v[0..V) are per-lane partials; on exit
+// v[0] of lane l is the 64-lane sum of value index (l >> (6 - log2 V)).
+template <int V>
+__device__ inline void lane_reduce(float (&v)[V], int lane) {
+  int count = V;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const bool upper = (lane & d) != 0;
+    if (count > 1) {
+      const int h = count / 2;
+#pragma unroll
+      for (int i = 0; i < V / 2; ++i) {
+        if (i < h) {
+          const float send = upper ? v[i] : v[i + h];
+          const float keep = upper ? v[i + h] : v[i];
+          v[i] = keep + __shfl_xor(send, d);
+        }
+      }
+      count = h;
+    } else {
+      v[0] += __shfl_xor(v[0], d);
+    }
+  }
+}
+
+template <int N> struct Log2 { static constexpr int value = 1 + Log2<N / 2>::value; };
+template <> struct Log2<1> { static constexpr int value = 0; };
+
+template <int WT, int MT, int R, int CPW, bool TR>
+__global__ __launch_bounds__(512) void gemv_kernel(const GemvArgs a) {
+  constexpr int XW = WTraits<WT>::XW;
+  constexpr int EPL = WTraits<WT>::EPL;
+  constexpr int V = R * MT;
+  constexpr int LOG2V = Log2<V>::value;
+  static_assert((1 << LOG2V) == V && V <= 64, "R*MT must be a power of two <= 64");
+  __shared__ float red[2][kMaxWaves][V];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nwaves = blockDim.x >> 6;
+
+  uint32_t xr[CPW][MT][XW];
+#pragma unroll
+  for (int i = 0; i < CPW; ++i) {
+    const int c = wave + i * nwaves;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      if (c < a.nchunks) {
+        load_x<WT>(a, c, m, lane, xr[i][m]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < XW; ++e) xr[i][m][e] = 0u;
+      }
+    }
+  }
+
+  int it = 0;
+  for (int g = blockIdx.x; g < a.groups; g += gridDim.x, ++it) {
+    float v[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) v[j] = 0.f;
+#pragma unroll
+    for (int i = 0; i < CPW; ++i) {
+      const int c = wave + i * nwaves;
+      const bool lane_ok = (c * 64 * EPL + lane * EPL) < a.K;
+      u32x4 w[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        int s, n;
+        const bool ok = resolve_row<R>(a, g, r, s, n);
+        if (ok && c < a.nchunks) {
+          w[r] = load_w<TR>(a, seg_view(a, s), n, c, lane, lane_ok);
+        } else {
+          w[r] = u32x4{0u, 0u, 0u, 0u};
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m) v[r * MT + m] = dot_chunk<WT>(w[r], xr[i][m], v[r * MT + m]);
+      }
+    }
+    lane_reduce<V>(v, lane);
+    const int buf = it & 1;
+    if ((lane & ((64 >> LOG2V) - 1)) == 0) red[buf][wave][lane >> (6 - LOG2V)] = v[0];
+    __syncthreads();
+
+    const int t = threadIdx.x;
+    if (a.mode == kStore) {
+      if (t < V) {
+        float sum = 0.f;
+        for (int ww = 0; ww < nwaves; ++ww) sum += red[buf][ww][t];
+        const int r = t / MT, m = t % MT;
+        int s, n;
+        if (resolve_row<R>(a, g, r, s, n) && m < a.mcount) {
+          const SegView sv = seg_view(a, s);
+          if (sv.scale) sum *= sv.scale[n];
+          const int col = sv.out_off + (sv.out_perm ? sv.out_perm[n] : n);
+          const int64_t idx = int64_t(a.m0 + m) * a.ldy + col;
+          if constexpr (WT == kF32) {
+            static_cast<float*>(a.y)[idx] = sum;
+          } else {
+            static_cast<uint16_t*>(a.y)[idx] = f32_to_bf16_rne(sum);
+          }
+        }
+      }
+    } else {
+      if (t < V / 2) {
+        float gs = 0.f, us = 0.f;
+        for (int ww = 0; ww < nwaves; ++ww) {
+          gs += red[buf][ww][t];
+          us += red[buf][ww][t + V / 2];
+        }
+        const int r = t / MT, m = t % MT;
+        const int h = g * (R / 2) + r;
+        if (h < a.seg[0].rows && m < a.mcount) {
+          if (a.seg[0].scale) gs *= a.seg[0].scale[h];
+          if (a.seg[1].scale) us *= a.seg[1].scale[h];
+          const float hv = gs / (1.0f + expf(-gs)) * us;
+          const int64_t idx = int64_t(a.m0 + m) * a.ldy + h;
+          if constexpr (WT == kF32) {
+            static_cast<float*>(a.y)[idx] = hv;
+          } else {
+            static_cast<uint16_t*>(a.y)[idx] = f32_to_bf16_rne(hv);
+          }
+        }
+      }
+    }
+  }
+}
+
+using KernelFn = void (*)(const GemvArgs);
+
+// Largest token tile that keeps a wave's activations (CPW * MT * XW words)
+// in registers without spilling at 256 VGPRs.
+int max_mtile(int wt, int cpw) {
+  if (wt == kFP8) return cpw <= 1 ? 8 : cpw == 2 ? 4 : cpw == 4 ? 2 : 1;
+  return cpw <= 2 ? 8 : cpw == 4 ? 4 : 2;
+}
+
+template <int WT, int CPW, bool TR>
+KernelFn pick_mt(int mt) {
+  constexpr int kMax = WT == kFP8 ? (CPW <= 1 ? 8 : CPW == 2 ? 4 : CPW == 4 ? 2 : 1)
+                                  : (CPW <= 2 ? 8 : CPW == 4 ? 4 : 2);
+  if (mt <= 1) return gemv_kernel<WT, 1, 8, CPW, TR>;
+  if (mt <= 2 || kMax == 2) return gemv_kernel<WT, (kMax < 2 ? 1 : 2), 8, CPW, TR>;
+  if (mt <= 4 || kMax == 4) return gemv_kernel<WT, (kMax < 4 ? 1 : 4), 8, CPW, TR>;
+  return gemv_kernel<WT, (kMax < 8 ? 1 : 8), 8, CPW, TR>;
+}
+
+template <int WT, bool TR>
+KernelFn pick_cpw(int cpw, int mt) {
+  switch (cpw) {
+    case 1: return pick_mt<WT, 1, TR>(mt);
+    case 2: return pick_mt<WT, 2, TR>(mt);
+    case 4: return pick_mt<WT, 4, TR>(mt);
+    default: return pick_mt<WT, 8, TR>(mt);
+  }
+}
+
+KernelFn pick(int wt, bool tr, int cpw, int mt) {
+  if (wt == kF32) return tr ? pick_cpw<kF32, true>(cpw, mt) : pick_cpw<kF32, false>(cpw, mt);
+  if (wt == kBF16) return tr ? pick_cpw<kBF16, true>(cpw, mt) : pick_cpw<kBF16, false>(cpw, mt);
+  return tr ? pick_cpw<kFP8, true>(cpw, mt) : pick_cpw<kFP8, false>(cpw, mt);
+}
+
+int resident_blocks(KernelFn fn, int threads) {
+  static std::mutex mu;
+  static std::map<std::pair<void*, int>, int> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto key = std::make_pair(reinterpret_cast<void*>(fn), threads);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), threads, 0) !=
+      hipSuccess)
+    return 0;
+  const int n = cus * (per_cu > 0 ? per_cu : 1);
+  cache[key] = n;
+  return n;
+}
+
+}  // namespace
+
+int gemv_cpw(int nchunks) {
+  int cpw = 1;
+  while ((nchunks + cpw - 1) / cpw > kMaxWaves) cpw *= 2;
+  return cpw;
+}
+
+int gemv_max_tokens(int wtype, int nchunks) { return max_mtile(wtype, gemv_cpw(nchunks)); }
+
+hipError_t launch_gemv(const GemvArgs& a, int wtype, int mtile, bool translate, hipStream_t s) {
+  if (a.groups <= 0) return hipSuccess;
+  const int cpw = gemv_cpw(a.nchunks);
+  if (cpw > 8 || mtile > max_mtile(wtype, cpw) || a.mcount > mtile) return hipErrorInvalidValue;
+  const int waves = (a.nchunks + cpw - 1) / cpw;
+  const int threads = waves * 64;
+  KernelFn fn = pick(wtype, translate, cpw, mtile);
+  int blocks = resident_blocks(fn, threads);
+  if (blocks <= 0) blocks = a.groups;
+  if (blocks > a.groups) blocks = a.groups;
+  hipLaunchKernelGGL(fn, dim3(blocks), dim3(threads), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace cloak

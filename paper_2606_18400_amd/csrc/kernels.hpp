@@ -1,0 +1,60 @@
+// Launch arguments and launchers of libcloak's HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cloak {
+
+// One weight tensor taking part in a launch.  Its stored rows are read from
+// the virtual page stream that starts at virtual page `vbase`.
+struct WSeg {
+  int64_t vbase;            // first virtual page of the tensor
+  int64_t npages;           // pages of the tensor
+  const int32_t* out_perm;  // logical output column of stored row j (gate/up), or null
+  const float* scale;       // per stored row (FP8 weights), or null
+  int32_t rows;             // N of the tensor
+  int32_t row0;             // first launch-row of this tensor
+  int32_t out_off;          // column offset of this tensor in y
+  int32_t pad;
+};
+
+enum WType : int { kF32 = 0, kBF16 = 1, kFP8 = 2 };
+enum Epilogue : int { kStore = 0, kSwiGLU = 1 };
+
+struct GemvArgs {
+  const uint8_t* pool;
+  const int32_t* phi;       // device page map (ignored by the untranslated twin)
+  int32_t log2_page;
+  int32_t row_bytes;        // K * element size
+  int32_t K;
+  int32_t nchunks;          // 1 KiB chunks per row (last one may be partial)
+  int32_t nseg;
+  int32_t groups;           // row groups (STORE) or hidden-unit groups (SWIGLU)
+  WSeg seg[4];
+  const void* x;            // [M][ldx] f32 or bf16 (logical order)
+  const int32_t* x_perm;    // gather: stored column j reads x[:, x_perm[j]] (down), or null
+  void* y;                  // [M][ldy] f32 or bf16
+  int64_t ldx, ldy;
+  int32_t m0, mcount;       // token block handled by this launch
+  int32_t mode;             // Epilogue
+  int32_t pad;
+};
+
+// Decode GEMV (VALU dot products, wave-level K split, 1 KiB page-translated
+// wave loads).  `translate` false is the uncloaked twin used on native layouts.
+hipError_t launch_gemv(const GemvArgs& a, int wtype, int mtile, bool translate, hipStream_t s);
+// Token tile limit of the GEMV for this weight type and row length.
+int gemv_max_tokens(int wtype, int nchunks);
+
+struct SwapArgs {
+  uint8_t* pool;
+  const int32_t* pairs;     // [2*npairs] physical page pairs
+  int64_t npairs;
+  int32_t log2_page;
+  int32_t pad;
+};
+hipError_t launch_swap(const SwapArgs& a, hipStream_t s);
+
+}  // namespace cloak

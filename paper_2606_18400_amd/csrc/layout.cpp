@@ -1,0 +1,460 @@
+// Layout core of libcloak: seeded draws, the layout descriptor, host-side
+// page streams and the remap matching.  Pure host C++; the definitions it
+// implements are written out in include/cloak.h (CloakLM, arXiv 2606.18400:
+// inter-layer order Section 4.2 / Table 1a, page placement Section 4.2 /
+// Table 1b, seeding before transfer Section 5).
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "cloak_internal.hpp"
+
+namespace cloak {
+
+static thread_local std::string g_error;
+
+void set_error(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+}
+void clear_error() { g_error.clear(); }
+const char* last_error() { return g_error.c_str(); }
+
+// SplitMix64: Weyl state advanced by the golden-ratio increment, output
+// through the variant-13 finaliser (Steele, Lea, Flood, OOPSLA 2014).
+uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+uint64_t SplitMix64::next() {
+  state += 0x9E3779B97F4A7C15ull;
+  return mix64(state);
+}
+
+SplitMix64 substream(uint64_t seed, uint32_t tag, uint32_t idx) {
+  SplitMix64 g;
+  g.state = mix64(seed ^ mix64((uint64_t(tag) << 32) | uint64_t(idx)));
+  return g;
+}
+
+// Uniform draw on [0, n): the 2^64 mod n smallest outputs are rejected so the
+// remaining range is a whole number of copies of [0, n).
+uint64_t bounded(SplitMix64& g, uint64_t n) {
+  const uint64_t reject_below = (0 - n) % n;  // == 2^64 mod n
+  for (;;) {
+    uint64_t r = g.next();
+    if (r >= reject_below) return r % n;
+  }
+}
+
+// Durstenfeld's in-place Fisher-Yates walk from the top slot down.
+std::vector<int32_t> fisher_yates(int64_t n, SplitMix64 g) {
+  std::vector<int32_t> a(static_cast<size_t>(n));
+  for (int64_t i = 0; i < n; ++i) a[i] = static_cast<int32_t>(i);
+  for (int64_t i = n - 1; i >= 1; --i) {
+    int64_t j = static_cast<int64_t>(bounded(g, static_cast<uint64_t>(i + 1)));
+    std::swap(a[i], a[j]);
+  }
+  return a;
+}
+
+std::vector<int32_t> upload_order(const cloak_layout* L, int32_t t) {
+  const int64_t n = L->tensors[t].npages;
+  if (L->identity()) {
+    std::vector<int32_t> a(n);
+    for (int64_t i = 0; i < n; ++i) a[i] = int32_t(i);
+    return a;
+  }
+  return fisher_yates(n, substream(L->seed, kTagUpload, uint32_t(t)));
+}
+
+std::vector<int32_t> remap_matching(uint64_t remap_seed, int64_t P) {
+  std::vector<int32_t> s = fisher_yates(P, substream(remap_seed, kTagRemap, 0));
+  std::vector<int32_t> tau(P);
+  for (int64_t p = 0; p < P; ++p) tau[p] = int32_t(p);
+  for (int64_t i = 0; 2 * i + 1 < P; ++i) {
+    tau[s[2 * i]] = s[2 * i + 1];
+    tau[s[2 * i + 1]] = s[2 * i];
+  }
+  return tau;
+}
+
+double contiguity(const cloak_layout* L) {
+  int64_t hits = 0, total = 0;
+  for (const auto& ti : L->tensors) {
+    for (int64_t i = 0; i + 1 < ti.npages; ++i) {
+      ++total;
+      hits += (L->phi[ti.vbase + i + 1] == L->phi[ti.vbase + i] + 1);
+    }
+  }
+  return total ? double(hits) / double(total) : 1.0;
+}
+
+// Bytes [page*B, page*B + B) of tensor t's shuffled stream, built from the
+// logical array `src`; bytes past the tensor are zero.
+void stream_page(const cloak_layout* L, int32_t t, const uint8_t* src, int64_t page, uint8_t* dst) {
+  const TensorInfo& ti = L->tensors[t];
+  const int64_t B = L->page_bytes;
+  const int64_t begin = page * B;
+  const int64_t end = std::min(begin + B, ti.bytes);
+  std::memset(dst, 0, size_t(B));
+  if (begin >= end) return;
+  const int64_t rb = ti.row_bytes;
+  const int elt = elt_bytes(ti.shape.dtype);
+  const int32_t* pi = ti.perm_layer >= 0 ? L->ffn[ti.perm_layer].pi.data() : nullptr;
+  const int kind = ti.shape.kind;
+  int64_t o = begin;
+  while (o < end) {
+    const int64_t row = o / rb;
+    const int64_t col = o % rb;
+    const int64_t seg = std::min(end - o, rb - col);
+    if (pi && is_row_permuted(kind)) {
+      std::memcpy(dst + (o - begin), src + int64_t(pi[row]) * rb + col, size_t(seg));
+    } else if (pi && is_col_permuted(kind)) {
+      // element e of stored row `row` is logical element (row, pi[e])
+      const uint8_t* srow = src + row * rb;
+      uint8_t* d = dst + (o - begin);
+      const int64_t e0 = col / elt, e1 = (col + seg) / elt;
+      for (int64_t e = e0; e < e1; ++e) {
+        std::memcpy(d + (e - e0) * elt, srow + int64_t(pi[e]) * elt, size_t(elt));
+      }
+    } else {
+      std::memcpy(dst + (o - begin), src + o, size_t(seg));
+    }
+    o += seg;
+  }
+}
+
+// Inverse of stream_page: scatter one page of the stream back into the
+// logical array `dst`.
+void unstream_page(const cloak_layout* L, int32_t t, const uint8_t* pagebuf, int64_t page, uint8_t* dst) {
+  const TensorInfo& ti = L->tensors[t];
+  const int64_t B = L->page_bytes;
+  const int64_t begin = page * B;
+  const int64_t end = std::min(begin + B, ti.bytes);
+  if (begin >= end) return;
+  const int64_t rb = ti.row_bytes;
+  const int elt = elt_bytes(ti.shape.dtype);
+  const int32_t* pi = ti.perm_layer >= 0 ? L->ffn[ti.perm_layer].pi.data() : nullptr;
+  const int kind = ti.shape.kind;
+  int64_t o = begin;
+  while (o < end) {
+    const int64_t row = o / rb;
+    const int64_t col = o % rb;
+    const int64_t seg = std::min(end - o, rb - col);
+    if (pi && is_row_permuted(kind)) {
+      std::memcpy(dst + int64_t(pi[row]) * rb + col, pagebuf + (o - begin), size_t(seg));
+    } else if (pi && is_col_permuted(kind)) {
+      uint8_t* drow = dst + row * rb;
+      const uint8_t* s = pagebuf + (o - begin);
+      const int64_t e0 = col / elt, e1 = (col + seg) / elt;
+      for (int64_t e = e0; e < e1; ++e) {
+        std::memcpy(drow + int64_t(pi[e]) * elt, s + (e - e0) * elt, size_t(elt));
+      }
+    } else {
+      std::memcpy(dst + o, pagebuf + (o - begin), size_t(seg));
+    }
+    o += seg;
+  }
+}
+
+}  // namespace cloak
+
+int cloak_layout::find_tensor(int32_t layer, int32_t kind) const {
+  for (size_t t = 0; t < tensors.size(); ++t)
+    if (tensors[t].shape.layer == layer && tensors[t].shape.kind == kind) return int(t);
+  return -1;
+}
+
+const cloak::FfnPerm* cloak_layout::ffn_of_layer(int32_t layer) const {
+  for (const auto& f : ffn)
+    if (f.layer == layer) return &f;
+  return nullptr;
+}
+
+using namespace cloak;
+
+extern "C" const char* cloak_last_error(void) { return cloak::last_error(); }
+
+extern "C" int cloak_layout_build(uint64_t seed, const cloak_shape* shapes, int32_t n_shapes,
+                                  uint64_t page_bytes, uint64_t pool_bytes, uint32_t flags,
+                                  cloak_layout** out) {
+  clear_error();
+  if (!out || (!shapes && n_shapes > 0) || n_shapes < 0) {
+    set_error("cloak_layout_build: null argument or negative count");
+    return CLOAK_EINVAL;
+  }
+  *out = nullptr;
+  if (page_bytes < 1024 || (page_bytes & (page_bytes - 1)) != 0) {
+    set_error("cloak_layout_build: page_bytes must be a power of two >= 1024 (got %llu)",
+              (unsigned long long)page_bytes);
+    return CLOAK_EINVAL;
+  }
+  if (pool_bytes == 0 || pool_bytes % page_bytes != 0) {
+    set_error("cloak_layout_build: pool_bytes must be a positive multiple of page_bytes");
+    return CLOAK_EINVAL;
+  }
+  if ((flags & ~(CLOAK_IDENTITY | CLOAK_NATIVE)) != 0 ||
+      ((flags & CLOAK_NATIVE) && !(flags & CLOAK_IDENTITY))) {
+    set_error("cloak_layout_build: bad flags 0x%x (CLOAK_NATIVE needs CLOAK_IDENTITY)", flags);
+    return CLOAK_EINVAL;
+  }
+  const int64_t P = int64_t(pool_bytes / page_bytes);
+  if (P > INT32_MAX) {
+    set_error("cloak_layout_build: too many pages");
+    return CLOAK_EINVAL;
+  }
+  auto L = new (std::nothrow) cloak_layout();
+  if (!L) {
+    set_error("cloak_layout_build: out of host memory");
+    return CLOAK_ENOMEM;
+  }
+  L->seed = seed;
+  L->flags = flags;
+  L->page_bytes = int64_t(page_bytes);
+  while ((int64_t(1) << L->log2_page) < L->page_bytes) ++L->log2_page;
+  L->pool_bytes = int64_t(pool_bytes);
+  L->P = P;
+  const bool ident = (flags & CLOAK_IDENTITY) != 0;
+
+  // Validate shapes and collect the FFN groups.
+  L->tensors.resize(n_shapes);
+  for (int32_t t = 0; t < n_shapes; ++t) {
+    const cloak_shape& s = shapes[t];
+    if (s.kind < CLOAK_Q || s.kind > CLOAK_HEAD || s.dtype < CLOAK_F32 || s.dtype > CLOAK_FP8_E4M3 ||
+        s.n_out <= 0 || s.k_in <= 0 || s.n_out > INT32_MAX || s.k_in > INT32_MAX) {
+      set_error("cloak_layout_build: tensor %d has a bad kind/dtype/size", t);
+      delete L;
+      return CLOAK_EINVAL;
+    }
+    for (int32_t u = 0; u < t; ++u) {
+      if (shapes[u].layer == s.layer && shapes[u].kind == s.kind) {
+        set_error("cloak_layout_build: tensors %d and %d are both (layer %d, kind %d)", u, t, s.layer, s.kind);
+        delete L;
+        return CLOAK_ESHAPE;
+      }
+    }
+    TensorInfo& ti = L->tensors[t];
+    ti.shape = s;
+    ti.row_bytes = s.k_in * elt_bytes(s.dtype);
+    ti.bytes = s.n_out * ti.row_bytes;
+    ti.npages = (ti.bytes + L->page_bytes - 1) / L->page_bytes;
+    if (is_row_permuted(s.kind) || is_col_permuted(s.kind)) {
+      const int64_t h = is_row_permuted(s.kind) ? s.n_out : s.k_in;
+      int idx = -1;
+      for (size_t f = 0; f < L->ffn.size(); ++f)
+        if (L->ffn[f].layer == s.layer) idx = int(f);
+      if (idx < 0) {
+        FfnPerm fp;
+        fp.layer = s.layer;
+        fp.d_ffn = h;
+        L->ffn.push_back(fp);
+        idx = int(L->ffn.size()) - 1;
+      } else if (L->ffn[idx].d_ffn != h) {
+        set_error("cloak_layout_build: layer %d hidden sizes disagree (%lld vs %lld)", s.layer,
+                  (long long)L->ffn[idx].d_ffn, (long long)h);
+        delete L;
+        return CLOAK_ESHAPE;
+      }
+      ti.perm_layer = idx;
+      if (s.kind == CLOAK_GATE) L->ffn[idx].gate = t;
+      if (s.kind == CLOAK_UP) L->ffn[idx].up = t;
+      if (s.kind == CLOAK_DOWN) L->ffn[idx].down = t;
+    }
+    if (s.dtype == CLOAK_FP8_E4M3) {
+      ti.scale_off = L->n_scales;
+      L->n_scales += s.n_out;
+    }
+  }
+
+  // Inter-layer shuffle: tensor order in the virtual page stream.
+  if (ident) {
+    L->sigma.resize(n_shapes);
+    for (int32_t i = 0; i < n_shapes; ++i) L->sigma[i] = i;
+  } else {
+    L->sigma = fisher_yates(n_shapes, substream(seed, kTagTensorOrder, 0));
+  }
+  // Intra-layer shuffle: hidden-neuron permutation of each FFN.
+  for (auto& f : L->ffn) {
+    if (ident) {
+      f.pi.resize(f.d_ffn);
+      for (int64_t i = 0; i < f.d_ffn; ++i) f.pi[i] = int32_t(i);
+    } else {
+      f.pi = fisher_yates(f.d_ffn, substream(seed, kTagHiddenPerm, uint32_t(f.layer)));
+    }
+    f.dev_off = L->n_perm;
+    L->n_perm += f.d_ffn;
+  }
+  // Virtual pages, tensors in sigma order.
+  int64_t cursor = 0;
+  for (int32_t i = 0; i < n_shapes; ++i) {
+    TensorInfo& ti = L->tensors[L->sigma[i]];
+    ti.vbase = cursor;
+    cursor += ti.npages;
+  }
+  L->V = cursor;
+  if (L->V > P) {
+    set_error("cloak_layout_build: tensors need %lld pages, pool has %lld", (long long)L->V, (long long)P);
+    delete L;
+    return CLOAK_ENOMEM;
+  }
+  // Physical placement over the whole pool.
+  if (ident) {
+    L->phi.resize(P);
+    for (int64_t p = 0; p < P; ++p) L->phi[p] = int32_t(p);
+  } else {
+    L->phi = fisher_yates(P, substream(seed, kTagPageMap, 0));
+  }
+  *out = L;
+  return CLOAK_OK;
+}
+
+extern "C" int cloak_query(const cloak_layout* L, int32_t what, int64_t index, void* out, uint64_t out_bytes) {
+  clear_error();
+  if (!L || !out) {
+    set_error("cloak_query: null argument");
+    return CLOAK_EINVAL;
+  }
+  auto need = [&](uint64_t n) {
+    if (out_bytes < n) {
+      set_error("cloak_query: buffer of %llu bytes, need %llu", (unsigned long long)out_bytes,
+                (unsigned long long)n);
+      return false;
+    }
+    return true;
+  };
+  const int64_t T = int64_t(L->tensors.size());
+  switch (what) {
+    case CLOAK_QUERY_P:
+    case CLOAK_QUERY_V:
+    case CLOAK_QUERY_T:
+    case CLOAK_QUERY_PAGE_BYTES:
+    case CLOAK_QUERY_REMAPS: {
+      if (!need(8)) return CLOAK_EINVAL;
+      int64_t v = what == CLOAK_QUERY_P ? L->P : what == CLOAK_QUERY_V ? L->V : what == CLOAK_QUERY_T ? T
+                : what == CLOAK_QUERY_PAGE_BYTES ? L->page_bytes : L->remaps;
+      std::memcpy(out, &v, 8);
+      return CLOAK_OK;
+    }
+    case CLOAK_QUERY_PHI:
+      if (!need(uint64_t(L->P) * 4)) return CLOAK_EINVAL;
+      std::memcpy(out, L->phi.data(), size_t(L->P) * 4);
+      return CLOAK_OK;
+    case CLOAK_QUERY_SIGMA:
+      if (!need(uint64_t(T) * 4)) return CLOAK_EINVAL;
+      std::memcpy(out, L->sigma.data(), size_t(T) * 4);
+      return CLOAK_OK;
+    case CLOAK_QUERY_PI: {
+      const FfnPerm* f = L->ffn_of_layer(int32_t(index));
+      if (!f) {
+        set_error("cloak_query: layer %lld has no FFN tensors", (long long)index);
+        return CLOAK_EINVAL;
+      }
+      if (!need(uint64_t(f->d_ffn) * 4)) return CLOAK_EINVAL;
+      std::memcpy(out, f->pi.data(), size_t(f->d_ffn) * 4);
+      return CLOAK_OK;
+    }
+    case CLOAK_QUERY_VBASE:
+    case CLOAK_QUERY_NPAGES: {
+      if (!need(uint64_t(T) * 8)) return CLOAK_EINVAL;
+      int64_t* o = static_cast<int64_t*>(out);
+      for (int64_t t = 0; t < T; ++t) o[t] = what == CLOAK_QUERY_VBASE ? L->tensors[t].vbase : L->tensors[t].npages;
+      return CLOAK_OK;
+    }
+    case CLOAK_QUERY_CONTIGUITY: {
+      if (!need(8)) return CLOAK_EINVAL;
+      double c = contiguity(L);
+      std::memcpy(out, &c, 8);
+      return CLOAK_OK;
+    }
+    case CLOAK_QUERY_UPLOAD_ORDER: {
+      if (index < 0 || index >= T) {
+        set_error("cloak_query: tensor %lld out of range", (long long)index);
+        return CLOAK_EINVAL;
+      }
+      auto ord = upload_order(L, int32_t(index));
+      if (!need(uint64_t(ord.size()) * 4)) return CLOAK_EINVAL;
+      std::memcpy(out, ord.data(), ord.size() * 4);
+      return CLOAK_OK;
+    }
+    case CLOAK_QUERY_DFFN: {
+      if (!need(8)) return CLOAK_EINVAL;
+      const FfnPerm* f = L->ffn_of_layer(int32_t(index));
+      int64_t v = f ? f->d_ffn : 0;
+      std::memcpy(out, &v, 8);
+      return CLOAK_OK;
+    }
+    case CLOAK_QUERY_TENSOR: {
+      if (!need(8)) return CLOAK_EINVAL;
+      int64_t v = L->find_tensor(int32_t(index >> 8), int32_t(index & 255));
+      std::memcpy(out, &v, 8);
+      return CLOAK_OK;
+    }
+    default:
+      set_error("cloak_query: unknown selector %d", what);
+      return CLOAK_EINVAL;
+  }
+}
+
+extern "C" int cloak_pack_host(const cloak_layout* L, int32_t tensor, const void* h_src, void* h_pool,
+                               uint64_t h_pool_bytes) {
+  clear_error();
+  if (!L || !h_src || !h_pool) {
+    set_error("cloak_pack_host: null argument");
+    return CLOAK_EINVAL;
+  }
+  if (tensor < 0 || tensor >= int32_t(L->tensors.size())) {
+    set_error("cloak_pack_host: tensor %d out of range", tensor);
+    return CLOAK_EINVAL;
+  }
+  if (h_pool_bytes < uint64_t(L->pool_bytes)) {
+    set_error("cloak_pack_host: pool image of %llu bytes, layout needs %lld", (unsigned long long)h_pool_bytes,
+              (long long)L->pool_bytes);
+    return CLOAK_EINVAL;
+  }
+  const TensorInfo& ti = L->tensors[tensor];
+  auto* pool = static_cast<uint8_t*>(h_pool);
+  for (int64_t i = 0; i < ti.npages; ++i) {
+    stream_page(L, tensor, static_cast<const uint8_t*>(h_src), i, pool + int64_t(L->phi[ti.vbase + i]) * L->page_bytes);
+  }
+  return CLOAK_OK;
+}
+
+extern "C" int cloak_remap_host(cloak_layout* L, void* h_pool, uint64_t h_pool_bytes, uint64_t remap_seed) {
+  clear_error();
+  if (!L || !h_pool) {
+    set_error("cloak_remap_host: null argument");
+    return CLOAK_EINVAL;
+  }
+  if (L->native()) {
+    set_error("cloak_remap_host: native (untranslated) layouts cannot be remapped");
+    return CLOAK_ESTATE;
+  }
+  if (h_pool_bytes < uint64_t(L->pool_bytes)) {
+    set_error("cloak_remap_host: pool image too small");
+    return CLOAK_EINVAL;
+  }
+  std::vector<int32_t> tau = remap_matching(remap_seed, L->P);
+  auto* pool = static_cast<uint8_t*>(h_pool);
+  std::vector<uint8_t> tmp(size_t(L->page_bytes));
+  for (int64_t p = 0; p < L->P; ++p) {
+    const int64_t q = tau[p];
+    if (q <= p) continue;  // each pair once
+    uint8_t* a = pool + p * L->page_bytes;
+    uint8_t* b = pool + q * L->page_bytes;
+    std::memcpy(tmp.data(), a, size_t(L->page_bytes));
+    std::memcpy(a, b, size_t(L->page_bytes));
+    std::memcpy(b, tmp.data(), size_t(L->page_bytes));
+  }
+  for (auto& v : L->phi) v = tau[v];
+  L->remaps += 1;
+  return CLOAK_OK;
+}

@@ -1,0 +1,178 @@
+"""The C-ABI library on the CPU: exports, layout and host images vs the oracle.
+
+No device is touched: these calls are host-only by contract (include/cloak.h).
+"""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import layout as OL
+from oracle import remap as OR
+from paper_2606_18400_amd import cloak as C
+from paper_2606_18400_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "cloak.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cloak_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = header_functions()
+    assert len(names) >= 15
+    lib = ctypes.CDLL(C.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(C.EXPORTED)
+
+
+def oracle_shapes(shapes):
+    return [OL.Shape(*s) for s in shapes]
+
+
+def small_model(dtype="bf16", layers=2, d=512, ffn=768, dkv=128, vocab=1000):
+    shapes = []
+    for l in range(layers):
+        shapes += synth.decoder_layer_shapes(d, ffn, dkv, dtype, layer=l)
+    shapes += [(-1, "embed", vocab, d, dtype), (-1, "head", vocab, d, dtype)]
+    return shapes
+
+
+def compare_layout(lay_c, lay_o):
+    assert C.cloak_query(lay_c, "P") == lay_o.P
+    assert C.cloak_query(lay_c, "V") == lay_o.V
+    assert list(C.cloak_query(lay_c, "SIGMA")) == lay_o.sigma
+    assert list(C.cloak_query(lay_c, "PHI")) == lay_o.phi
+    assert list(C.cloak_query(lay_c, "VBASE")) == lay_o.vbase
+    assert list(C.cloak_query(lay_c, "NPAGES")) == lay_o.npages
+    for l, pi in lay_o.pi.items():
+        assert list(C.cloak_query(lay_c, "PI", l)) == pi
+    for t in range(lay_o.T):
+        assert list(C.cloak_query(lay_c, "UPLOAD_ORDER", t)) == OL.upload_order(lay_o, t)
+    assert C.cloak_query(lay_c, "CONTIGUITY") == pytest.approx(OL.contiguity(lay_o), abs=0)
+
+
+@pytest.mark.parametrize("seed", [1, 0xC10A4, (1 << 64) - 1])
+@pytest.mark.parametrize("flags", [0, C.CLOAK_IDENTITY])
+def test_layout_matches_oracle(seed, flags):
+    shapes = small_model()
+    lay_c = C.cloak_layout_build(seed, shapes, 64 << 10, 64 << 20, flags)
+    try:
+        lay_o = OL.build_layout(seed, oracle_shapes(shapes), 64 << 10, 64 << 20, identity=bool(flags))
+        compare_layout(lay_c, lay_o)
+    finally:
+        C.cloak_layout_free(lay_c)
+
+
+def test_layout_matches_oracle_on_ffn512_block():
+    cfg = synth.FFN512
+    shapes = synth.ffn_block_shapes(cfg["d_model"], cfg["d_ffn"], cfg["dtype"])
+    for seed in (1, 2, 3):
+        lay_c = C.cloak_layout_build(seed, shapes, cfg["page_bytes"], cfg["pool_bytes"])
+        lay_o = OL.build_layout(seed, oracle_shapes(shapes), cfg["page_bytes"], cfg["pool_bytes"])
+        compare_layout(lay_c, lay_o)
+        assert lay_o.V == 96 and lay_o.P == 256
+        C.cloak_layout_free(lay_c)
+
+
+def test_layout_matches_oracle_on_layer4096_pool():
+    cfg = synth.LAYER4096
+    shapes = []
+    for copy in range(16):
+        shapes += synth.decoder_layer_shapes(cfg["d_model"], cfg["d_ffn"], cfg["d_kv"], "bf16", layer=copy)
+    lay_c = C.cloak_layout_build(1, shapes, cfg["page_bytes"], cfg["pool_bytes"])
+    lay_o = OL.build_layout(1, oracle_shapes(shapes), cfg["page_bytes"], cfg["pool_bytes"])
+    assert lay_o.V == 16 * 208 and lay_o.P == 4096
+    compare_layout(lay_c, lay_o)
+    C.cloak_layout_free(lay_c)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+@pytest.mark.parametrize("seed", [3, 4])
+def test_pack_host_matches_oracle_pool_bytes(dtype, seed):
+    # 1 KiB pages, rows that straddle pages (K*elt not a multiple of 1 KiB)
+    shapes = [(0, "q", 40, 264, dtype), (0, "gate", 72, 264, dtype), (0, "up", 72, 264, dtype),
+              (0, "down", 264, 72, dtype), (1, "gate", 48, 264, dtype), (1, "up", 48, 264, dtype),
+              (1, "down", 264, 48, dtype), (-1, "head", 50, 264, dtype)]
+    P, B = 512, 1024
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ws = [rng.integers(0, 256, (s[2], s[3] * {"f32": 4, "bf16": 2, "fp8": 1}[dtype]), dtype=np.uint8)
+          .view(C.STORAGE[dtype]) for s in shapes]
+    lay_c = C.cloak_layout_build(seed, shapes, B, P * B)
+    lay_o = OL.build_layout(seed, oracle_shapes(shapes), B, P * B)
+    img = np.zeros(P * B, np.uint8)
+    for t, w in enumerate(ws):
+        C.cloak_pack_host(lay_c, t, w, img)
+    want = OL.pack(lay_o, ws)
+    assert np.array_equal(img, want)
+    C.cloak_layout_free(lay_c)
+
+
+@pytest.mark.parametrize("remap_seed", [1, 2, 12345])
+def test_remap_host_matches_oracle(remap_seed):
+    shapes = small_model("bf16", layers=1, d=128, ffn=256, dkv=32, vocab=100)
+    P, B = 1025, 1024   # odd P: one page stays put
+    ws = [synth.weight(t, s[2], s[3], "bf16")[0] for t, s in enumerate(shapes)]
+    lay_c = C.cloak_layout_build(9, shapes, B, P * B)
+    lay_o = OL.build_layout(9, oracle_shapes(shapes), B, P * B)
+    img = np.zeros(P * B, np.uint8)
+    for t, w in enumerate(ws):
+        C.cloak_pack_host(lay_c, t, w, img)
+    pool_o = OL.pack(lay_o, ws)
+    C.cloak_remap_host(lay_c, img, remap_seed)
+    pool_o2, phi_o2 = OR.remap(pool_o, lay_o.phi, remap_seed, B)
+    assert list(C.cloak_query(lay_c, "PHI")) == phi_o2
+    assert np.array_equal(img, pool_o2)
+    assert C.cloak_query(lay_c, "REMAPS") == 1
+    C.cloak_layout_free(lay_c)
+
+
+def expect_error(code, fn, *args):
+    with pytest.raises(C.CloakError) as e:
+        fn(*args)
+    assert e.value.code == code
+    assert C.cloak_last_error()
+
+
+def test_error_codes_without_device():
+    good = [(0, "q", 8, 512, "bf16")]
+    expect_error(C.CLOAK_EINVAL, C.cloak_layout_build, 1, good, 3000, 3000 * 8)       # not a power of two
+    expect_error(C.CLOAK_EINVAL, C.cloak_layout_build, 1, good, 512, 512 * 8)         # below 1 KiB
+    expect_error(C.CLOAK_EINVAL, C.cloak_layout_build, 1, good, 1024, 1024 * 8 + 1)   # pool not whole pages
+    expect_error(C.CLOAK_ENOMEM, C.cloak_layout_build, 1, [(0, "q", 4096, 512, "bf16")], 1024, 1024 * 8)
+    expect_error(C.CLOAK_ESHAPE, C.cloak_layout_build, 1, good + good, 1024, 1024 * 64)
+    expect_error(C.CLOAK_ESHAPE, C.cloak_layout_build, 1,
+                 [(0, "gate", 64, 512, "bf16"), (0, "down", 512, 48, "bf16")], 1024, 1024 * 256)
+    expect_error(C.CLOAK_EINVAL, C.cloak_layout_build, 1, good, 1024, 1024 * 64, C.CLOAK_NATIVE)
+    expect_error(C.CLOAK_EINVAL, C.cloak_layout_build, 1, [(0, "q", 0, 512, "bf16")], 1024, 1024 * 64)
+    L = C.cloak_layout_build(1, good, 1024, 1024 * 64)
+    try:
+        # device calls before cloak_layout_to_device are refused before any launch
+        expect_error(C.CLOAK_ESTATE, C.cloak_linear, L, 256, 0, 256, 1, 256, None, 0, 0)
+        expect_error(C.CLOAK_ESTATE, C.cloak_remap, L, 256, 1, 0)
+        expect_error(C.CLOAK_EINVAL, C.cloak_query, L, 99, 0)
+        expect_error(C.CLOAK_EINVAL, C.cloak_query, L, "PI", 5)
+        img = np.zeros(10, np.uint8)
+        expect_error(C.CLOAK_EINVAL, C.cloak_pack_host, L, 0, np.zeros((8, 512), np.uint16), img)
+        expect_error(C.CLOAK_EINVAL, C.cloak_pack_host, L, 3, np.zeros((8, 512), np.uint16),
+                     np.zeros(1024 * 64, np.uint8))
+    finally:
+        C.cloak_layout_free(L)
+    N = C.cloak_layout_build(1, good, 1024, 1024 * 64, C.CLOAK_IDENTITY | C.CLOAK_NATIVE)
+    expect_error(C.CLOAK_ESTATE, C.cloak_remap_host, N, np.zeros(1024 * 64, np.uint8), 1)
+    C.cloak_layout_free(N)
+
+
+def test_identity_layout_is_contiguous():
+    shapes = small_model("f32", layers=1, d=256, ffn=512, dkv=64, vocab=300)
+    L = C.cloak_layout_build(5, shapes, 1024, 1024 * 4096, C.CLOAK_IDENTITY)
+    assert C.cloak_query(L, "CONTIGUITY") == 1.0
+    assert list(C.cloak_query(L, "SIGMA")) == list(range(len(shapes)))
+    C.cloak_layout_free(L)
