@@ -200,6 +200,19 @@ int cloak_linear_fused(const cloak_layout* layout, const void* d_pool, const int
 int cloak_mlp(const cloak_layout* layout, const void* d_pool, int32_t layer, const void* d_x,
               int64_t M, void* d_y, void* d_ws, uint64_t ws_bytes, void* stream);
 
+/* First half of cloak_mlp, one launch: h[M][d_ffn] = silu(x Wg^T) * (x Wu^T)
+ * with h left in the layer's PERMUTED hidden order (column j holds hidden
+ * unit pi[j]); each workgroup reads matching gate and up rows.  h is bf16
+ * (f32 for f32 weights). */
+int cloak_swiglu(const cloak_layout* layout, const void* d_pool, int32_t layer, const void* d_x,
+                 int64_t M, void* d_h, void* stream);
+
+/* Second half of cloak_mlp, one launch: y[M][d_model] = h . Wd^T for h in the
+ * permuted hidden order cloak_swiglu produces (down's stored columns carry
+ * the same permutation, so nothing is gathered). */
+int cloak_down(const cloak_layout* layout, const void* d_pool, int32_t layer, const void* d_h,
+               int64_t M, void* d_y, void* stream);
+
 /* Re-randomise page placement in place (Section 4.2, periodic remapping
  * with no extra memory footprint): draw the matching tau from remap_seed,
  * swap every page pair in the pool on `stream`, and set phi' = tau o phi on

@@ -15,6 +15,11 @@ import os
 
 import numpy as np
 
+# PyTorch ships its own HIP runtime (same SONAME as /opt/rocm's).  It must be
+# loaded before libcloak so that the library binds to that one runtime:
+# device pointers and streams handed over from torch are only valid there.
+import torch  # noqa: F401,E402
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcloak.so")
 if not os.path.exists(LIB_PATH):
@@ -61,6 +66,8 @@ _SIGS = {
     "cloak_linear": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _u64, _vp], _i32),
     "cloak_linear_fused": ([_vp, _vp, ctypes.POINTER(_i32), _i32, _vp, _i64, _vp, _vp, _u64, _vp], _i32),
     "cloak_mlp": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _u64, _vp], _i32),
+    "cloak_swiglu": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp], _i32),
+    "cloak_down": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp], _i32),
     "cloak_remap": ([_vp, _vp, _u64, _vp], _i32),
     "cloak_remap_host": ([_vp, _vp, _u64, _u64], _i32),
     "cloak_last_error": ([], ctypes.c_char_p),
@@ -198,6 +205,14 @@ def cloak_linear_fused(layout, pool, tensors, x, M, y, ws=None, ws_bytes=0, stre
 def cloak_mlp(layout, pool, layer, x, M, y, ws, ws_bytes, stream=None):
     _check(_lib.cloak_mlp(layout, _ptr(pool), layer, _ptr(x), M, _ptr(y), _ptr(ws), ws_bytes, _stream(stream)),
            "cloak_mlp")
+
+
+def cloak_swiglu(layout, pool, layer, x, M, h, stream=None):
+    _check(_lib.cloak_swiglu(layout, _ptr(pool), layer, _ptr(x), M, _ptr(h), _stream(stream)), "cloak_swiglu")
+
+
+def cloak_down(layout, pool, layer, h, M, y, stream=None):
+    _check(_lib.cloak_down(layout, _ptr(pool), layer, _ptr(h), M, _ptr(y), _stream(stream)), "cloak_down")
 
 
 def cloak_remap(layout, pool, remap_seed, stream=None):

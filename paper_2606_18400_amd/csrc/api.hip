@@ -367,18 +367,20 @@ extern "C" int cloak_linear(const cloak_layout* L, const void* d_pool, int32_t t
   return cloak_linear_fused(L, d_pool, &tensor, 1, d_x, M, d_y, d_ws, ws_bytes, stream);
 }
 
-extern "C" int cloak_mlp(const cloak_layout* L, const void* d_pool, int32_t layer, const void* d_x, int64_t M,
-                         void* d_y, void* d_ws, uint64_t ws_bytes, void* stream) {
-  clear_error();
-  if (int rc = check_device_state(L, "cloak_mlp")) return rc;
-  if (int rc = check_pool(L, d_pool, "cloak_mlp")) return rc;
+namespace {
+
+// Shared checks of the FFN entry points; fills the three tensors.
+int ffn_tensors(const cloak_layout* L, const void* d_pool, int32_t layer, int64_t M, const char* fn,
+                const FfnPerm** out) {
+  if (int rc = check_device_state(L, fn)) return rc;
+  if (int rc = check_pool(L, d_pool, fn)) return rc;
   const FfnPerm* f = L->ffn_of_layer(layer);
   if (!f || f->gate < 0 || f->up < 0 || f->down < 0) {
-    set_error("cloak_mlp: layer %d lacks gate, up or down", layer);
+    set_error("%s: layer %d lacks gate, up or down", fn, layer);
     return CLOAK_EINVAL;
   }
   if (M < 0 || M > INT32_MAX) {
-    set_error("cloak_mlp: bad M");
+    set_error("%s: bad M", fn);
     return CLOAK_EINVAL;
   }
   const TensorInfo& tg = L->tensors[f->gate];
@@ -387,23 +389,37 @@ extern "C" int cloak_mlp(const cloak_layout* L, const void* d_pool, int32_t laye
   const int32_t dtype = tg.shape.dtype;
   if (tu.shape.dtype != dtype || td.shape.dtype != dtype || tu.shape.k_in != tg.shape.k_in ||
       td.shape.n_out != tg.shape.k_in) {
-    set_error("cloak_mlp: gate/up/down dtypes or d_model disagree");
+    set_error("%s: gate/up/down dtypes or d_model disagree", fn);
     return CLOAK_ESHAPE;
   }
   const int elt = elt_bytes(dtype);
   const int64_t dm = tg.shape.k_in, dff = f->d_ffn;
-  if ((dm * elt) % 16 != 0 || (dff * elt) % 16 != 0 || (dff * elt + 1023) / 1024 > 64 || (dm * elt + 1023) / 1024 > 64) {
-    set_error("cloak_mlp: rows must be multiples of 16 bytes and at most 64 KiB");
+  if ((dm * elt) % 16 != 0 || (dff * elt) % 16 != 0 || (dff * elt + 1023) / 1024 > 64 ||
+      (dm * elt + 1023) / 1024 > 64) {
+    set_error("%s: rows must be multiples of 16 bytes and at most 64 KiB", fn);
     return CLOAK_ESHAPE;
   }
+  *out = f;
+  return CLOAK_OK;
+}
+
+}  // namespace
+
+extern "C" int cloak_swiglu(const cloak_layout* L, const void* d_pool, int32_t layer, const void* d_x, int64_t M,
+                            void* d_h, void* stream) {
+  clear_error();
+  const FfnPerm* f = nullptr;
+  if (int rc = ffn_tensors(L, d_pool, layer, M, "cloak_swiglu", &f)) return rc;
   if (M == 0) return CLOAK_OK;
-  const uint64_t need = cloak_ws_bytes(L, CLOAK_OP_MLP, layer, M);
-  if (!d_x || !d_y || !d_ws || ws_bytes < need) {
-    set_error("cloak_mlp: null x/y/workspace or workspace below %llu bytes", (unsigned long long)need);
+  if (!d_x || !d_h) {
+    set_error("cloak_swiglu: null x or h");
     return CLOAK_EINVAL;
   }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  // gate + up, paired rows, SwiGLU epilogue -> h in permuted order
+  const TensorInfo& tg = L->tensors[f->gate];
+  const int32_t dtype = tg.shape.dtype;
+  const int elt = elt_bytes(dtype);
+  const int64_t dm = tg.shape.k_in, dff = f->d_ffn;
+  // gate + up row pairs in one launch, SwiGLU epilogue -> h in permuted order
   GemvArgs a{};
   fill_common(L, d_pool, a, dm, elt);
   a.nseg = 2;
@@ -414,25 +430,56 @@ extern "C" int cloak_mlp(const cloak_layout* L, const void* d_pool, int32_t laye
   a.groups = int32_t((dff + 3) / 4);
   a.x = d_x;
   a.x_perm = nullptr;
-  a.y = d_ws;
+  a.y = d_h;
   a.ldx = dm;
   a.ldy = dff;
   a.mode = kSwiGLU;
-  if (int rc = run_gemv(L, a, wtype_of(dtype), M, st, "cloak_mlp(gate/up)")) return rc;
-  // down: its columns are permuted exactly like h, so no gather is needed
+  return run_gemv(L, a, wtype_of(dtype), M, static_cast<hipStream_t>(stream), "cloak_swiglu");
+}
+
+extern "C" int cloak_down(const cloak_layout* L, const void* d_pool, int32_t layer, const void* d_h, int64_t M,
+                          void* d_y, void* stream) {
+  clear_error();
+  const FfnPerm* f = nullptr;
+  if (int rc = ffn_tensors(L, d_pool, layer, M, "cloak_down", &f)) return rc;
+  if (M == 0) return CLOAK_OK;
+  if (!d_h || !d_y) {
+    set_error("cloak_down: null h or y");
+    return CLOAK_EINVAL;
+  }
+  const TensorInfo& tg = L->tensors[f->gate];
+  const int32_t dtype = tg.shape.dtype;
+  const int elt = elt_bytes(dtype);
+  const int64_t dm = tg.shape.k_in, dff = f->d_ffn;
+  // down's stored columns are permuted exactly like h: no gather needed
   GemvArgs b{};
   fill_common(L, d_pool, b, dff, elt);
   b.nseg = 1;
   b.seg[0] = make_seg(L, f->down, false, 0, 0);
   for (int i = 1; i < 4; ++i) b.seg[i] = b.seg[0], b.seg[i].row0 = INT32_MAX;
   b.groups = int32_t((dm + 7) / 8);
-  b.x = d_ws;
+  b.x = d_h;
   b.x_perm = nullptr;
   b.y = d_y;
   b.ldx = dff;
   b.ldy = dm;
   b.mode = kStore;
-  return run_gemv(L, b, wtype_of(dtype), M, st, "cloak_mlp(down)");
+  return run_gemv(L, b, wtype_of(dtype), M, static_cast<hipStream_t>(stream), "cloak_down");
+}
+
+extern "C" int cloak_mlp(const cloak_layout* L, const void* d_pool, int32_t layer, const void* d_x, int64_t M,
+                         void* d_y, void* d_ws, uint64_t ws_bytes, void* stream) {
+  clear_error();
+  const FfnPerm* f = nullptr;
+  if (int rc = ffn_tensors(L, d_pool, layer, M, "cloak_mlp", &f)) return rc;
+  if (M == 0) return CLOAK_OK;
+  const uint64_t need = cloak_ws_bytes(L, CLOAK_OP_MLP, layer, M);
+  if (!d_x || !d_y || !d_ws || ws_bytes < need) {
+    set_error("cloak_mlp: null x/y/workspace or workspace below %llu bytes", (unsigned long long)need);
+    return CLOAK_EINVAL;
+  }
+  if (int rc = cloak_swiglu(L, d_pool, layer, d_x, M, d_ws, stream)) return rc;
+  return cloak_down(L, d_pool, layer, d_ws, M, d_y, stream);
 }
 
 extern "C" int cloak_remap(cloak_layout* L, void* d_pool, uint64_t remap_seed, void* stream) {

@@ -78,9 +78,9 @@ __device__ inline SegView seg_view(const GemvArgs& a, int s) {
 }
 
 // Row r of group g -> (segment, stored row n).  Returns false past the end.
-template <int R>
+template <int R, int EPI>
 __device__ inline bool resolve_row(const GemvArgs& a, int g, int r, int& s, int& n) {
-  if (a.mode == kSwiGLU) {
+  if (EPI == kSwiGLU) {
     s = r < R / 2 ? 0 : 1;
     n = g * (R / 2) + (r % (R / 2));
     return n < a.seg[0].rows;
@@ -202,7 +202,7 @@ __device__ inline void lane_reduce(float (&v)[V], int lane) {
 template <int N> struct Log2 { static constexpr int value = 1 + Log2<N / 2>::value; };
 template <> struct Log2<1> { static constexpr int value = 0; };
 
-template <int WT, int MT, int R, int CPW, bool TR>
+template <int WT, int MT, int R, int CPW, bool TR, int EPI>
 __global__ __launch_bounds__(512) void gemv_kernel(const GemvArgs a) {
   constexpr int XW = WTraits<WT>::XW;
   constexpr int EPL = WTraits<WT>::EPL;
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(512) void gemv_kernel(const GemvArgs a) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         int s, n;
-        const bool ok = resolve_row<R>(a, g, r, s, n);
+        const bool ok = resolve_row<R, EPI>(a, g, r, s, n);
         if (ok && c < a.nchunks) {
           w[r] = load_w<TR>(a, seg_view(a, s), n, c, lane, lane_ok);
         } else {
@@ -262,13 +262,13 @@ __global__ __launch_bounds__(512) void gemv_kernel(const GemvArgs a) {
     __syncthreads();
 
     const int t = threadIdx.x;
-    if (a.mode == kStore) {
+    if constexpr (EPI == kStore) {
       if (t < V) {
         float sum = 0.f;
         for (int ww = 0; ww < nwaves; ++ww) sum += red[buf][ww][t];
         const int r = t / MT, m = t % MT;
         int s, n;
-        if (resolve_row<R>(a, g, r, s, n) && m < a.mcount) {
+        if (resolve_row<R, EPI>(a, g, r, s, n) && m < a.mcount) {
           const SegView sv = seg_view(a, s);
           if (sv.scale) sum *= sv.scale[n];
           const int col = sv.out_off + (sv.out_perm ? sv.out_perm[n] : n);
@@ -314,30 +314,40 @@ int max_mtile(int wt, int cpw) {
   return cpw <= 2 ? 8 : cpw == 4 ? 4 : 2;
 }
 
-template <int WT, int CPW, bool TR>
+template <int WT, int CPW, bool TR, int EPI>
 KernelFn pick_mt(int mt) {
   constexpr int kMax = WT == kFP8 ? (CPW <= 1 ? 8 : CPW == 2 ? 4 : CPW == 4 ? 2 : 1)
                                   : (CPW <= 2 ? 8 : CPW == 4 ? 4 : 2);
-  if (mt <= 1) return gemv_kernel<WT, 1, 8, CPW, TR>;
-  if (mt <= 2 || kMax == 2) return gemv_kernel<WT, (kMax < 2 ? 1 : 2), 8, CPW, TR>;
-  if (mt <= 4 || kMax == 4) return gemv_kernel<WT, (kMax < 4 ? 1 : 4), 8, CPW, TR>;
-  return gemv_kernel<WT, (kMax < 8 ? 1 : 8), 8, CPW, TR>;
+  if (mt <= 1) return gemv_kernel<WT, 1, 8, CPW, TR, EPI>;
+  if (mt <= 2 || kMax == 2) return gemv_kernel<WT, (kMax < 2 ? 1 : 2), 8, CPW, TR, EPI>;
+  if (mt <= 4 || kMax == 4) return gemv_kernel<WT, (kMax < 4 ? 1 : 4), 8, CPW, TR, EPI>;
+  return gemv_kernel<WT, (kMax < 8 ? 1 : 8), 8, CPW, TR, EPI>;
 }
 
-template <int WT, bool TR>
+template <int WT, bool TR, int EPI>
 KernelFn pick_cpw(int cpw, int mt) {
   switch (cpw) {
-    case 1: return pick_mt<WT, 1, TR>(mt);
-    case 2: return pick_mt<WT, 2, TR>(mt);
-    case 4: return pick_mt<WT, 4, TR>(mt);
-    default: return pick_mt<WT, 8, TR>(mt);
+    case 1: return pick_mt<WT, 1, TR, EPI>(mt);
+    case 2: return pick_mt<WT, 2, TR, EPI>(mt);
+    case 4: return pick_mt<WT, 4, TR, EPI>(mt);
+    default: return pick_mt<WT, 8, TR, EPI>(mt);
   }
 }
 
-KernelFn pick(int wt, bool tr, int cpw, int mt) {
-  if (wt == kF32) return tr ? pick_cpw<kF32, true>(cpw, mt) : pick_cpw<kF32, false>(cpw, mt);
-  if (wt == kBF16) return tr ? pick_cpw<kBF16, true>(cpw, mt) : pick_cpw<kBF16, false>(cpw, mt);
-  return tr ? pick_cpw<kFP8, true>(cpw, mt) : pick_cpw<kFP8, false>(cpw, mt);
+template <int WT, int EPI>
+KernelFn pick_tr(bool tr, int cpw, int mt) {
+  return tr ? pick_cpw<WT, true, EPI>(cpw, mt) : pick_cpw<WT, false, EPI>(cpw, mt);
+}
+
+KernelFn pick(int wt, bool tr, int cpw, int mt, int epi) {
+  if (epi == kSwiGLU) {
+    if (wt == kF32) return pick_tr<kF32, kSwiGLU>(tr, cpw, mt);
+    if (wt == kBF16) return pick_tr<kBF16, kSwiGLU>(tr, cpw, mt);
+    return pick_tr<kFP8, kSwiGLU>(tr, cpw, mt);
+  }
+  if (wt == kF32) return pick_tr<kF32, kStore>(tr, cpw, mt);
+  if (wt == kBF16) return pick_tr<kBF16, kStore>(tr, cpw, mt);
+  return pick_tr<kFP8, kStore>(tr, cpw, mt);
 }
 
 int resident_blocks(KernelFn fn, int threads) {
@@ -374,7 +384,7 @@ hipError_t launch_gemv(const GemvArgs& a, int wtype, int mtile, bool translate, 
   if (cpw > 8 || mtile > max_mtile(wtype, cpw) || a.mcount > mtile) return hipErrorInvalidValue;
   const int waves = (a.nchunks + cpw - 1) / cpw;
   const int threads = waves * 64;
-  KernelFn fn = pick(wtype, translate, cpw, mtile);
+  KernelFn fn = pick(wtype, translate, cpw, mtile, a.mode);
   int blocks = resident_blocks(fn, threads);
   if (blocks <= 0) blocks = a.groups;
   if (blocks > a.groups) blocks = a.groups;

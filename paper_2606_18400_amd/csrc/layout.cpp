@@ -98,6 +98,19 @@ double contiguity(const cloak_layout* L) {
   return total ? double(hits) / double(total) : 1.0;
 }
 
+// d[e - e0] = srow[pi[e]] for e in [e0, e1), elements of `elt` bytes.
+static void gather_elements(uint8_t* d, const uint8_t* srow, const int32_t* pi, int64_t e0, int64_t e1, int elt) {
+  if (elt == 2) {
+    auto* dd = reinterpret_cast<uint16_t*>(d);
+    for (int64_t e = e0; e < e1; ++e) std::memcpy(dd + (e - e0), srow + int64_t(pi[e]) * 2, 2);
+  } else if (elt == 4) {
+    auto* dd = reinterpret_cast<uint32_t*>(d);
+    for (int64_t e = e0; e < e1; ++e) std::memcpy(dd + (e - e0), srow + int64_t(pi[e]) * 4, 4);
+  } else {
+    for (int64_t e = e0; e < e1; ++e) d[e - e0] = srow[pi[e]];
+  }
+}
+
 // Bytes [page*B, page*B + B) of tensor t's shuffled stream, built from the
 // logical array `src`; bytes past the tensor are zero.
 void stream_page(const cloak_layout* L, int32_t t, const uint8_t* src, int64_t page, uint8_t* dst) {
@@ -109,7 +122,7 @@ void stream_page(const cloak_layout* L, int32_t t, const uint8_t* src, int64_t p
   if (begin >= end) return;
   const int64_t rb = ti.row_bytes;
   const int elt = elt_bytes(ti.shape.dtype);
-  const int32_t* pi = ti.perm_layer >= 0 ? L->ffn[ti.perm_layer].pi.data() : nullptr;
+  const int32_t* pi = (ti.perm_layer >= 0 && !L->identity()) ? L->ffn[ti.perm_layer].pi.data() : nullptr;
   const int kind = ti.shape.kind;
   int64_t o = begin;
   while (o < end) {
@@ -123,9 +136,7 @@ void stream_page(const cloak_layout* L, int32_t t, const uint8_t* src, int64_t p
       const uint8_t* srow = src + row * rb;
       uint8_t* d = dst + (o - begin);
       const int64_t e0 = col / elt, e1 = (col + seg) / elt;
-      for (int64_t e = e0; e < e1; ++e) {
-        std::memcpy(d + (e - e0) * elt, srow + int64_t(pi[e]) * elt, size_t(elt));
-      }
+      gather_elements(d, srow, pi, e0, e1, elt);
     } else {
       std::memcpy(dst + (o - begin), src + o, size_t(seg));
     }
@@ -143,7 +154,7 @@ void unstream_page(const cloak_layout* L, int32_t t, const uint8_t* pagebuf, int
   if (begin >= end) return;
   const int64_t rb = ti.row_bytes;
   const int elt = elt_bytes(ti.shape.dtype);
-  const int32_t* pi = ti.perm_layer >= 0 ? L->ffn[ti.perm_layer].pi.data() : nullptr;
+  const int32_t* pi = (ti.perm_layer >= 0 && !L->identity()) ? L->ffn[ti.perm_layer].pi.data() : nullptr;
   const int kind = ti.shape.kind;
   int64_t o = begin;
   while (o < end) {

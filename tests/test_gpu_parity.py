@@ -1,0 +1,267 @@
+"""GPU parity of the cloaked path against the CPU oracle (MI355X, via the C-ABI).
+
+Bit-exact: pool bytes after upload, read-back, remap, one-hot probes through
+the GEMV and the cloaked-vs-native comparison of tensors whose K is not
+permuted.  Normwise tolerance against FP64 (max|y-y*| / max|y*|): 1e-5 for
+f32, 1e-2 for bf16, 5e-2 for FP8.
+"""
+
+import numpy as np
+import pytest
+
+from cloak_cases import (TOL, act_dtype, decoder_shapes, from_device, make_weights, oracle_layout, to_device_x,
+                         values_f64, w64)
+from oracle import layout as OL
+from oracle import numerics as ON
+from oracle import remap as OR
+from paper_2606_18400_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def C():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2606_18400_amd import cloak
+    return cloak
+
+
+def pool_bytes_of(cw):
+    return cw.pool.cpu().numpy()
+
+
+# rows of 272 elements (544 B bf16, 1088 B f32, 272 B fp8) and hidden sizes 80/48:
+# no row is a multiple of 1 KiB, so 1 KiB wave loads cross page boundaries
+RAGGED = [(0, "q", 40, 272, None), (0, "gate", 80, 272, None), (0, "up", 80, 272, None),
+          (0, "down", 272, 80, None), (1, "gate", 48, 272, None), (1, "up", 48, 272, None),
+          (1, "down", 272, 48, None), (-1, "head", 50, 272, None)]
+
+
+def ragged_shapes(dtype):
+    return [(l, k, n, kk, dtype) for (l, k, n, kk, _) in RAGGED]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+@pytest.mark.parametrize("page_bytes", [1024, 65536])
+def test_upload_pool_bytes_and_readback_bit_exact(C, dtype, page_bytes):
+    shapes = ragged_shapes(dtype) + decoder_shapes(512, 1024, 128, dtype, layers=1)[:0]
+    pool = page_bytes * (512 if page_bytes == 1024 else 16)
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, page_bytes, pool, seed=7)
+    cw.load(ws, scs)
+    lay = oracle_layout(7, shapes, page_bytes, pool)
+    assert np.array_equal(pool_bytes_of(cw), OL.pack(lay, ws))
+    for t, w in enumerate(ws):
+        back = np.zeros_like(w)
+        C.cloak_unload(cw.layout, cw.pool, t, back)
+        assert np.array_equal(back.view(np.uint8), w.view(np.uint8))
+    cw.close()
+
+
+def test_remap_on_device_matches_oracle_and_keeps_results(C):
+    import torch
+    shapes = decoder_shapes(512, 1024, 128, "bf16", layers=2)
+    B, P = 65536, 257   # odd pool: one page keeps its place in every remap
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, B, B * P, seed=3)
+    cw.load(ws, scs)
+    lay = oracle_layout(3, shapes, B, B * P)
+    pool, phi = OL.pack(lay, ws), lay.phi
+    x = to_device_x(synth.activations(5, 512, "bf16"))
+    before = [cw.linear(t, x).clone() for t in range(len(shapes)) if shapes[t][3] == 512]
+    mlp_before = cw.mlp(0, x).clone()
+    for rs in (1, 2, 99):
+        cw.remap(rs)
+        pool, phi = OR.remap(pool, phi, rs, B)
+    torch.cuda.synchronize()
+    assert list(C.cloak_query(cw.layout, "PHI")) == phi
+    assert np.array_equal(pool_bytes_of(cw), pool)
+    after = [cw.linear(t, x) for t in range(len(shapes)) if shapes[t][3] == 512]
+    for a, b in zip(before, after):
+        assert torch.equal(a.view(torch.int16), b.view(torch.int16))
+    assert torch.equal(mlp_before.view(torch.int16), cw.mlp(0, x).view(torch.int16))
+    cw.close()
+
+
+def check_linear_all(C, cw, shapes, ws, scs, M, xseed=5678):
+    """Every tensor through cloak_linear and every FFN through cloak_mlp."""
+    dtypes = {s[4] for s in shapes}
+    worst = 0.0
+    for t, s in enumerate(shapes):
+        adt = act_dtype(s[4])
+        x_np = synth.activations(M, s[3], adt, seed=xseed + t)
+        y = from_device(cw.linear(t, to_device_x(x_np)))
+        ref = ON.linear(values_f64(x_np), w64(shapes, ws, scs, t))
+        err = ON.normwise_err(values_f64(y), ref)
+        worst = max(worst, err)
+        assert err <= TOL[s[4]], (t, s, M, err)
+    layers = sorted({s[0] for s in shapes if s[1] == "gate"})
+    for l in layers:
+        ig = next(t for t, s in enumerate(shapes) if s[0] == l and s[1] == "gate")
+        iu = next(t for t, s in enumerate(shapes) if s[0] == l and s[1] == "up")
+        idn = next(t for t, s in enumerate(shapes) if s[0] == l and s[1] == "down")
+        wdt = shapes[ig][4]
+        x_np = synth.activations(M, shapes[ig][3], act_dtype(wdt), seed=xseed + 100 + l)
+        y = from_device(cw.mlp(l, to_device_x(x_np)))
+        ref, _ = ON.swiglu_ffn(values_f64(x_np), w64(shapes, ws, scs, ig), w64(shapes, ws, scs, iu),
+                               w64(shapes, ws, scs, idn))
+        err = ON.normwise_err(values_f64(y), ref)
+        worst = max(worst, err)
+        assert err <= TOL[wdt], ("mlp", l, M, err)
+    return worst, dtypes
+
+
+@pytest.mark.parametrize("M", [1, 4])
+def test_ffn512_block_f32_vs_fp64(C, M):
+    cfg = synth.FFN512
+    shapes = synth.ffn_block_shapes(cfg["d_model"], cfg["d_ffn"], "f32")
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, cfg["page_bytes"], cfg["pool_bytes"], seed=1)
+    cw.load(ws, scs)
+    check_linear_all(C, cw, shapes, ws, scs, M)
+    cw.close()
+
+
+@pytest.mark.parametrize("M", [1, 2, 3, 5, 8, 13])
+def test_bf16_layer_vs_fp64(C, M):
+    shapes = decoder_shapes(1024, 2816, 256, "bf16", layers=1, extra=[(-1, "head", 1000, 1024, "bf16")])
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, 65536, 65536 * 512, seed=11)
+    cw.load(ws, scs)
+    check_linear_all(C, cw, shapes, ws, scs, M)
+    cw.close()
+
+
+@pytest.mark.parametrize("M", [1, 3, 8])
+@pytest.mark.parametrize("dtype", ["bf16", "fp8", "f32"])
+def test_ragged_rows_straddling_pages(C, M, dtype):
+    shapes = ragged_shapes(dtype)
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, 1024, 1024 * 512, seed=5)
+    cw.load(ws, scs)
+    check_linear_all(C, cw, shapes, ws, scs, M)
+    cw.close()
+
+
+@pytest.mark.parametrize("M", [1, 2, 4, 8])
+def test_fp8_layer_vs_fp64(C, M):
+    shapes = decoder_shapes(1280, 3456, 256, "fp8", layers=1, extra=[(-1, "head", 700, 1280, "bf16")])
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, 65536, 65536 * 512, seed=13)
+    cw.load(ws, scs)
+    check_linear_all(C, cw, shapes, ws, scs, M)
+    cw.close()
+
+
+def one_hot_expected(shapes, ws, scs, t, ks):
+    """y[m][n] for x = e_{ks[m]}: the weight itself, rounded like the kernel's output."""
+    s = shapes[t]
+    if s[4] == "f32":
+        return np.stack([ws[t][:, k] for k in ks])
+    if s[4] == "bf16":
+        return np.stack([ws[t][:, k] for k in ks])
+    # FP8: acc = e4m3(q) exactly, times the f32 row scale (one f32 rounding), then bf16
+    q = ON.e4m3_bits_to_f64(ws[t]).astype(np.float32)
+    prod = q * scs[t].astype(np.float32)[:, None]
+    return np.stack([ON.f32_to_bf16_bits_rne(prod[:, k]) for k in ks])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+def test_one_hot_probes_are_bit_exact(C, dtype):
+    shapes = ragged_shapes(dtype) + [(2, "gate", 64, 512, dtype), (2, "up", 64, 512, dtype),
+                                     (2, "down", 512, 64, dtype)]
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, 1024, 1024 * 1024, seed=21)
+    cw.load(ws, scs)
+    rng = np.random.Generator(np.random.PCG64(4))
+    for t, s in enumerate(shapes):
+        K = s[3]
+        ks = list(rng.choice(K, size=min(8, K), replace=False))
+        ks[0], ks[-1] = 0, K - 1
+        if dtype == "f32":
+            x = np.zeros((len(ks), K), np.float32)
+            for m, k in enumerate(ks):
+                x[m, k] = 1.0
+        else:
+            x = np.zeros((len(ks), K), np.uint16)
+            for m, k in enumerate(ks):
+                x[m, k] = 0x3F80
+        y = from_device(cw.linear(t, to_device_x(x)))
+        want = one_hot_expected(shapes, ws, scs, t, ks)
+        assert np.array_equal(y.view(np.uint8), want.view(np.uint8)), (t, s)
+    cw.close()
+
+
+def test_cloaked_equals_native_twin(C):
+    import torch
+    shapes = decoder_shapes(1024, 2816, 256, "bf16", layers=2)
+    ws, scs = make_weights(shapes)
+    B, P = 65536, 1024
+    cl = C.CloakedWeights(shapes, B, B * P, seed=31)
+    nat = C.CloakedWeights(shapes, B, B * P, seed=31, flags=C.CLOAK_IDENTITY | C.CLOAK_NATIVE)
+    idt = C.CloakedWeights(shapes, B, B * P, seed=31, flags=C.CLOAK_IDENTITY)
+    for cw in (cl, nat, idt):
+        cw.load(ws, scs)
+    assert C.cloak_query(nat.layout, "CONTIGUITY") == 1.0
+    assert C.cloak_query(cl.layout, "CONTIGUITY") < 0.05
+    for M in (1, 8):
+        for t, s in enumerate(shapes):
+            x = to_device_x(synth.activations(M, s[3], "bf16", seed=t))
+            a, b, c = cl.linear(t, x), nat.linear(t, x), idt.linear(t, x)
+            assert torch.equal(b.view(torch.int16), c.view(torch.int16))
+            if s[1] == "down":
+                err = ON.normwise_err(values_f64(from_device(a)), values_f64(from_device(b)))
+                assert err <= 1e-2
+            else:
+                assert torch.equal(a.view(torch.int16), b.view(torch.int16)), s
+        x = to_device_x(synth.activations(M, 1024, "bf16", seed=77))
+        err = ON.normwise_err(values_f64(from_device(cl.mlp(1, x))), values_f64(from_device(nat.mlp(1, x))))
+        assert err <= 1e-2
+    for cw in (cl, nat, idt):
+        cw.close()
+
+
+def test_fused_qkv_equals_separate(C):
+    import torch
+    shapes = decoder_shapes(1024, 2816, 256, "bf16", layers=1)
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, 65536, 65536 * 512, seed=2)
+    cw.load(ws, scs)
+    x = to_device_x(synth.activations(3, 1024, "bf16"))
+    fused = cw.linear_fused([0, 1, 2], x)
+    sep = torch.cat([cw.linear(t, x) for t in (0, 1, 2)], dim=1)
+    assert torch.equal(fused.view(torch.int16), sep.view(torch.int16))
+    # gate and up fused: the scatter through pi applies per tensor
+    gu = cw.linear_fused([4, 5], x)
+    assert torch.equal(gu.view(torch.int16), torch.cat([cw.linear(4, x), cw.linear(5, x)], 1).view(torch.int16))
+    cw.close()
+
+
+def test_empty_batch_and_argument_errors(C):
+    import torch
+    shapes = decoder_shapes(512, 1024, 128, "bf16", layers=1)
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, 65536, 65536 * 128, seed=4)
+    cw.load(ws, scs)
+    y = torch.full((1, 512), 7, dtype=torch.int16, device="cuda")
+    C.cloak_linear(cw.layout, cw.pool, 0, y, 0, y)     # M = 0: nothing written
+    torch.cuda.synchronize()
+    assert int(y.min()) == 7 and int(y.max()) == 7
+    x = to_device_x(synth.activations(2, 512, "bf16"))
+    out = torch.empty((2, 512), dtype=torch.bfloat16, device="cuda")
+    with pytest.raises(C.CloakError) as e:
+        C.cloak_mlp(cw.layout, cw.pool, 0, x, 2, out, out, 16)   # workspace too small
+    assert e.value.code == C.CLOAK_EINVAL
+    with pytest.raises(C.CloakError) as e:
+        C.cloak_linear_fused(cw.layout, cw.pool, [0, 6], x, 2, out)   # K differs
+    assert e.value.code == C.CLOAK_ESHAPE
+    with pytest.raises(C.CloakError) as e:
+        C.cloak_linear(cw.layout, cw.pool.data_ptr() + 16, 0, x, 2, out)   # misaligned pool
+    assert e.value.code == C.CLOAK_EINVAL
+    cw.close()
+    nat = C.CloakedWeights(shapes, 65536, 65536 * 128, seed=4, flags=C.CLOAK_IDENTITY | C.CLOAK_NATIVE)
+    with pytest.raises(C.CloakError) as e:
+        nat.remap(1)
+    assert e.value.code == C.CLOAK_ESTATE
+    nat.close()
