@@ -142,6 +142,25 @@ def time_remap(var, reps):
                 frac_of_peak=traffic / ms / 1e6 / HBM_PEAK_GBS)
 
 
+def copy_calibration(nbytes=1 << 30):
+    """A plain elementwise copy of known size (reads and writes nbytes once);
+    hardware byte counters of the decode kernels are scaled by what they read
+    for this kernel."""
+    import torch
+    src = torch.ones(nbytes // 2, dtype=torch.bfloat16, device="cuda")
+    dst = torch.empty_like(src)
+    torch.mul(src, 1, out=dst)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    torch.mul(src, 1, out=dst)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    del src, dst
+    return dict(bytes_read=nbytes, bytes_written=nbytes, ms=ms, gbs=2 * nbytes / ms / 1e6)
+
+
 def cpu_oracle_baseline(cfg, weights, budget_s=12.0):
     """The oracle's FP64 decode step (decode stored weights, then the products)."""
     from oracle import numerics as ON
@@ -221,6 +240,7 @@ def main():
                               ms=m_cl, native_ms=m_nat)
         log(f"M={M} cloaked {b / m_cl / 1e6:.0f} GB/s native {b / m_nat / 1e6:.0f} GB/s")
 
+    calib = copy_calibration()
     log("timing remap of the whole pool")
     remap = time_remap(cl, args.remap_reps)
     log(f"remap {remap['gbs']:.0f} GB/s vs device copy {remap['memcpy_gbs']:.0f} GB/s")
@@ -246,6 +266,7 @@ def main():
         "decode": decode,
         "prefill": None,
         "remap": remap,
+        "copy_calibration": calib,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "contiguity": C.cloak_query(cl.cw.layout, "CONTIGUITY"),

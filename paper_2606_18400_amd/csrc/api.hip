@@ -346,13 +346,20 @@ extern "C" int cloak_linear_fused(const cloak_layout* L, const void* d_pool, con
   GemvArgs a{};
   fill_common(L, d_pool, a, K, elt);
   a.nseg = n;
-  int32_t row0 = 0;
+  // every tensor starts on a whole row group (kGemvRows launch-rows), so a
+  // group never mixes tensors; out_off is the tensor's real column offset
+  int64_t row0 = 0, out_off = 0;
   for (int i = 0; i < n; ++i) {
-    a.seg[i] = make_seg(L, tensors[i], true, row0, row0);
-    row0 += a.seg[i].rows;
+    a.seg[i] = make_seg(L, tensors[i], true, int32_t(row0), int32_t(out_off));
+    row0 += (a.seg[i].rows + kGemvRows - 1) / kGemvRows * kGemvRows;
+    out_off += a.seg[i].rows;
+  }
+  if (row0 > INT32_MAX) {
+    set_error("cloak_linear: too many output rows");
+    return CLOAK_ESHAPE;
   }
   for (int i = n; i < 4; ++i) a.seg[i] = a.seg[0], a.seg[i].row0 = INT32_MAX;
-  a.groups = int32_t((total + 7) / 8);
+  a.groups = int32_t(row0 / kGemvRows);
   a.x = d_x;
   a.x_perm = any_down ? L->dev.perms + L->ffn[t0.perm_layer].dev_off : nullptr;
   a.y = d_y;
@@ -427,7 +434,7 @@ extern "C" int cloak_swiglu(const cloak_layout* L, const void* d_pool, int32_t l
   a.seg[1] = make_seg(L, f->up, false, 0, 0);
   a.seg[2] = a.seg[0];
   a.seg[3] = a.seg[0];
-  a.groups = int32_t((dff + 3) / 4);
+  a.groups = int32_t((dff + kGemvRows / 2 - 1) / (kGemvRows / 2));
   a.x = d_x;
   a.x_perm = nullptr;
   a.y = d_h;
@@ -457,7 +464,7 @@ extern "C" int cloak_down(const cloak_layout* L, const void* d_pool, int32_t lay
   b.nseg = 1;
   b.seg[0] = make_seg(L, f->down, false, 0, 0);
   for (int i = 1; i < 4; ++i) b.seg[i] = b.seg[0], b.seg[i].row0 = INT32_MAX;
-  b.groups = int32_t((dm + 7) / 8);
+  b.groups = int32_t((dm + kGemvRows - 1) / kGemvRows);
   b.x = d_h;
   b.x_perm = nullptr;
   b.y = d_y;

@@ -36,6 +36,22 @@ namespace {
 
 typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2_t;
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+// The page map is read through the constant address space so that its
+// wave-uniform lookups become scalar loads (lgkmcnt), which never make the
+// vector weight loads wait for each other.
+typedef const int32_t __attribute__((address_space(4)))* scalar_i32_ptr;
+
+// Wave-uniform by construction (derived from the workgroup id and loop
+// counters); readfirstlane tells the compiler so.
+__device__ inline int64_t uniform64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
+  return int64_t((uint64_t(hi) << 32) | lo);
+}
+
+__device__ inline int64_t page_of(const int32_t* phi, int64_t vpage) {
+  return int64_t(((scalar_i32_ptr)phi)[uniform64(vpage)]);
+}
 
 constexpr int kChunkBytes = 1024;
 constexpr int kMaxWaves = 8;
@@ -54,8 +70,7 @@ __device__ inline uint16_t f32_to_bf16_rne(float f) {
 
 __device__ inline bf16x2_t as_bf16x2(uint32_t v) { return __builtin_bit_cast(bf16x2_t, v); }
 
-// Segment fields picked with an unrolled select so the by-value kernel
-// argument is never indexed dynamically.
+// One tensor of a launch, as the kernel uses it.
 struct SegView {
   int64_t vbase, npages;
   const int32_t* out_perm;
@@ -63,36 +78,31 @@ struct SegView {
   int32_t rows, row0, out_off;
 };
 
-__device__ inline SegView seg_view(const GemvArgs& a, int s) {
+__device__ inline SegView seg_at(const GemvArgs& a, int i) {
+  // i is wave-uniform: one batch of scalar loads from the argument segment
+  const WSeg& w = a.seg[i];
   SegView v;
-  v.vbase = a.seg[0].vbase; v.npages = a.seg[0].npages; v.out_perm = a.seg[0].out_perm;
-  v.scale = a.seg[0].scale; v.rows = a.seg[0].rows; v.row0 = a.seg[0].row0; v.out_off = a.seg[0].out_off;
-#pragma unroll
-  for (int i = 1; i < 4; ++i) {
-    if (s == i) {
-      v.vbase = a.seg[i].vbase; v.npages = a.seg[i].npages; v.out_perm = a.seg[i].out_perm;
-      v.scale = a.seg[i].scale; v.rows = a.seg[i].rows; v.row0 = a.seg[i].row0; v.out_off = a.seg[i].out_off;
-    }
-  }
+  v.vbase = w.vbase;
+  v.npages = w.npages;
+  v.out_perm = w.out_perm;
+  v.scale = w.scale;
+  v.rows = w.rows;
+  v.row0 = w.row0;
+  v.out_off = w.out_off;
   return v;
 }
 
-// Row r of group g -> (segment, stored row n).  Returns false past the end.
+// Rows of one group all belong to one tensor: the host starts every tensor
+// on a multiple of R launch-rows.  SwiGLU groups pair R/2 gate rows
+// (segment 0) with the same R/2 up rows (segment 1).
 template <int R, int EPI>
-__device__ inline bool resolve_row(const GemvArgs& a, int g, int r, int& s, int& n) {
-  if (EPI == kSwiGLU) {
-    s = r < R / 2 ? 0 : 1;
-    n = g * (R / 2) + (r % (R / 2));
-    return n < a.seg[0].rows;
-  }
-  const int row = g * R + r;
-  s = 0;
+__device__ inline int group_segment(const GemvArgs& a, int grp) {
+  if (EPI == kSwiGLU) return 0;
+  int s = 0;
 #pragma unroll
   for (int i = 1; i < 4; ++i)
-    if (i < a.nseg && row >= a.seg[i].row0) s = i;
-  const SegView v = seg_view(a, s);
-  n = row - v.row0;
-  return n < v.rows;
+    if (i < a.nseg && grp * R >= a.seg[i].row0) s = i;
+  return __builtin_amdgcn_readfirstlane(s);
 }
 
 template <int WT>
@@ -122,30 +132,39 @@ __device__ inline void load_x(const GemvArgs& a, int c, int m, int lane, uint32_
   }
 }
 
-// 16 B of stored row n, chunk c, for this lane; zero when the lane is past
-// the end of the row.
+// Where chunk c of stored row n lives: the physical pages holding its first
+// byte (p0) and, for a chunk that crosses a page boundary (rows whose size
+// is not a multiple of 1 KiB), the next one (p1); `inpage` is the chunk's
+// offset in p0.  All wave-uniform: scalar loads only.
+struct ChunkLoc {
+  int64_t p0, p1, inpage;
+};
+
 template <bool TR>
-__device__ inline u32x4 load_w(const GemvArgs& a, const SegView& v, int n, int c, int lane, bool lane_ok) {
+__device__ inline ChunkLoc locate(const GemvArgs& a, const SegView& v, int n, int c) {
   const int64_t o = int64_t(n) * a.row_bytes + int64_t(c) * kChunkBytes;
   const int64_t page_bytes = int64_t(1) << a.log2_page;
   const int64_t vp = o >> a.log2_page;
-  const int64_t inpage = o & (page_bytes - 1);
+  ChunkLoc L;
+  L.inpage = o & (page_bytes - 1);
   const int64_t vpage = v.vbase + vp;
-  const int64_t p0 = TR ? int64_t(a.phi[vpage]) : vpage;
+  // the second lookup is unconditional (index clamped to the tensor's last
+  // page) so that both scalar loads of every row can be in flight together
+  const int64_t vnext = vp + 1 < v.npages ? vpage + 1 : vpage;
+  L.p0 = TR ? page_of(a.phi, vpage) : vpage;
+  L.p1 = TR ? page_of(a.phi, vnext) : vnext;
+  return L;
+}
+
+// This lane's 16 B of a located chunk (zero past the end of the row).
+__device__ inline u32x4 load_chunk(const GemvArgs& a, const ChunkLoc& L, int lane, bool lane_ok) {
+  const int64_t page_bytes = int64_t(1) << a.log2_page;
+  const int64_t lo = L.inpage + int64_t(lane) * 16;
+  const bool second = lo >= page_bytes;
+  const int64_t phys = second ? L.p1 : L.p0;
+  const uint8_t* addr = a.pool + (phys << a.log2_page) + (second ? lo - page_bytes : lo);
   u32x4 w = {0u, 0u, 0u, 0u};
-  if (inpage + kChunkBytes <= page_bytes) {
-    // common case: the whole chunk sits in one page, uniform base address
-    const uint8_t* base = a.pool + (p0 << a.log2_page) + inpage;
-    if (lane_ok) w = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(base) + lane);
-  } else {
-    // ragged rows only: the chunk crosses into the next virtual page
-    const int64_t p1 = (vp + 1 < v.npages) ? (TR ? int64_t(a.phi[vpage + 1]) : vpage + 1) : p0;
-    const int64_t lo = inpage + int64_t(lane) * 16;
-    const bool second = lo >= page_bytes;
-    const int64_t phys = second ? p1 : p0;
-    const uint8_t* addr = a.pool + (phys << a.log2_page) + (second ? lo - page_bytes : lo);
-    if (lane_ok) w = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(addr));
-  }
+  if (lane_ok) w = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(addr));
   return w;
 }
 
@@ -176,38 +195,81 @@ __device__ inline float dot_chunk(const u32x4 w, const uint32_t (&x)[WTraits<WT>
 
 // Transposing butterfly: on entry v[0..V) are per-lane partials; on exit
 // v[0] of lane l is the 64-lane sum of value index (l >> (6 - log2 V)).
-template <int V>
-__device__ inline void lane_reduce(float (&v)[V], int lane) {
-  int count = V;
+// Stage with partner distance D and COUNT live values: a lane keeps the
+// half selected by its D bit and adds the partner's copy of that half;
+// once one value is left, the remaining stages are plain xor sums.  Every
+// count and index is a compile-time constant, so v stays in registers.
+template <int D, int COUNT, int V>
+struct LaneReduce {
+  __device__ static inline void run(float (&v)[V], int lane) {
+    const bool upper = (lane & D) != 0;
+    if constexpr (COUNT > 1) {
+      constexpr int H = COUNT / 2;
 #pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    const bool upper = (lane & d) != 0;
-    if (count > 1) {
-      const int h = count / 2;
-#pragma unroll
-      for (int i = 0; i < V / 2; ++i) {
-        if (i < h) {
-          const float send = upper ? v[i] : v[i + h];
-          const float keep = upper ? v[i + h] : v[i];
-          v[i] = keep + __shfl_xor(send, d);
-        }
+      for (int i = 0; i < H; ++i) {
+        const float send = upper ? v[i] : v[i + H];
+        const float keep = upper ? v[i + H] : v[i];
+        v[i] = keep + __shfl_xor(send, D);
       }
-      count = h;
+      if constexpr (D > 1) LaneReduce<D / 2, H, V>::run(v, lane);
     } else {
-      v[0] += __shfl_xor(v[0], d);
+      v[0] += __shfl_xor(v[0], D);
+      if constexpr (D > 1) LaneReduce<D / 2, 1, V>::run(v, lane);
     }
   }
+};
+
+template <int V>
+__device__ inline void lane_reduce(float (&v)[V], int lane) {
+  LaneReduce<32, V, V>::run(v, lane);
 }
 
 template <int N> struct Log2 { static constexpr int value = 1 + Log2<N / 2>::value; };
 template <> struct Log2<1> { static constexpr int value = 0; };
 
+template <int WT, int R, int CPW, bool TR, int EPI>
+struct GroupLoads {
+  u32x4 w[CPW][R];
+};
+
+// Issue every weight load of group `grp` for this wave (page lookups first,
+// as one batch of scalar loads, then R*CPW independent 16 B loads per lane).
+template <int WT, int R, int CPW, bool TR, int EPI>
+__device__ inline void issue_group(const GemvArgs& a, int grp, int wave, int nwaves, int lane,
+                                   GroupLoads<WT, R, CPW, TR, EPI>& L) {
+  constexpr int EPL = WTraits<WT>::EPL;
+  const SegView sv = seg_at(a, EPI == kSwiGLU ? 0 : group_segment<R, EPI>(a, grp));
+  const SegView up = seg_at(a, EPI == kSwiGLU ? 1 : 0);
+#pragma unroll
+  for (int i = 0; i < CPW; ++i) {
+    const int c = wave + i * nwaves;
+    const bool c_ok = c < a.nchunks;
+    const int cc = c_ok ? c : 0;
+    const bool lane_ok = (cc * 64 * EPL + lane * EPL) < a.K;
+    ChunkLoc loc[R];
+    bool rok[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int n = EPI == kSwiGLU ? grp * (R / 2) + (r % (R / 2)) : grp * R + r - sv.row0;
+      const SegView v = (EPI == kSwiGLU && r >= R / 2) ? up : sv;
+      rok[r] = c_ok && n < v.rows;
+      // rows past the end look up row 0 (always valid) and skip their load
+      loc[r] = locate<TR>(a, v, rok[r] ? n : 0, cc);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      L.w[i][r] = rok[r] ? load_chunk(a, loc[r], lane, lane_ok) : u32x4{0u, 0u, 0u, 0u};
+  }
+}
+
 template <int WT, int MT, int R, int CPW, bool TR, int EPI>
 __global__ __launch_bounds__(512) void gemv_kernel(const GemvArgs a) {
   constexpr int XW = WTraits<WT>::XW;
-  constexpr int EPL = WTraits<WT>::EPL;
   constexpr int V = R * MT;
   constexpr int LOG2V = Log2<V>::value;
+  // prefetch the next group's weights while reducing the current one when
+  // the second register set fits
+  constexpr bool PF = CPW * R <= 16;
   static_assert((1 << LOG2V) == V && V <= 64, "R*MT must be a power of two <= 64");
   __shared__ float red[2][kMaxWaves][V];
 
@@ -230,31 +292,25 @@ __global__ __launch_bounds__(512) void gemv_kernel(const GemvArgs a) {
     }
   }
 
+  using Loads = GroupLoads<WT, R, CPW, TR, EPI>;
+  Loads cur;
+  if (PF && int(blockIdx.x) < a.groups) issue_group<WT, R, CPW, TR, EPI>(a, blockIdx.x, wave, nwaves, lane, cur);
+
   int it = 0;
   for (int g = blockIdx.x; g < a.groups; g += gridDim.x, ++it) {
+    if constexpr (!PF) issue_group<WT, R, CPW, TR, EPI>(a, g, wave, nwaves, lane, cur);
     float v[V];
 #pragma unroll
     for (int j = 0; j < V; ++j) v[j] = 0.f;
 #pragma unroll
-    for (int i = 0; i < CPW; ++i) {
-      const int c = wave + i * nwaves;
-      const bool lane_ok = (c * 64 * EPL + lane * EPL) < a.K;
-      u32x4 w[R];
+    for (int i = 0; i < CPW; ++i)
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        int s, n;
-        const bool ok = resolve_row<R, EPI>(a, g, r, s, n);
-        if (ok && c < a.nchunks) {
-          w[r] = load_w<TR>(a, seg_view(a, s), n, c, lane, lane_ok);
-        } else {
-          w[r] = u32x4{0u, 0u, 0u, 0u};
-        }
-      }
+      for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-#pragma unroll
-        for (int m = 0; m < MT; ++m) v[r * MT + m] = dot_chunk<WT>(w[r], xr[i][m], v[r * MT + m]);
-      }
+        for (int m = 0; m < MT; ++m) v[r * MT + m] = dot_chunk<WT>(cur.w[i][r], xr[i][m], v[r * MT + m]);
+    if constexpr (PF) {
+      const int gn = g + int(gridDim.x);
+      if (gn < a.groups) issue_group<WT, R, CPW, TR, EPI>(a, gn, wave, nwaves, lane, cur);
     }
     lane_reduce<V>(v, lane);
     const int buf = it & 1;
@@ -267,9 +323,9 @@ __global__ __launch_bounds__(512) void gemv_kernel(const GemvArgs a) {
         float sum = 0.f;
         for (int ww = 0; ww < nwaves; ++ww) sum += red[buf][ww][t];
         const int r = t / MT, m = t % MT;
-        int s, n;
-        if (resolve_row<R, EPI>(a, g, r, s, n) && m < a.mcount) {
-          const SegView sv = seg_view(a, s);
+        const SegView sv = seg_at(a, group_segment<R, EPI>(a, g));
+        const int n = g * R + r - sv.row0;
+        if (n < sv.rows && m < a.mcount) {
           if (sv.scale) sum *= sv.scale[n];
           const int col = sv.out_off + (sv.out_perm ? sv.out_perm[n] : n);
           const int64_t idx = int64_t(a.m0 + m) * a.ldy + col;
@@ -318,10 +374,10 @@ template <int WT, int CPW, bool TR, int EPI>
 KernelFn pick_mt(int mt) {
   constexpr int kMax = WT == kFP8 ? (CPW <= 1 ? 8 : CPW == 2 ? 4 : CPW == 4 ? 2 : 1)
                                   : (CPW <= 2 ? 8 : CPW == 4 ? 4 : 2);
-  if (mt <= 1) return gemv_kernel<WT, 1, 8, CPW, TR, EPI>;
-  if (mt <= 2 || kMax == 2) return gemv_kernel<WT, (kMax < 2 ? 1 : 2), 8, CPW, TR, EPI>;
-  if (mt <= 4 || kMax == 4) return gemv_kernel<WT, (kMax < 4 ? 1 : 4), 8, CPW, TR, EPI>;
-  return gemv_kernel<WT, (kMax < 8 ? 1 : 8), 8, CPW, TR, EPI>;
+  if (mt <= 1) return gemv_kernel<WT, 1, kGemvRows, CPW, TR, EPI>;
+  if (mt <= 2 || kMax == 2) return gemv_kernel<WT, (kMax < 2 ? 1 : 2), kGemvRows, CPW, TR, EPI>;
+  if (mt <= 4 || kMax == 4) return gemv_kernel<WT, (kMax < 4 ? 1 : 4), kGemvRows, CPW, TR, EPI>;
+  return gemv_kernel<WT, (kMax < 8 ? 1 : 8), kGemvRows, CPW, TR, EPI>;
 }
 
 template <int WT, bool TR, int EPI>

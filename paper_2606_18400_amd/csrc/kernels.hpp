@@ -21,6 +21,8 @@ struct WSeg {
 };
 
 enum WType : int { kF32 = 0, kBF16 = 1, kFP8 = 2 };
+// Rows per GEMV row group (a SwiGLU group holds kGemvRows/2 gate/up pairs).
+constexpr int kGemvRows = 8;
 enum Epilogue : int { kStore = 0, kSwiGLU = 1 };
 
 struct GemvArgs {
