@@ -34,6 +34,7 @@ if ROOT not in sys.path:
 
 METRIC = "cloaked/native ratio of decode GB/s and prefill TFLOP/s; p50/p99 token latency"
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_TFLOPS = 2500.0
 COPIES = 16
 TENSORS_PER_LAYER = 7   # q k v o gate up down
 
@@ -108,6 +109,31 @@ def time_steps(var, M, steps, warmup, kernel_events=False):
     if evs:
         kms = float(np.mean([a.elapsed_time(z) for a, z in evs]))
     return ms, kms
+
+
+def layer_flops(cfg, M):
+    d, f, kv = cfg["d_model"], cfg["d_ffn"], cfg["d_kv"]
+    return 2 * M * (d * d + 2 * kv * d + d * d + 3 * f * d)
+
+
+def time_prefill(var, M, reps, warmup):
+    """One prefill step (q,k,v fused, o, SwiGLU gate/up, down) at M tokens."""
+    import torch
+    b = var.buffers(M)
+    for i in range(warmup):
+        var.step(i, M, b)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for i in range(reps):
+        var.step(i, M, b, evs[i])
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / reps
+    k_ms = float(np.mean([a.elapsed_time(z) for a, z in evs]))
+    del b
+    return ms, k_ms
 
 
 def time_remap(var, reps):
@@ -197,6 +223,7 @@ def main():
     ap.add_argument("--batches", default="8,32,64", help="extra decode batch sizes reported beside M=1")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--remap-reps", type=int, default=5)
+    ap.add_argument("--prefill-tokens", type=int, default=8192, help="prefill batch (0 skips the prefill pass)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the cloaked layer needs no "
@@ -240,6 +267,21 @@ def main():
                               ms=m_cl, native_ms=m_nat)
         log(f"M={M} cloaked {b / m_cl / 1e6:.0f} GB/s native {b / m_nat / 1e6:.0f} GB/s")
 
+    pm = args.prefill_tokens
+    prefill = None
+    if pm > 0:
+        log(f"timing prefill M={pm}")
+        p_ms, p_kms = time_prefill(cl, pm, max(args.steps // 20, 5), 2)
+        n_ms, n_kms = time_prefill(nat, pm, max(args.steps // 20, 5), 2)
+        fl = layer_flops(cfg, pm)
+        sw_fl = 2 * pm * 2 * f * d
+        prefill = dict(tokens=pm, cloaked_tflops=fl / p_ms / 1e9, native_tflops=fl / n_ms / 1e9,
+                       ratio=n_ms / p_ms, ms=p_ms, native_ms=n_ms,
+                       roofline=dict(kernel="gemm_kernel SwiGLU (gate+up, bf16 MFMA)", bound="mfma",
+                                     achieved=sw_fl / p_kms / 1e9, peak=MFMA_BF16_PEAK_TFLOPS, unit="TFLOP/s",
+                                     frac=sw_fl / p_kms / 1e9 / MFMA_BF16_PEAK_TFLOPS, flops_per_launch=sw_fl,
+                                     avg_launch_ms=p_kms, native_avg_launch_ms=n_kms))
+        log(f"prefill cloaked {fl / p_ms / 1e9:.0f} TFLOP/s native {fl / n_ms / 1e9:.0f} TFLOP/s")
     calib = copy_calibration()
     log("timing remap of the whole pool")
     remap = time_remap(cl, args.remap_reps)
@@ -264,7 +306,7 @@ def main():
                    "layout_seed": 1, "pages": 4096, "used_pages": 16 * 208},
         "cloaked_native_ratio": value / native,
         "decode": decode,
-        "prefill": None,
+        "prefill": prefill,
         "remap": remap,
         "copy_calibration": calib,
         "roofline": roofline,

@@ -225,6 +225,65 @@ int cloak_remap(cloak_layout* layout, void* d_pool, uint64_t remap_seed, void* s
 int cloak_remap_host(cloak_layout* layout, void* h_pool, uint64_t h_pool_bytes,
                      uint64_t remap_seed);
 
+/* ------------------------------------------------------------------------
+ * Decoder step for the serving loop.  The engine keeps KV state on the
+ * device (Section 4.1: the serving engine manages KV-cache blocks); only the
+ * weights are cloaked.  A model binds a layout whose tensors are, per layer
+ * l, (l, q) (l, k) (l, v) (l, o) (l, gate) (l, up) (l, down) in BF16, plus
+ * (-1, embed) [vocab][d_model] and (-1, head) [vocab][d_model].
+ * ------------------------------------------------------------------------ */
+typedef struct cloak_model cloak_model; /* opaque, owned by the library */
+
+typedef struct {
+  int32_t n_layers, d_model, n_heads, n_kv_heads, head_dim, d_ffn, vocab;
+  int32_t block_size;  /* tokens per KV block */
+  int64_t num_blocks;  /* KV blocks per layer */
+  float rope_theta;    /* rotate-half RoPE base */
+  float norm_eps;      /* RMSNorm epsilon */
+} cloak_model_config;
+
+/* One step's batch: n_tokens new tokens of n_seqs sequences (a prefill chunk
+ * or one decode token each), all arrays on the device.  Tokens of a sequence
+ * are consecutive in the arrays with consecutive positions; its KV blocks are
+ * block_table[seq][0 .. ceil(ctx/block_size)).  Attention work: n_tiles tiles
+ * of <= 16 consecutive tokens of one sequence (tile_seq/tok0/ntok), the
+ * context cut into n_splits slices of split_keys keys. */
+typedef struct {
+  int32_t n_tokens, n_seqs, max_blocks, n_logits;
+  int32_t n_tiles, n_splits, split_keys, reserved;
+  const int32_t* d_tokens;       /* [n_tokens] token ids (< vocab)            */
+  const int32_t* d_positions;    /* [n_tokens]                                */
+  const int32_t* d_tok_seq;      /* [n_tokens] sequence slot of each token    */
+  const int32_t* d_block_table;  /* [n_seqs][max_blocks] KV block ids         */
+  const int32_t* d_tile_seq;     /* [n_tiles]                                 */
+  const int32_t* d_tile_tok0;    /* [n_tiles]                                 */
+  const int32_t* d_tile_ntok;    /* [n_tiles]                                 */
+  const int32_t* d_logit_rows;   /* [n_logits] token rows that get logits     */
+  int32_t* d_out_tokens;         /* [n_logits] greedy argmax                  */
+  void* d_out_logits;            /* [n_logits][vocab] bf16, or NULL           */
+} cloak_step;
+
+/* Bind a layout, its pool, RMSNorm gains (d_gains: [2*n_layers+1][d_model]
+ * bf16 in the order attn_0, mlp_0, ..., final; NULL = all ones) and the KV
+ * cache (d_kv: [n_layers][2][num_blocks][n_kv_heads][block_size][head_dim]
+ * bf16, caller-owned).  head_dim must be 128 and n_heads/n_kv_heads <= 8.
+ * Errors: EINVAL, ESHAPE (missing tensor or shapes that disagree with cfg). */
+int cloak_model_create(const cloak_layout* layout, const void* d_pool, const cloak_model_config* cfg,
+                       const void* d_gains, void* d_kv, cloak_model** out);
+int cloak_model_free(cloak_model* model);
+
+/* Workspace for steps of at most max_tokens tokens, max_logits logit rows
+ * and max_tiles * max_splits attention slices. */
+uint64_t cloak_model_ws_bytes(const cloak_model* model, int64_t max_tokens, int64_t max_logits,
+                              int64_t max_tiles, int64_t max_splits);
+
+/* Run one decoder step on `stream`: embedding -> layers (RMSNorm, fused
+ * q/k/v projection, RoPE + KV write, paged attention, o projection,
+ * residual, RMSNorm, cloak_swiglu, cloak_down, residual) -> final RMSNorm of
+ * the logit rows -> head projection -> argmax.  Enqueues only. */
+int cloak_model_step(cloak_model* model, const cloak_step* step, void* d_ws, uint64_t ws_bytes,
+                     void* stream);
+
 /* Message describing the last error on the calling thread ("" if none). */
 const char* cloak_last_error(void);
 

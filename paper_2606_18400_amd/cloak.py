@@ -52,6 +52,24 @@ class CloakError(RuntimeError):
         self.code = code
 
 
+class cloak_model_config(ctypes.Structure):
+    _fields_ = [("n_layers", ctypes.c_int32), ("d_model", ctypes.c_int32), ("n_heads", ctypes.c_int32),
+                ("n_kv_heads", ctypes.c_int32), ("head_dim", ctypes.c_int32), ("d_ffn", ctypes.c_int32),
+                ("vocab", ctypes.c_int32), ("block_size", ctypes.c_int32), ("num_blocks", ctypes.c_int64),
+                ("rope_theta", ctypes.c_float), ("norm_eps", ctypes.c_float)]
+
+
+class cloak_step(ctypes.Structure):
+    _fields_ = [("n_tokens", ctypes.c_int32), ("n_seqs", ctypes.c_int32), ("max_blocks", ctypes.c_int32),
+                ("n_logits", ctypes.c_int32), ("n_tiles", ctypes.c_int32), ("n_splits", ctypes.c_int32),
+                ("split_keys", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("d_tokens", ctypes.c_void_p), ("d_positions", ctypes.c_void_p), ("d_tok_seq", ctypes.c_void_p),
+                ("d_block_table", ctypes.c_void_p), ("d_tile_seq", ctypes.c_void_p),
+                ("d_tile_tok0", ctypes.c_void_p), ("d_tile_ntok", ctypes.c_void_p),
+                ("d_logit_rows", ctypes.c_void_p), ("d_out_tokens", ctypes.c_void_p),
+                ("d_out_logits", ctypes.c_void_p)]
+
+
 _vp, _i32, _i64, _u64, _u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32
 _SIGS = {
     "cloak_layout_build": ([_u64, ctypes.POINTER(cloak_shape), _i32, _u64, _u64, _u32, ctypes.POINTER(_vp)], _i32),
@@ -70,6 +88,10 @@ _SIGS = {
     "cloak_down": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp], _i32),
     "cloak_remap": ([_vp, _vp, _u64, _vp], _i32),
     "cloak_remap_host": ([_vp, _vp, _u64, _u64], _i32),
+    "cloak_model_create": ([_vp, _vp, ctypes.POINTER(cloak_model_config), _vp, _vp, ctypes.POINTER(_vp)], _i32),
+    "cloak_model_free": ([_vp], _i32),
+    "cloak_model_ws_bytes": ([_vp, _i64, _i64, _i64, _i64], _u64),
+    "cloak_model_step": ([_vp, ctypes.POINTER(cloak_step), _vp, _u64, _vp], _i32),
     "cloak_last_error": ([], ctypes.c_char_p),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -224,6 +246,29 @@ def cloak_remap_host(layout, pool_image, remap_seed):
            "cloak_remap_host")
 
 
+def cloak_model_create(layout, pool, cfg, gains, kv):
+    out = _vp()
+    _check(_lib.cloak_model_create(layout, _ptr(pool), ctypes.byref(cfg), _ptr(gains), _ptr(kv), ctypes.byref(out)),
+           "cloak_model_create")
+    return out.value
+
+
+def cloak_model_free(model):
+    _check(_lib.cloak_model_free(model), "cloak_model_free")
+
+
+def cloak_model_ws_bytes(model, max_tokens, max_logits, max_tiles, max_splits):
+    v = _lib.cloak_model_ws_bytes(model, max_tokens, max_logits, max_tiles, max_splits)
+    if v == (1 << 64) - 1:
+        raise CloakError(CLOAK_EINVAL, "cloak_model_ws_bytes", "bad arguments")
+    return v
+
+
+def cloak_model_step(model, step, ws, ws_bytes, stream=None):
+    _check(_lib.cloak_model_step(model, ctypes.byref(step), _ptr(ws), ws_bytes, _stream(stream)),
+           "cloak_model_step")
+
+
 # ---------------------------------------------------------------- convenience
 class CloakedWeights:
     """A layout, its device pool and the tensors loaded into it.
@@ -270,7 +315,9 @@ class CloakedWeights:
         M = x.shape[0]
         if out is None:
             out = torch.empty((M, n), dtype=x.dtype, device=x.device)
-        cloak_linear(self.layout, self.pool, t, x, M, out)
+        need = cloak_ws_bytes(self.layout, CLOAK_OP_LINEAR, t, M)
+        ws = self.workspace(need) if need else None
+        cloak_linear(self.layout, self.pool, t, x, M, out, ws, 0 if ws is None else ws.numel())
         return out
 
     def linear_fused(self, ts, x, out=None):

@@ -130,6 +130,20 @@ int run_gemv(const cloak_layout* L, GemvArgs a, int wtype, int64_t M, hipStream_
   return CLOAK_OK;
 }
 
+bool use_gemm(int32_t dtype, int64_t K, int64_t M) {
+  return dtype == CLOAK_BF16 && M >= kGemmMinTokens && K % gemm_k_step() == 0;
+}
+
+void fill_gemm(const cloak_layout* L, const void* pool, GemmArgs& g, int64_t K, int64_t M) {
+  g.pool = static_cast<const uint8_t*>(pool);
+  g.phi = L->dev.phi;
+  g.log2_page = L->log2_page;
+  g.K = int32_t(K);
+  g.row_bytes = K * 2;
+  g.M = int32_t(M);
+  g.tiles_m = int32_t((M + gemm_tile_rows() - 1) / gemm_tile_rows());
+}
+
 void fill_common(const cloak_layout* L, const void* pool, GemvArgs& a, int64_t K, int elt) {
   a.pool = static_cast<const uint8_t*>(pool);
   a.phi = L->dev.phi;
@@ -277,6 +291,11 @@ extern "C" uint64_t cloak_ws_bytes(const cloak_layout* L, int32_t op, int32_t in
   if (!L || M < 0) return UINT64_MAX;
   if (op == CLOAK_OP_LINEAR) {
     if (index < 0 || index >= int32_t(L->tensors.size())) return UINT64_MAX;
+    const TensorInfo& ti = L->tensors[index];
+    // the prefill GEMM reads x in stored column order: a down projection's
+    // activations are gathered through pi into the workspace first
+    if (ti.perm_layer >= 0 && is_col_permuted(ti.shape.kind) && use_gemm(ti.shape.dtype, ti.shape.k_in, M))
+      return (uint64_t(M) * uint64_t(ti.shape.k_in) * 2 + 255) / 256 * 256;
     return 0;
   }
   if (op == CLOAK_OP_MLP) {
@@ -343,6 +362,48 @@ extern "C" int cloak_linear_fused(const cloak_layout* L, const void* d_pool, con
     set_error("cloak_linear: null x or y");
     return CLOAK_EINVAL;
   }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (use_gemm(dtype, K, M)) {
+    GemmArgs g{};
+    fill_gemm(L, d_pool, g, K, M);
+    const void* xin = d_x;
+    if (any_down) {
+      const uint64_t need = cloak_ws_bytes(L, CLOAK_OP_LINEAR, tensors[0], M);
+      if (!d_ws || ws_bytes < need) {
+        set_error("cloak_linear: down projection at M=%lld needs a workspace of %llu bytes", (long long)M,
+                  (unsigned long long)need);
+        return CLOAK_EINVAL;
+      }
+      HIP_TRY(launch_gather_cols(static_cast<const uint16_t*>(d_x), K, L->dev.perms + L->ffn[t0.perm_layer].dev_off,
+                                 static_cast<uint16_t*>(d_ws), M, K, st),
+              "cloak_linear(gather)");
+      xin = d_ws;
+    }
+    const int64_t tr = gemm_tile_rows();
+    int64_t row0 = 0, out_off = 0;
+    bool aligned = total % 4 == 0 && reinterpret_cast<uintptr_t>(d_y) % 8 == 0;
+    for (int i = 0; i < n; ++i) {
+      g.seg[i] = make_seg(L, tensors[i], true, int32_t(row0), int32_t(out_off));
+      aligned = aligned && out_off % 4 == 0;
+      row0 += (g.seg[i].rows + tr - 1) / tr * tr;
+      out_off += g.seg[i].rows;
+    }
+    if (row0 > INT32_MAX) {
+      set_error("cloak_linear: too many output rows");
+      return CLOAK_ESHAPE;
+    }
+    for (int i = n; i < 4; ++i) g.seg[i] = g.seg[0], g.seg[i].row0 = INT32_MAX;
+    g.nseg = n;
+    g.mode = kStore;
+    g.tiles_n = int32_t(row0 / tr);
+    g.x = static_cast<const uint16_t*>(xin);
+    g.ldx = K;
+    g.y = d_y;
+    g.ldy = total;
+    g.vec_store = aligned ? 1 : 0;
+    HIP_TRY(launch_gemm(g, !L->native(), st), "cloak_linear(gemm)");
+    return CLOAK_OK;
+  }
   GemvArgs a{};
   fill_common(L, d_pool, a, K, elt);
   a.nseg = n;
@@ -366,7 +427,7 @@ extern "C" int cloak_linear_fused(const cloak_layout* L, const void* d_pool, con
   a.ldx = K;
   a.ldy = total;
   a.mode = kStore;
-  return run_gemv(L, a, wtype_of(dtype), M, static_cast<hipStream_t>(stream), "cloak_linear");
+  return run_gemv(L, a, wtype_of(dtype), M, st, "cloak_linear");
 }
 
 extern "C" int cloak_linear(const cloak_layout* L, const void* d_pool, int32_t tensor, const void* d_x, int64_t M,
@@ -426,6 +487,25 @@ extern "C" int cloak_swiglu(const cloak_layout* L, const void* d_pool, int32_t l
   const int32_t dtype = tg.shape.dtype;
   const int elt = elt_bytes(dtype);
   const int64_t dm = tg.shape.k_in, dff = f->d_ffn;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (use_gemm(dtype, dm, M)) {
+    GemmArgs g{};
+    fill_gemm(L, d_pool, g, dm, M);
+    g.nseg = 2;
+    g.seg[0] = make_seg(L, f->gate, false, 0, 0);
+    g.seg[1] = make_seg(L, f->up, false, 0, 0);
+    g.seg[2] = g.seg[0];
+    g.seg[3] = g.seg[0];
+    g.mode = kSwiGLU;
+    g.tiles_n = int32_t((dff + gemm_tile_rows() / 2 - 1) / (gemm_tile_rows() / 2));
+    g.x = static_cast<const uint16_t*>(d_x);
+    g.ldx = dm;
+    g.y = d_h;
+    g.ldy = dff;
+    g.vec_store = (dff % 4 == 0 && reinterpret_cast<uintptr_t>(d_h) % 8 == 0) ? 1 : 0;
+    HIP_TRY(launch_gemm(g, !L->native(), st), "cloak_swiglu(gemm)");
+    return CLOAK_OK;
+  }
   // gate + up row pairs in one launch, SwiGLU epilogue -> h in permuted order
   GemvArgs a{};
   fill_common(L, d_pool, a, dm, elt);
@@ -441,7 +521,7 @@ extern "C" int cloak_swiglu(const cloak_layout* L, const void* d_pool, int32_t l
   a.ldx = dm;
   a.ldy = dff;
   a.mode = kSwiGLU;
-  return run_gemv(L, a, wtype_of(dtype), M, static_cast<hipStream_t>(stream), "cloak_swiglu");
+  return run_gemv(L, a, wtype_of(dtype), M, st, "cloak_swiglu");
 }
 
 extern "C" int cloak_down(const cloak_layout* L, const void* d_pool, int32_t layer, const void* d_h, int64_t M,
@@ -458,6 +538,24 @@ extern "C" int cloak_down(const cloak_layout* L, const void* d_pool, int32_t lay
   const int32_t dtype = tg.shape.dtype;
   const int elt = elt_bytes(dtype);
   const int64_t dm = tg.shape.k_in, dff = f->d_ffn;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (use_gemm(dtype, dff, M)) {
+    // down's stored columns are permuted exactly like h: no gather needed
+    GemmArgs g{};
+    fill_gemm(L, d_pool, g, dff, M);
+    g.nseg = 1;
+    g.seg[0] = make_seg(L, f->down, false, 0, 0);
+    for (int i = 1; i < 4; ++i) g.seg[i] = g.seg[0], g.seg[i].row0 = INT32_MAX;
+    g.mode = kStore;
+    g.tiles_n = int32_t((dm + gemm_tile_rows() - 1) / gemm_tile_rows());
+    g.x = static_cast<const uint16_t*>(d_h);
+    g.ldx = dff;
+    g.y = d_y;
+    g.ldy = dm;
+    g.vec_store = (dm % 4 == 0 && reinterpret_cast<uintptr_t>(d_y) % 8 == 0) ? 1 : 0;
+    HIP_TRY(launch_gemm(g, !L->native(), st), "cloak_down(gemm)");
+    return CLOAK_OK;
+  }
   // down's stored columns are permuted exactly like h: no gather needed
   GemvArgs b{};
   fill_common(L, d_pool, b, dff, elt);
@@ -471,7 +569,7 @@ extern "C" int cloak_down(const cloak_layout* L, const void* d_pool, int32_t lay
   b.ldx = dff;
   b.ldy = dm;
   b.mode = kStore;
-  return run_gemv(L, b, wtype_of(dtype), M, static_cast<hipStream_t>(stream), "cloak_down");
+  return run_gemv(L, b, wtype_of(dtype), M, st, "cloak_down");
 }
 
 extern "C" int cloak_mlp(const cloak_layout* L, const void* d_pool, int32_t layer, const void* d_x, int64_t M,

@@ -50,6 +50,97 @@ hipError_t launch_gemv(const GemvArgs& a, int wtype, int mtile, bool translate, 
 // Token tile limit of the GEMV for this weight type and row length.
 int gemv_max_tokens(int wtype, int nchunks);
 
+// Prefill GEMM (BF16 MFMA, 256x256x64 tiles).  In STORE mode every tensor
+// starts on a multiple of gemm_tile_rows() launch-rows; in SwiGLU mode
+// segment 0 is gate and segment 1 is up, and a tile covers
+// gemm_tile_rows()/2 hidden units.
+struct GemmArgs {
+  const uint8_t* pool;
+  const int32_t* phi;
+  int32_t log2_page;
+  int32_t K;                // multiple of gemm_k_step()
+  int64_t row_bytes;        // K * 2
+  int32_t nseg;
+  int32_t mode;             // Epilogue
+  WSeg seg[4];
+  const uint16_t* x;        // [M][ldx] bf16, in the tensors' stored column order
+  int64_t ldx;
+  void* y;                  // [M][ldy] bf16
+  int64_t ldy;
+  int32_t M;
+  int32_t tiles_m, tiles_n;
+  int32_t vec_store;        // 1 if 8-byte output stores are aligned
+};
+hipError_t launch_gemm(const GemmArgs& a, bool translate, hipStream_t s);
+hipError_t launch_gather_cols(const uint16_t* x, int64_t ldx, const int32_t* perm, uint16_t* out, int64_t M,
+                              int64_t K, hipStream_t s);
+int gemm_tile_rows();
+int gemm_k_step();
+// Token count from which BF16 projections use the MFMA GEMM instead of the GEMV.
+constexpr int64_t kGemmMinTokens = 17;
+
+// ---- decoder-step kernels (serve.hip)
+struct EmbedArgs {
+  const uint8_t* pool;
+  const int32_t* phi;
+  int32_t log2_page;
+  int32_t translate;
+  int64_t vbase;
+  int32_t vocab;
+  int32_t row_bytes;
+  const int32_t* ids;
+  int32_t T;
+  int32_t pad;
+  void* out;                // [T][D] bf16
+};
+struct NormArgs {
+  const uint16_t* x;        // residual stream rows
+  const uint16_t* add;      // added to x first (or null)
+  uint16_t* r_out;          // where x + add is stored (or null)
+  const uint16_t* gain;     // [D] (or null = ones)
+  uint16_t* h;              // normalised rows (row i <- source row rows[i])
+  const int32_t* rows;      // source rows (or null = identity)
+  int32_t D;
+  float eps;
+};
+struct RopeArgs {
+  uint16_t* qkv;            // [T][ldqkv]: q heads, k heads, v heads
+  int64_t ldqkv;
+  const int32_t* positions;
+  const int32_t* tok_seq;
+  const int32_t* block_table;
+  int32_t max_blocks, bs, n_heads, n_kv, hd;
+  int64_t num_blocks;       // cache blocks per layer (block ids are clamped to it)
+  float theta;
+  uint16_t* kc;             // this layer's K cache [blocks][n_kv][bs][hd]
+  uint16_t* vc;
+};
+struct AttnArgs {
+  const uint16_t* q;        // rotated queries, row t at q + t*ldq, head h at column h*128
+  int64_t ldq;
+  const uint16_t* kc;
+  const uint16_t* vc;
+  const int32_t* block_table;
+  int32_t max_blocks, bs;
+  int64_t num_blocks;
+  const int32_t* tile_seq;  // per query tile (<= 16 consecutive new tokens of one sequence)
+  const int32_t* tile_tok0;
+  const int32_t* tile_ntok;
+  const int32_t* positions;
+  int32_t n_tiles, n_splits, split_keys;
+  int32_t n_heads, n_kv;
+  float scale;
+  float* part_o;            // [tiles][n_kv][splits][group][16][128]
+  float* part_ml;           // [tiles][n_kv][splits][group][16][2]
+  uint16_t* out;            // [T][ldo]
+  int64_t ldo;
+};
+hipError_t launch_embed(const EmbedArgs& a, hipStream_t s);
+hipError_t launch_rmsnorm(const NormArgs& a, int rows, hipStream_t s);
+hipError_t launch_rope_kv(const RopeArgs& a, int T, hipStream_t s);
+hipError_t launch_attention(const AttnArgs& a, hipStream_t s);
+hipError_t launch_argmax(const uint16_t* logits, int64_t rows, int64_t V, int32_t* out, hipStream_t s);
+
 struct SwapArgs {
   uint8_t* pool;
   const int32_t* pairs;     // [2*npairs] physical page pairs

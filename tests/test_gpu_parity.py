@@ -265,3 +265,91 @@ def test_empty_batch_and_argument_errors(C):
         nat.remap(1)
     assert e.value.code == C.CLOAK_ESTATE
     nat.close()
+
+
+# ---------------------------------------------------------------- prefill GEMM (MFMA)
+
+@pytest.mark.parametrize("M", [17, 100, 300, 600])
+def test_prefill_gemm_vs_fp64(C, M):
+    # K = 1024 / 2816 (multiples of 64): the BF16 MFMA GEMM path; N = 1000 and
+    # d_ffn 2816 leave ragged row tiles, M leaves ragged token tiles
+    shapes = decoder_shapes(1024, 2816, 256, "bf16", layers=1, extra=[(-1, "head", 1000, 1024, "bf16")])
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, 65536, 65536 * 512, seed=17)
+    cw.load(ws, scs)
+    check_linear_all(C, cw, shapes, ws, scs, M)
+    cw.close()
+
+
+def test_prefill_gemm_one_hot_bit_exact(C):
+    import torch
+    shapes = decoder_shapes(1024, 2816, 256, "bf16", layers=1)
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, 65536, 65536 * 512, seed=19)
+    cw.load(ws, scs)
+    rng = np.random.Generator(np.random.PCG64(8))
+    for t, s in enumerate(shapes):
+        K = s[3]
+        ks = list(rng.choice(K, size=40, replace=False))
+        ks[0], ks[-1] = 0, K - 1
+        x = np.zeros((len(ks), K), np.uint16)
+        for m, k in enumerate(ks):
+            x[m, k] = 0x3F80
+        xd = to_device_x(x)
+        need = C.cloak_ws_bytes(cw.layout, C.CLOAK_OP_LINEAR, t, len(ks))
+        ws_buf = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+        y = torch.empty((len(ks), s[2]), dtype=torch.bfloat16, device="cuda")
+        C.cloak_linear(cw.layout, cw.pool, t, xd, len(ks), y, ws_buf, ws_buf.numel())
+        want = np.stack([ws[t][:, k] for k in ks])
+        assert np.array_equal(from_device(y), want), (t, s)
+    cw.close()
+
+
+def test_prefill_gemm_cloaked_equals_native(C):
+    import torch
+    shapes = decoder_shapes(1024, 2816, 256, "bf16", layers=1)
+    ws, scs = make_weights(shapes)
+    B, P = 65536, 512
+    cl = C.CloakedWeights(shapes, B, B * P, seed=23)
+    nat = C.CloakedWeights(shapes, B, B * P, seed=23, flags=C.CLOAK_IDENTITY | C.CLOAK_NATIVE)
+    cl.load(ws, scs)
+    nat.load(ws, scs)
+    M = 333
+    for t, s in enumerate(shapes):
+        if s[1] == "down":
+            continue
+        x = to_device_x(synth.activations(M, s[3], "bf16", seed=t))
+        assert torch.equal(cl.linear(t, x).view(torch.int16), nat.linear(t, x).view(torch.int16)), s
+    x = to_device_x(synth.activations(M, 1024, "bf16", seed=99))
+    err = ON.normwise_err(values_f64(from_device(cl.mlp(0, x))), values_f64(from_device(nat.mlp(0, x))))
+    assert err <= 1e-2
+    cl.close()
+    nat.close()
+
+
+def test_prefill_full_layer4096_sampled_tokens(C):
+    """The 4096/14336 layer at M = 8192 prefill tokens, 2 MiB pages over an
+    8 GiB pool, checked against FP64 on 48 sampled tokens."""
+    import torch
+    cfg = synth.LAYER4096
+    shapes = decoder_shapes(cfg["d_model"], cfg["d_ffn"], cfg["d_kv"], "bf16", layers=1)
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, cfg["page_bytes"], cfg["pool_bytes"], seed=1)
+    cw.load(ws, scs)
+    M = 8192
+    x_np = synth.activations(M, cfg["d_model"], "bf16")
+    x = to_device_x(x_np)
+    rng = np.random.Generator(np.random.PCG64(3))
+    rows = np.sort(rng.choice(M, size=48, replace=False))
+    rows[0], rows[-1] = 0, M - 1
+    x64 = values_f64(x_np[rows])
+    for t in (0, 3):   # q and o (K = 4096)
+        y = from_device(cw.linear(t, x))[rows]
+        err = ON.normwise_err(values_f64(y), ON.linear(x64, w64(shapes, ws, scs, t)))
+        assert err <= 1e-2, (t, err)
+    y = from_device(cw.mlp(0, x))[rows]
+    ref, _ = ON.swiglu_ffn(x64, w64(shapes, ws, scs, 4), w64(shapes, ws, scs, 5), w64(shapes, ws, scs, 6))
+    err = ON.normwise_err(values_f64(y), ref)
+    assert err <= 1e-2, err
+    cw.close()
+    torch.cuda.empty_cache()

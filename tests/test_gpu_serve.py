@@ -1,0 +1,133 @@
+"""Serving loop on the GPU: decoder step vs the FP64 oracle decoder, each
+request's result alone vs in a continuous-batching mix, remap mid-run, and
+admission under KV-block pressure.
+
+Tolerance: logits per generated position, normwise max|y - y*| / max|y*|.
+The decoder runs every activation in bf16 between kernels (norms, q/k/v,
+attention, projections, residual stream), so against FP64 the bound is the
+per-op bf16 budget summed over the ops of two layers: 3e-2.  Alone vs mix
+compares two GPU runs whose only differences are kernel choices (GEMV vs
+MFMA GEMM by batch size, context slicing): 1e-2.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import model as OM
+from oracle import numerics as ON
+from paper_2606_18400_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TINY = dict(n_layers=2, d_model=256, n_heads=2, n_kv_heads=1, head_dim=128, d_ffn=512, vocab=1024,
+            theta=500000.0, eps=1e-5)
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2606_18400_amd import serve
+    return serve
+
+
+def tiny_weights(cfg, base_seed=1234):
+    shapes = __import__("paper_2606_18400_amd.serve", fromlist=["x"]).model_shapes(cfg)
+    ws = [synth.weight(t, s[2], s[3], "bf16", base_seed=base_seed)[0] for t, s in enumerate(shapes)]
+    return shapes, ws
+
+
+def oracle_decoder(cfg, shapes, ws):
+    w = {(s[0], s[1]): ON.bf16_bits_to_f64(ws[t]) for t, s in enumerate(shapes)}
+    return OM.DecoderFP64(cfg, w)
+
+
+def make_engine(S, cfg, ws, **kw):
+    args = dict(pool_bytes=64 << 20, page_bytes=64 << 10, seed=5, kv_blocks=256, block_size=16, max_tokens=256,
+                prefill_chunk=16, max_seqs=16, split_keys=64, remap_every=0, weights=ws, record_logits=True)
+    args.update(kw)
+    return S.Engine(cfg, **args)
+
+
+def test_tiny_decoder_matches_fp64_oracle(S):
+    shapes, ws = tiny_weights(TINY)
+    rng = np.random.Generator(np.random.PCG64(11))
+    prompt = rng.integers(0, TINY["vocab"], 40).astype(np.int32)
+    forced = rng.integers(0, TINY["vocab"], 8).astype(np.int32)
+    eng = make_engine(S, TINY, ws)
+    r = S.Request(0, prompt, len(forced), forced=forced)
+    eng.run([r], realtime=False)
+    ref = oracle_decoder(TINY, shapes, ws).forward(np.concatenate([prompt, forced[:-1]]))
+    worst = 0.0
+    for i, lg in enumerate(r.logits):
+        err = ON.normwise_err(lg, ref[len(prompt) - 1 + i])
+        worst = max(worst, err)
+        assert err <= 3e-2, (i, err)
+    print(f"tiny decoder worst normwise logit error vs FP64: {worst:.3e}")
+    eng.close()
+
+
+def test_each_result_same_alone_and_in_the_mix(S):
+    shapes, ws = tiny_weights(TINY)
+    rng = np.random.Generator(np.random.PCG64(12))
+    probe_prompt = rng.integers(0, TINY["vocab"], 37).astype(np.int32)
+    # alone: greedy
+    eng = make_engine(S, TINY, ws)
+    alone = S.Request(0, probe_prompt, 12)
+    eng.run([alone], realtime=False)
+    eng.close()
+    # in the mix: six other requests of uneven lengths arrive together; the
+    # probe is teacher-forced to its own greedy tokens
+    eng = make_engine(S, TINY, ws)
+    others = [S.Request(1 + i, rng.integers(0, TINY["vocab"], n).astype(np.int32), m)
+              for i, (n, m) in enumerate([(5, 20), (70, 6), (33, 15), (1, 9), (120, 4), (18, 30)])]
+    probe = S.Request(0, probe_prompt, 12, forced=alone.out)
+    eng.run(others[:3] + [probe] + others[3:], realtime=False)
+    assert eng.steps > 0 and all(o.done for o in others)
+    for i, (a, b) in enumerate(zip(alone.logits, probe.logits)):
+        err = ON.normwise_err(b, a)
+        assert err <= 1e-2, (i, err)
+        # greedy tokens agree unless the alone run had a near tie
+        top2 = np.sort(a)[-2:]
+        if top2[1] - top2[0] > 1e-2 * np.max(np.abs(a)):
+            assert int(np.argmax(b)) == alone.out[i]
+    eng.close()
+
+
+def test_remap_between_steps_changes_nothing(S):
+    shapes, ws = tiny_weights(TINY)
+    rng = np.random.Generator(np.random.PCG64(13))
+    prompts = [rng.integers(0, TINY["vocab"], n).astype(np.int32) for n in (20, 45, 3)]
+    outs = []
+    for every in (0, 1):
+        eng = make_engine(S, TINY, ws, remap_every=every)
+        reqs = [S.Request(i, p, 10) for i, p in enumerate(prompts)]
+        eng.run(reqs, realtime=False)
+        if every:
+            assert eng.remaps == eng.steps > 0
+        outs.append([(r.out, [l.copy() for l in r.logits]) for r in reqs])
+        eng.close()
+    for (oa, la), (ob, lb) in zip(*outs):
+        assert oa == ob
+        for x, y in zip(la, lb):
+            assert np.array_equal(x, y)
+
+
+def test_admission_never_overcommits_kv(S):
+    shapes, ws = tiny_weights(TINY)
+    rng = np.random.Generator(np.random.PCG64(14))
+    eng = make_engine(S, TINY, ws, kv_blocks=12, record_logits=False)
+    reqs = [S.Request(i, rng.integers(0, TINY["vocab"], n).astype(np.int32), m)
+            for i, (n, m) in enumerate([(60, 30), (40, 20), (90, 5), (10, 60), (30, 30)])]
+    for r in reqs:
+        eng.submit(r)
+    peak = 0
+    while eng.waiting or eng.running:
+        eng._admit(float("inf"))
+        used = sum(len(r.blocks) for r in eng.running)
+        assert used + len(eng.free_blocks) == 12
+        peak = max(peak, used)
+        eng.step()
+    assert all(r.done and len(r.out) == r.max_new for r in reqs)
+    assert peak <= 12
+    eng.close()

@@ -121,3 +121,50 @@ def test_synth_fp8_quantiser_is_nearest_even_saturating():
         ties = codes[d == best]
         if len(ties) > 1 and best > 0:   # exact tie: even mantissa wins
             assert (int(qb) & 1) == 0
+
+
+# ---------------------------------------------------------------- decoder pieces
+
+def test_rmsnorm_closed_form():
+    from oracle import model as M
+    v = np.array([[3.0, 4.0], [1.0, -1.0]])
+    out = M.rmsnorm(v, 1.0, 0.0)
+    np.testing.assert_allclose(out[0], [3 / np.sqrt(12.5), 4 / np.sqrt(12.5)], rtol=1e-15)
+    np.testing.assert_allclose(out[1], [1.0, -1.0], rtol=1e-15)
+
+
+def test_rope_is_a_rotation_and_relative():
+    from oracle import model as M
+    rng = np.random.Generator(np.random.PCG64(1))
+    q = rng.standard_normal((5, 16))
+    k = rng.standard_normal((5, 16))
+    pos = np.array([0, 3, 7, 100, 4097])
+    rq = M.rope(q, pos, 500000.0)
+    np.testing.assert_allclose(np.linalg.norm(rq, axis=1), np.linalg.norm(q, axis=1), rtol=1e-13)
+    np.testing.assert_allclose(rq[0], q[0], rtol=0, atol=0)          # position 0 is the identity
+    # scores depend only on the distance: <R(a)q, R(b)k> = <R(a+s)q, R(b+s)k>
+    a, b = np.array([10] * 5), np.array([3] * 5)
+    s1 = np.sum(M.rope(q, a, 1e4) * M.rope(k, b, 1e4), axis=1)
+    s2 = np.sum(M.rope(q, a + 57, 1e4) * M.rope(k, b + 57, 1e4), axis=1)
+    np.testing.assert_allclose(s1, s2, rtol=1e-10, atol=1e-12)
+    # 2-D case written out: angle = pos * theta^0 for d = 2
+    r = M.rope(np.array([[1.0, 0.0]]), np.array([0.5]), 10.0)
+    np.testing.assert_allclose(r[0], [np.cos(0.5), np.sin(0.5)], rtol=1e-15)
+
+
+def test_causal_attention_brute_force():
+    from oracle import model as M
+    rng = np.random.Generator(np.random.PCG64(2))
+    H, Hkv, T, d = 4, 2, 6, 8
+    q, k, v = rng.standard_normal((H, T, d)), rng.standard_normal((Hkv, T, d)), rng.standard_normal((Hkv, T, d))
+    out = M.causal_attention(q, k, v)
+    for h in range(H):
+        for t in range(T):
+            kv = h // 2
+            s = np.array([q[h, t] @ k[kv, j] / np.sqrt(d) for j in range(t + 1)])
+            p = np.exp(s - s.max())
+            p /= p.sum()
+            want = sum(p[j] * v[kv, j] for j in range(t + 1))
+            np.testing.assert_allclose(out[t, h * d:(h + 1) * d], want, rtol=1e-12, atol=1e-12)
+    # the first token attends only to itself
+    np.testing.assert_allclose(out[0, :d], v[0, 0], rtol=1e-13)
