@@ -68,7 +68,12 @@ class Variant:
         from paper_2606_18400_amd import synth
         d, f, kv = self.cfg["d_model"], self.cfg["d_ffn"], self.cfg["d_kv"]
         x = torch.from_numpy(synth.activations(M, d, "bf16").view(np.int16)).cuda().view(torch.bfloat16)
-        return dict(x=x,
+        C, L = self.C, self.cw.layout
+        # one workspace large enough for every call of the step (split-K partial sums)
+        need = max(C.cloak_linear_fused_ws_bytes(L, [0, 1, 2], M), C.cloak_ws_bytes(L, C.CLOAK_OP_LINEAR, 3, M),
+                   C.cloak_ws_bytes(L, C.CLOAK_OP_SWIGLU, 0, M), C.cloak_ws_bytes(L, C.CLOAK_OP_DOWN, 0, M))
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+        return dict(x=x, ws=ws,
                     qkv=torch.empty((M, d + 2 * kv), dtype=torch.bfloat16, device="cuda"),
                     o=torch.empty((M, d), dtype=torch.bfloat16, device="cuda"),
                     h=torch.empty((M, f), dtype=torch.bfloat16, device="cuda"),
@@ -79,14 +84,15 @@ class Variant:
         L, pool = cw.layout, cw.pool
         l = i % COPIES
         t0 = TENSORS_PER_LAYER * l
-        C.cloak_linear_fused(L, pool, [t0, t0 + 1, t0 + 2], b["x"], M, b["qkv"])
-        C.cloak_linear(L, pool, t0 + 3, b["x"], M, b["o"])
+        ws, wsb = b["ws"], b["ws"].numel()
+        C.cloak_linear_fused(L, pool, [t0, t0 + 1, t0 + 2], b["x"], M, b["qkv"], ws, wsb)
+        C.cloak_linear(L, pool, t0 + 3, b["x"], M, b["o"], ws, wsb)
         if ev is not None:
             ev[0].record()
-        C.cloak_swiglu(L, pool, l, b["x"], M, b["h"])
+        C.cloak_swiglu(L, pool, l, b["x"], M, b["h"], ws, wsb)
         if ev is not None:
             ev[1].record()
-        C.cloak_down(L, pool, l, b["h"], M, b["y"])
+        C.cloak_down(L, pool, l, b["h"], M, b["y"], ws, wsb)
 
 
 def time_steps(var, M, steps, warmup, kernel_events=False):
@@ -215,6 +221,141 @@ def cpu_oracle_baseline(cfg, weights, budget_s=12.0):
                        f"plus FP64 products, {el:.1f} s")
 
 
+def bench_serve(args):
+    """Serving trace on the 32-layer 4096/14336 BF16 stack (vocab 128256):
+    Poisson arrivals, prompts U[128,4096], outputs U[64,1024], continuous
+    batching with paged KV, remap every 256 steps (cloaked) vs the identity
+    layout with untranslated kernels and no remap (native)."""
+    import torch
+    from paper_2606_18400_amd import cloak as C
+    from paper_2606_18400_amd import serve, synth
+    cfg = serve.LLAMA8B
+    shapes = serve.model_shapes(cfg)
+    log("generating weights (one decoder layer's random weights in every layer, distinct placement)")
+    layer_w = [synth.weight(t, s[2], s[3], "bf16")[0] for t, s in enumerate(shapes[:TENSORS_PER_LAYER])]
+    emb = synth.weight(len(shapes) - 2, cfg["vocab"], cfg["d_model"], "bf16")[0]
+    head = synth.weight(len(shapes) - 1, cfg["vocab"], cfg["d_model"], "bf16")[0]
+    weights = [layer_w[t % TENSORS_PER_LAYER] for t in range(len(shapes) - 2)] + [emb, head]
+    rates = [float(r) for r in args.rates.split(",")]
+    results = {}
+    for name, flags, every in [("cloaked", 0, 256), ("native", C.CLOAK_IDENTITY | C.CLOAK_NATIVE, 0)]:
+        log(f"{name}: loading 32 layers into a 16 GiB pool")
+        eng = serve.Engine(cfg, pool_bytes=16 << 30, page_bytes=2 << 20, seed=1, flags=flags, kv_blocks=24576,
+                           max_tokens=2048, prefill_chunk=512, max_seqs=64, split_keys=512, remap_every=every,
+                           weights=weights, max_context=8192)
+        results[name] = {}
+        for rate in rates:
+            trace = synth.poisson_trace(args.requests, rate, 128, 4096, 64, 1024, cfg["vocab"], seed=7)
+            reqs = [serve.Request(t["id"], t["prompt"], t["max_new"], t["arrival"]) for t in trace]
+            steps0, remaps0 = eng.steps, eng.remaps
+            rep = eng.run(reqs)
+            rep["steps"] = eng.steps - steps0
+            rep["remaps"] = eng.remaps - remaps0
+            results[name][str(rate)] = rep
+            log(f"{name} rate {rate}/s: ttft p50 {rep['ttft_ms_p50']:.0f} p99 {rep['ttft_ms_p99']:.0f} ms, "
+                f"tpot p50 {rep['tpot_ms_p50']:.1f} p99 {rep['tpot_ms_p99']:.1f} ms, "
+                f"{rep['output_tok_per_s']:.0f} tok/s, {rep['steps']} steps, {rep['remaps']} remaps")
+        eng.close()
+        torch.cuda.empty_cache()
+    first = str(rates[0])
+    out = {"metric": METRIC, "value": results["cloaked"][first]["output_tok_per_s"], "unit": "tokens/s",
+           "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": f"serving trace on a 32-layer 4096/14336/1024 BF16 stack, vocab 128256, "
+                                  f"{args.requests} requests per rate, Poisson rates {rates} req/s, prompts "
+                                  f"U[128,4096], outputs U[64,1024], remap every 256 steps"},
+           "serving": results}
+    print(json.dumps(out), flush=True)
+
+
+def stack_shapes(cfg):
+    shapes = []
+    for l in range(cfg["n_layers"]):
+        shapes += synth_decoder(cfg, l)
+    shapes.append((-1, "head", cfg["vocab"], cfg["d_model"], "bf16"))
+    return shapes
+
+
+def synth_decoder(cfg, l):
+    from paper_2606_18400_amd import synth
+    return synth.decoder_layer_shapes(cfg["d_model"], cfg["d_ffn"], cfg["d_kv"], "fp8", layer=l)
+
+
+def bench_stack(args):
+    """Decode step through a 64-layer FP8 E4M3 stack (5120/27648/1024, per-row
+    FP32 scales) and its BF16 head (152064 x 5120), 2 MiB pages over 34 GiB."""
+    import torch
+    from paper_2606_18400_amd import cloak as C
+    from paper_2606_18400_amd import synth
+    cfg = synth.STACK5120
+    shapes = stack_shapes(cfg)
+    log("generating and quantising one FP8 layer (reused by all 64 layers, distinct placement) and the head")
+    lw = [synth.weight(t, s[2], s[3], "fp8") for t, s in enumerate(shapes[:TENSORS_PER_LAYER])]
+    head = synth.weight(len(shapes) - 1, cfg["vocab"], cfg["d_model"], "bf16")[0]
+    weights = [lw[t % TENSORS_PER_LAYER][0] for t in range(len(shapes) - 1)] + [head]
+    scales = [lw[t % TENSORS_PER_LAYER][1] for t in range(len(shapes) - 1)] + [None]
+    L = cfg["n_layers"]
+    d, f, kv, V = cfg["d_model"], cfg["d_ffn"], cfg["d_kv"], cfg["vocab"]
+    layer_bytes_fp8 = (d * d * 2 + 2 * kv * d + 3 * f * d) + (d + 2 * kv + d + 3 * f) * 4
+
+    def step_bytes(M):
+        acts = L * 2 * M * (d + (d + 2 * kv) + d + d + d + f + f + d) + 2 * M * (d + V)
+        return L * layer_bytes_fp8 + V * d * 2 + acts
+
+    res = {}
+    for name, flags in [("cloaked", 0), ("native", C.CLOAK_IDENTITY | C.CLOAK_NATIVE)]:
+        log(f"{name}: loading 64 FP8 layers + head into a 34 GiB pool")
+        cw = C.CloakedWeights(shapes, cfg["page_bytes"], cfg["pool_bytes"], seed=1, flags=flags)
+        cw.load(weights, scales)
+        res[name] = {}
+        for M in [int(m) for m in args.stack_batches.split(",")]:
+            x = torch.from_numpy(synth.activations(M, d, "bf16").view(np.int16)).cuda().view(torch.bfloat16)
+            qkv = torch.empty((M, d + 2 * kv), dtype=torch.bfloat16, device="cuda")
+            o = torch.empty((M, d), dtype=torch.bfloat16, device="cuda")
+            h = torch.empty((M, f), dtype=torch.bfloat16, device="cuda")
+            y = torch.empty((M, d), dtype=torch.bfloat16, device="cuda")
+            logits = torch.empty((M, V), dtype=torch.bfloat16, device="cuda")
+            need = max(C.cloak_linear_fused_ws_bytes(cw.layout, [0, 1, 2], M),
+                       C.cloak_ws_bytes(cw.layout, C.CLOAK_OP_SWIGLU, 0, M),
+                       C.cloak_ws_bytes(cw.layout, C.CLOAK_OP_DOWN, 0, M),
+                       C.cloak_ws_bytes(cw.layout, C.CLOAK_OP_LINEAR, len(shapes) - 1, M))
+            ws = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+
+            def one_step():
+                for l in range(L):
+                    t0 = TENSORS_PER_LAYER * l
+                    C.cloak_linear_fused(cw.layout, cw.pool, [t0, t0 + 1, t0 + 2], x, M, qkv, ws, ws.numel())
+                    C.cloak_linear(cw.layout, cw.pool, t0 + 3, x, M, o, ws, ws.numel())
+                    C.cloak_swiglu(cw.layout, cw.pool, l, x, M, h, ws, ws.numel())
+                    C.cloak_down(cw.layout, cw.pool, l, h, M, y, ws, ws.numel())
+                C.cloak_linear(cw.layout, cw.pool, len(shapes) - 1, x, M, logits, ws, ws.numel())
+
+            one_step()
+            torch.cuda.synchronize()
+            reps = max(args.steps // 40, 3)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                one_step()
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            res[name][str(M)] = dict(ms=ms, gbs=step_bytes(M) / ms / 1e6)
+            log(f"{name} M={M}: {ms:.2f} ms/step, {step_bytes(M) / ms / 1e6:.0f} GB/s")
+        cw.close()
+        torch.cuda.empty_cache()
+    for M in res["cloaked"]:
+        res["cloaked"][M]["ratio"] = res["native"][M]["ms"] / res["cloaked"][M]["ms"]
+    m0 = args.stack_batches.split(",")[0]
+    out = {"metric": METRIC, "value": res["cloaked"][m0]["gbs"], "unit": "GB/s", "n_gpus": 1,
+           "ms_per_step": res["cloaked"][m0]["ms"], "higher_is_better": True, "vs_baseline": None, "dtype": "fp8",
+           "data": "synthetic",
+           "config": {"workload": "decode step through a 64-layer FP8 E4M3 5120/27648/1024 stack with per-row FP32 "
+                                  "scales and a BF16 152064x5120 head, 2 MiB pages over a 34 GiB pool",
+                      "step_bytes_M1": step_bytes(1)},
+           "stack": res}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,6 +365,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--remap-reps", type=int, default=5)
     ap.add_argument("--prefill-tokens", type=int, default=8192, help="prefill batch (0 skips the prefill pass)")
+    ap.add_argument("--workload", default="layer", choices=["layer", "serve", "stack"],
+                    help="layer: the headline decode layer (default); serve: serving trace; stack: 64-layer FP8")
+    ap.add_argument("--rates", default="2,8", help="serve: Poisson arrival rates (req/s)")
+    ap.add_argument("--requests", type=int, default=32, help="serve: requests per rate")
+    ap.add_argument("--stack-batches", default="1,8,32,64", help="stack: decode batch sizes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the cloaked layer needs no "
@@ -236,6 +382,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "serve":
+        return bench_serve(args)
+    if args.workload == "stack":
+        return bench_stack(args)
     cfg = synth.LAYER4096
     d, f, kv = cfg["d_model"], cfg["d_ffn"], cfg["d_kv"]
     one = synth.decoder_layer_shapes(d, f, kv, "bf16", layer=0)
@@ -253,8 +403,12 @@ def main():
     step_bytes = sum(layer_bytes(cfg, 1))
     swiglu_bytes = layer_bytes(cfg, 1)[2]
     log(f"timing M=1: {args.warmup} warmup + {args.steps} steps")
-    ms, k_ms = time_steps(cl, 1, args.steps, args.warmup, kernel_events=True)
-    ms_nat, k_ms_nat = time_steps(nat, 1, args.steps, args.warmup, kernel_events=True)
+    ms, _ = time_steps(cl, 1, args.steps, args.warmup)
+    ms_nat, _ = time_steps(nat, 1, args.steps, args.warmup)
+    # the dominant kernel, timed with events around each of its launches in a
+    # second pass of the same steps (so the events do not slow the step timing)
+    _, k_ms = time_steps(cl, 1, args.steps, 2, kernel_events=True)
+    _, k_ms_nat = time_steps(nat, 1, args.steps, 2, kernel_events=True)
     value = step_bytes / ms / 1e6
     native = step_bytes / ms_nat / 1e6
     log(f"M=1 cloaked {value:.0f} GB/s native {native:.0f} GB/s")

@@ -123,8 +123,10 @@ typedef struct {
 #define CLOAK_QUERY_DFFN        14  /* int64: hidden size of layer `index` (0 if no FFN) */
 
 /* Workspace selectors for cloak_ws_bytes(). */
-#define CLOAK_OP_LINEAR 1
-#define CLOAK_OP_MLP    2
+#define CLOAK_OP_LINEAR 1   /* index = tensor */
+#define CLOAK_OP_MLP    2   /* index = layer  */
+#define CLOAK_OP_SWIGLU 3   /* index = layer  */
+#define CLOAK_OP_DOWN   4   /* index = layer  */
 
 /* Draw the layout from `seed` for `n_shapes` tensors (Section 5: all
  * permutations and page placements are fixed before any transfer).  Host
@@ -174,9 +176,15 @@ int cloak_unload(const cloak_layout* layout, const void* d_pool, int32_t tensor,
 int cloak_pack_host(const cloak_layout* layout, int32_t tensor, const void* h_src,
                     void* h_pool, uint64_t h_pool_bytes);
 
-/* Bytes of device workspace `op` needs for `index` (tensor for LINEAR, layer
- * for MLP) at M tokens.  0 if none; UINT64_MAX on bad arguments. */
+/* Bytes of device workspace `op` needs for `index` at M tokens: the FP32
+ * partial sums of the split-K decode GEMM (17..64 tokens) and, for a down
+ * projection called through cloak_linear, its activations gathered through
+ * pi.  0 if none; UINT64_MAX on bad arguments. */
 uint64_t cloak_ws_bytes(const cloak_layout* layout, int32_t op, int32_t index, int64_t M);
+
+/* Workspace of cloak_linear_fused for these n tensors at M tokens. */
+uint64_t cloak_linear_fused_ws_bytes(const cloak_layout* layout, const int32_t* tensors, int32_t n,
+                                     int64_t M);
 
 /* y[M][N] = x[M][K] . W^T for tensor `tensor`, with x and y in LOGICAL
  * order: for gate/up the kernel scatters stored row j to column pi[j]; for
@@ -205,13 +213,14 @@ int cloak_mlp(const cloak_layout* layout, const void* d_pool, int32_t layer, con
  * unit pi[j]); each workgroup reads matching gate and up rows.  h is bf16
  * (f32 for f32 weights). */
 int cloak_swiglu(const cloak_layout* layout, const void* d_pool, int32_t layer, const void* d_x,
-                 int64_t M, void* d_h, void* stream);
+                 int64_t M, void* d_h, void* d_ws, uint64_t ws_bytes, void* stream);
 
 /* Second half of cloak_mlp, one launch: y[M][d_model] = h . Wd^T for h in the
  * permuted hidden order cloak_swiglu produces (down's stored columns carry
- * the same permutation, so nothing is gathered). */
+ * the same permutation, so nothing is gathered).  Workspaces: cloak_ws_bytes
+ * with CLOAK_OP_SWIGLU / CLOAK_OP_DOWN. */
 int cloak_down(const cloak_layout* layout, const void* d_pool, int32_t layer, const void* d_h,
-               int64_t M, void* d_y, void* stream);
+               int64_t M, void* d_y, void* d_ws, uint64_t ws_bytes, void* stream);
 
 /* Re-randomise page placement in place (Section 4.2, periodic remapping
  * with no extra memory footprint): draw the matching tau from remap_seed,

@@ -37,7 +37,7 @@ CLOAK_IDENTITY = 1
 CLOAK_NATIVE = 2
 QUERY = dict(P=1, V=2, T=3, PAGE_BYTES=4, PHI=5, SIGMA=6, PI=7, VBASE=8, NPAGES=9, CONTIGUITY=10,
              UPLOAD_ORDER=11, REMAPS=12, TENSOR=13, DFFN=14)
-CLOAK_OP_LINEAR, CLOAK_OP_MLP = 1, 2
+CLOAK_OP_LINEAR, CLOAK_OP_MLP, CLOAK_OP_SWIGLU, CLOAK_OP_DOWN = 1, 2, 3, 4
 STORAGE = {"f32": np.float32, "bf16": np.uint16, "fp8": np.uint8}
 
 
@@ -81,11 +81,12 @@ _SIGS = {
     "cloak_unload": ([_vp, _vp, _i32, _vp, _vp], _i32),
     "cloak_pack_host": ([_vp, _i32, _vp, _vp, _u64], _i32),
     "cloak_ws_bytes": ([_vp, _i32, _i32, _i64], _u64),
+    "cloak_linear_fused_ws_bytes": ([_vp, ctypes.POINTER(_i32), _i32, _i64], _u64),
     "cloak_linear": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _u64, _vp], _i32),
     "cloak_linear_fused": ([_vp, _vp, ctypes.POINTER(_i32), _i32, _vp, _i64, _vp, _vp, _u64, _vp], _i32),
     "cloak_mlp": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _u64, _vp], _i32),
-    "cloak_swiglu": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp], _i32),
-    "cloak_down": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp], _i32),
+    "cloak_swiglu": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _u64, _vp], _i32),
+    "cloak_down": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _u64, _vp], _i32),
     "cloak_remap": ([_vp, _vp, _u64, _vp], _i32),
     "cloak_remap_host": ([_vp, _vp, _u64, _u64], _i32),
     "cloak_model_create": ([_vp, _vp, ctypes.POINTER(cloak_model_config), _vp, _vp, ctypes.POINTER(_vp)], _i32),
@@ -213,6 +214,14 @@ def cloak_ws_bytes(layout, op, index, M):
     return v
 
 
+def cloak_linear_fused_ws_bytes(layout, tensors, M):
+    arr = (_i32 * len(tensors))(*tensors)
+    v = _lib.cloak_linear_fused_ws_bytes(layout, arr, len(tensors), M)
+    if v == (1 << 64) - 1:
+        raise CloakError(CLOAK_EINVAL, "cloak_linear_fused_ws_bytes", cloak_last_error() or "bad arguments")
+    return v
+
+
 def cloak_linear(layout, pool, tensor, x, M, y, ws=None, ws_bytes=0, stream=None):
     _check(_lib.cloak_linear(layout, _ptr(pool), tensor, _ptr(x), M, _ptr(y), _ptr(ws), ws_bytes,
                              _stream(stream)), "cloak_linear")
@@ -229,12 +238,14 @@ def cloak_mlp(layout, pool, layer, x, M, y, ws, ws_bytes, stream=None):
            "cloak_mlp")
 
 
-def cloak_swiglu(layout, pool, layer, x, M, h, stream=None):
-    _check(_lib.cloak_swiglu(layout, _ptr(pool), layer, _ptr(x), M, _ptr(h), _stream(stream)), "cloak_swiglu")
+def cloak_swiglu(layout, pool, layer, x, M, h, ws=None, ws_bytes=0, stream=None):
+    _check(_lib.cloak_swiglu(layout, _ptr(pool), layer, _ptr(x), M, _ptr(h), _ptr(ws), ws_bytes, _stream(stream)),
+           "cloak_swiglu")
 
 
-def cloak_down(layout, pool, layer, h, M, y, stream=None):
-    _check(_lib.cloak_down(layout, _ptr(pool), layer, _ptr(h), M, _ptr(y), _stream(stream)), "cloak_down")
+def cloak_down(layout, pool, layer, h, M, y, ws=None, ws_bytes=0, stream=None):
+    _check(_lib.cloak_down(layout, _ptr(pool), layer, _ptr(h), M, _ptr(y), _ptr(ws), ws_bytes, _stream(stream)),
+           "cloak_down")
 
 
 def cloak_remap(layout, pool, remap_seed, stream=None):
@@ -326,7 +337,9 @@ class CloakedWeights:
         M = x.shape[0]
         if out is None:
             out = torch.empty((M, n), dtype=x.dtype, device=x.device)
-        cloak_linear_fused(self.layout, self.pool, list(ts), x, M, out)
+        need = cloak_linear_fused_ws_bytes(self.layout, list(ts), M)
+        ws = self.workspace(need) if need else None
+        cloak_linear_fused(self.layout, self.pool, list(ts), x, M, out, ws, 0 if ws is None else ws.numel())
         return out
 
     def mlp(self, layer, x, out=None):

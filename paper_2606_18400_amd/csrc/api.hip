@@ -130,20 +130,6 @@ int run_gemv(const cloak_layout* L, GemvArgs a, int wtype, int64_t M, hipStream_
   return CLOAK_OK;
 }
 
-bool use_gemm(int32_t dtype, int64_t K, int64_t M) {
-  return dtype == CLOAK_BF16 && M >= kGemmMinTokens && K % gemm_k_step() == 0;
-}
-
-void fill_gemm(const cloak_layout* L, const void* pool, GemmArgs& g, int64_t K, int64_t M) {
-  g.pool = static_cast<const uint8_t*>(pool);
-  g.phi = L->dev.phi;
-  g.log2_page = L->log2_page;
-  g.K = int32_t(K);
-  g.row_bytes = K * 2;
-  g.M = int32_t(M);
-  g.tiles_m = int32_t((M + gemm_tile_rows() - 1) / gemm_tile_rows());
-}
-
 void fill_common(const cloak_layout* L, const void* pool, GemvArgs& a, int64_t K, int elt) {
   a.pool = static_cast<const uint8_t*>(pool);
   a.phi = L->dev.phi;
@@ -287,168 +273,227 @@ extern "C" int cloak_unload(const cloak_layout* L, const void* d_pool, int32_t t
   return CLOAK_OK;
 }
 
-extern "C" uint64_t cloak_ws_bytes(const cloak_layout* L, int32_t op, int32_t index, int64_t M) {
-  if (!L || M < 0) return UINT64_MAX;
-  if (op == CLOAK_OP_LINEAR) {
-    if (index < 0 || index >= int32_t(L->tensors.size())) return UINT64_MAX;
-    const TensorInfo& ti = L->tensors[index];
-    // the prefill GEMM reads x in stored column order: a down projection's
-    // activations are gathered through pi into the workspace first
-    if (ti.perm_layer >= 0 && is_col_permuted(ti.shape.kind) && use_gemm(ti.shape.dtype, ti.shape.k_in, M))
-      return (uint64_t(M) * uint64_t(ti.shape.k_in) * 2 + 255) / 256 * 256;
-    return 0;
-  }
-  if (op == CLOAK_OP_MLP) {
-    const FfnPerm* f = L->ffn_of_layer(index);
-    if (!f || f->gate < 0 || f->up < 0 || f->down < 0) return UINT64_MAX;
-    const int hb = L->tensors[f->gate].shape.dtype == CLOAK_F32 ? 4 : 2;
-    const uint64_t b = uint64_t(M) * uint64_t(f->d_ffn) * uint64_t(hb);
-    return (b + 255) / 256 * 256;
-  }
-  return UINT64_MAX;
+namespace {
+
+// Which kernel family serves a projection: the VALU GEMV for small batches
+// (and for f32 / FP8 weights), the skinny split-K MFMA GEMM for 17..64
+// tokens, the 256x256 MFMA GEMM above that.
+enum Path { kPathGemv, kPathSkinny, kPathGemm };
+
+Path pick_path(int32_t dtype, int64_t K, int64_t M) {
+  if (dtype == CLOAK_BF16 && K % gemm_k_step() == 0 && M >= kGemmMinTokens)
+    return M <= kSkinnyMaxTokens ? kPathSkinny : kPathGemm;
+  return kPathGemv;
 }
 
-extern "C" int cloak_linear_fused(const cloak_layout* L, const void* d_pool, const int32_t* tensors, int32_t n,
-                                  const void* d_x, int64_t M, void* d_y, void* d_ws, uint64_t ws_bytes,
-                                  void* stream) {
-  clear_error();
-  (void)d_ws;
-  (void)ws_bytes;
-  if (int rc = check_device_state(L, "cloak_linear")) return rc;
-  if (int rc = check_pool(L, d_pool, "cloak_linear")) return rc;
-  if (!tensors || n < 1 || n > 4 || M < 0 || M > INT32_MAX) {
-    set_error("cloak_linear: need 1..4 tensors and 0 <= M < 2^31");
+struct SplitPlan {
+  int32_t ksplit, kb_per;
+};
+
+// K slices per skinny row tile: about 1024 workgroups in total, but no
+// slice shorter than 8 K steps.
+SplitPlan plan_split(int64_t tiles_n, int64_t K) {
+  const int64_t nk = K / gemm_k_step();
+  int64_t ks = (1024 + tiles_n - 1) / tiles_n;
+  const int64_t cap = nk / 8 > 1 ? nk / 8 : 1;
+  if (ks > cap) ks = cap;
+  if (ks < 1) ks = 1;
+  const int64_t per = (nk + ks - 1) / ks;
+  return {int32_t((nk + per - 1) / per), int32_t(per)};
+}
+
+uint64_t a256(uint64_t b) { return (b + 255) / 256 * 256; }
+
+// One projection launch: up to 4 tensors sharing K (STORE), or a layer's
+// gate/up pair with the SwiGLU epilogue.
+struct Proj {
+  int32_t tensors[4] = {0, 0, 0, 0};
+  int n = 0;
+  int mode = kStore;
+  bool scatter = false;        // gate/up rows written to their logical columns
+  bool gather = false;         // x gathered through pi (down via cloak_linear)
+  const int32_t* x_perm = nullptr;  // that permutation on the device
+  int64_t K = 0;
+  int32_t dtype = CLOAK_BF16;
+  int64_t rows = 0;            // sum of N (STORE) or d_ffn (SwiGLU)
+};
+
+int64_t launch_rows(const cloak_layout* L, const Proj& p, int64_t tile) {
+  if (p.mode == kSwiGLU) return (p.rows + tile / 2 - 1) / (tile / 2) * tile;
+  int64_t r = 0;
+  for (int i = 0; i < p.n; ++i) r += (L->tensors[p.tensors[i]].shape.n_out + tile - 1) / tile * tile;
+  return r;
+}
+
+uint64_t proj_ws_bytes(const cloak_layout* L, const Proj& p, int64_t M) {
+  const Path path = pick_path(p.dtype, p.K, M);
+  uint64_t b = 0;
+  if (p.gather && path != kPathGemv) b += a256(uint64_t(M) * uint64_t(p.K) * 2);
+  if (path == kPathSkinny) {
+    const int64_t lr = launch_rows(L, p, skinny_tile_rows());
+    const SplitPlan sp = plan_split(lr / skinny_tile_rows(), p.K);
+    b += a256(uint64_t(sp.ksplit) * uint64_t(M) * uint64_t(lr) * 4);
+  }
+  return b;
+}
+
+int run_proj(const cloak_layout* L, const void* pool, const Proj& p, const void* x, int64_t ldx, int64_t M, void* y,
+             int64_t ldy, void* ws, uint64_t ws_bytes, hipStream_t st, const char* fn) {
+  const uint64_t need = proj_ws_bytes(L, p, M);
+  if (need > 0 && (!ws || ws_bytes < need)) {
+    set_error("%s: M=%lld needs a workspace of %llu bytes (cloak_ws_bytes)", fn, (long long)M,
+              (unsigned long long)need);
+    return CLOAK_EINVAL;
+  }
+  const int elt = elt_bytes(p.dtype);
+  const Path path = pick_path(p.dtype, p.K, M);
+  if (path == kPathGemv) {
+    GemvArgs a{};
+    fill_common(L, pool, a, p.K, elt);
+    if (p.mode == kSwiGLU) {
+      a.nseg = 2;
+      a.seg[0] = make_seg(L, p.tensors[0], false, 0, 0);
+      a.seg[1] = make_seg(L, p.tensors[1], false, 0, 0);
+      a.seg[2] = a.seg[0];
+      a.seg[3] = a.seg[0];
+      a.groups = int32_t((p.rows + kGemvRows / 2 - 1) / (kGemvRows / 2));
+    } else {
+      // every tensor starts on a whole row group, so a group never mixes tensors
+      int64_t row0 = 0, out_off = 0;
+      for (int i = 0; i < p.n; ++i) {
+        a.seg[i] = make_seg(L, p.tensors[i], p.scatter, int32_t(row0), int32_t(out_off));
+        row0 += (a.seg[i].rows + kGemvRows - 1) / kGemvRows * kGemvRows;
+        out_off += a.seg[i].rows;
+      }
+      for (int i = p.n; i < 4; ++i) a.seg[i] = a.seg[0], a.seg[i].row0 = INT32_MAX;
+      a.nseg = p.n;
+      a.groups = int32_t(row0 / kGemvRows);
+    }
+    a.x = x;
+    a.x_perm = p.x_perm;
+    a.y = y;
+    a.ldx = ldx;
+    a.ldy = ldy;
+    a.mode = p.mode;
+    return run_gemv(L, a, wtype_of(p.dtype), M, st, fn);
+  }
+  // MFMA paths read x in the tensors' stored column order
+  uint8_t* wsb = static_cast<uint8_t*>(ws);
+  const void* xin = x;
+  if (p.gather) {
+    HIP_TRY(launch_gather_cols(static_cast<const uint16_t*>(x), ldx, p.x_perm, reinterpret_cast<uint16_t*>(wsb), M,
+                               p.K, st),
+            fn);
+    xin = wsb;
+    ldx = p.K;
+    wsb += a256(uint64_t(M) * uint64_t(p.K) * 2);
+  }
+  const int64_t tile = path == kPathSkinny ? skinny_tile_rows() : gemm_tile_rows();
+  SkinnyArgs g{};
+  g.pool = static_cast<const uint8_t*>(pool);
+  g.phi = L->dev.phi;
+  g.log2_page = L->log2_page;
+  g.K = int32_t(p.K);
+  g.row_bytes = p.K * 2;
+  g.M = int32_t(M);
+  g.mode = p.mode;
+  g.x = static_cast<const uint16_t*>(xin);
+  g.ldx = ldx;
+  g.y = y;
+  g.ldy = ldy;
+  bool aligned = ldy % 4 == 0 && reinterpret_cast<uintptr_t>(y) % 8 == 0;
+  if (p.mode == kSwiGLU) {
+    g.nseg = 2;
+    g.seg[0] = make_seg(L, p.tensors[0], false, 0, 0);
+    g.seg[1] = make_seg(L, p.tensors[1], false, 0, 0);
+    g.seg[2] = g.seg[0];
+    g.seg[3] = g.seg[0];
+  } else {
+    int64_t row0 = 0, out_off = 0;
+    for (int i = 0; i < p.n; ++i) {
+      g.seg[i] = make_seg(L, p.tensors[i], p.scatter, int32_t(row0), int32_t(out_off));
+      aligned = aligned && out_off % 4 == 0;
+      row0 += (g.seg[i].rows + tile - 1) / tile * tile;
+      out_off += g.seg[i].rows;
+    }
+    for (int i = p.n; i < 4; ++i) g.seg[i] = g.seg[0], g.seg[i].row0 = INT32_MAX;
+    g.nseg = p.n;
+  }
+  const int64_t lr = launch_rows(L, p, tile);
+  if (lr > INT32_MAX) {
+    set_error("%s: too many output rows", fn);
+    return CLOAK_ESHAPE;
+  }
+  g.tiles_n = int32_t(lr / tile);
+  g.tiles_m = int32_t((M + gemm_tile_rows() - 1) / gemm_tile_rows());
+  g.vec_store = aligned ? 1 : 0;
+  if (path == kPathSkinny) {
+    const SplitPlan sp = plan_split(g.tiles_n, p.K);
+    g.part = reinterpret_cast<float*>(wsb);
+    g.ldp = lr;
+    g.ksplit = sp.ksplit;
+    g.kblocks_per_split = sp.kb_per;
+    HIP_TRY(launch_skinny(g, !L->native(), st), fn);
+  } else {
+    GemmArgs ga{};
+    std::memcpy(&ga, &g, sizeof(GemmArgs));
+    HIP_TRY(launch_gemm(ga, !L->native(), st), fn);
+  }
+  return CLOAK_OK;
+}
+
+int linear_proj(const cloak_layout* L, const int32_t* tensors, int32_t n, Proj& p, const char* fn) {
+  if (!tensors || n < 1 || n > 4) {
+    set_error("%s: need 1..4 tensors", fn);
     return CLOAK_EINVAL;
   }
   for (int i = 0; i < n; ++i) {
     if (tensors[i] < 0 || tensors[i] >= int32_t(L->tensors.size())) {
-      set_error("cloak_linear: tensor %d out of range", tensors[i]);
+      set_error("%s: tensor %d out of range", fn, tensors[i]);
       return CLOAK_EINVAL;
     }
   }
   const TensorInfo& t0 = L->tensors[tensors[0]];
-  const int64_t K = t0.shape.k_in;
-  const int32_t dtype = t0.shape.dtype;
-  const int elt = elt_bytes(dtype);
+  p.K = t0.shape.k_in;
+  p.dtype = t0.shape.dtype;
   bool any_down = false;
-  int64_t total = 0;
   for (int i = 0; i < n; ++i) {
     const TensorInfo& ti = L->tensors[tensors[i]];
-    if (ti.shape.k_in != K || ti.shape.dtype != dtype) {
-      set_error("cloak_linear: fused tensors must share K and dtype");
+    if (ti.shape.k_in != p.K || ti.shape.dtype != p.dtype) {
+      set_error("%s: fused tensors must share K and dtype", fn);
       return CLOAK_ESHAPE;
     }
     any_down |= ti.perm_layer >= 0 && is_col_permuted(ti.shape.kind);
-    total += ti.shape.n_out;
+    p.rows += ti.shape.n_out;
+    p.tensors[i] = tensors[i];
   }
+  p.n = n;
+  p.mode = kStore;
+  p.scatter = true;
   if (any_down && n > 1) {
-    set_error("cloak_linear: a down projection (permuted K) cannot be fused with other tensors");
+    set_error("%s: a down projection (permuted K) cannot be fused with other tensors", fn);
     return CLOAK_ESHAPE;
   }
-  if ((K * elt) % 16 != 0) {
-    set_error("cloak_linear: rows must be a multiple of 16 bytes (K*elt = %lld)", (long long)(K * elt));
+  p.gather = any_down;
+  p.x_perm = (any_down && L->dev.perms) ? L->dev.perms + L->ffn[t0.perm_layer].dev_off : nullptr;
+  const int elt = elt_bytes(p.dtype);
+  if ((p.K * elt) % 16 != 0 || (p.K * elt + 1023) / 1024 > 64) {
+    set_error("%s: rows must be a multiple of 16 bytes and at most 64 KiB (K*elt = %lld)", fn,
+              (long long)(p.K * elt));
     return CLOAK_ESHAPE;
   }
-  if ((K * elt + 1023) / 1024 > 64) {
-    set_error("cloak_linear: rows longer than 64 KiB are not supported");
+  if (p.rows > INT32_MAX) {
+    set_error("%s: too many output columns", fn);
     return CLOAK_ESHAPE;
   }
-  if (total > INT32_MAX) {
-    set_error("cloak_linear: too many output columns");
-    return CLOAK_ESHAPE;
-  }
-  if (M == 0) return CLOAK_OK;
-  if (!d_x || !d_y) {
-    set_error("cloak_linear: null x or y");
-    return CLOAK_EINVAL;
-  }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  if (use_gemm(dtype, K, M)) {
-    GemmArgs g{};
-    fill_gemm(L, d_pool, g, K, M);
-    const void* xin = d_x;
-    if (any_down) {
-      const uint64_t need = cloak_ws_bytes(L, CLOAK_OP_LINEAR, tensors[0], M);
-      if (!d_ws || ws_bytes < need) {
-        set_error("cloak_linear: down projection at M=%lld needs a workspace of %llu bytes", (long long)M,
-                  (unsigned long long)need);
-        return CLOAK_EINVAL;
-      }
-      HIP_TRY(launch_gather_cols(static_cast<const uint16_t*>(d_x), K, L->dev.perms + L->ffn[t0.perm_layer].dev_off,
-                                 static_cast<uint16_t*>(d_ws), M, K, st),
-              "cloak_linear(gather)");
-      xin = d_ws;
-    }
-    const int64_t tr = gemm_tile_rows();
-    int64_t row0 = 0, out_off = 0;
-    bool aligned = total % 4 == 0 && reinterpret_cast<uintptr_t>(d_y) % 8 == 0;
-    for (int i = 0; i < n; ++i) {
-      g.seg[i] = make_seg(L, tensors[i], true, int32_t(row0), int32_t(out_off));
-      aligned = aligned && out_off % 4 == 0;
-      row0 += (g.seg[i].rows + tr - 1) / tr * tr;
-      out_off += g.seg[i].rows;
-    }
-    if (row0 > INT32_MAX) {
-      set_error("cloak_linear: too many output rows");
-      return CLOAK_ESHAPE;
-    }
-    for (int i = n; i < 4; ++i) g.seg[i] = g.seg[0], g.seg[i].row0 = INT32_MAX;
-    g.nseg = n;
-    g.mode = kStore;
-    g.tiles_n = int32_t(row0 / tr);
-    g.x = static_cast<const uint16_t*>(xin);
-    g.ldx = K;
-    g.y = d_y;
-    g.ldy = total;
-    g.vec_store = aligned ? 1 : 0;
-    HIP_TRY(launch_gemm(g, !L->native(), st), "cloak_linear(gemm)");
-    return CLOAK_OK;
-  }
-  GemvArgs a{};
-  fill_common(L, d_pool, a, K, elt);
-  a.nseg = n;
-  // every tensor starts on a whole row group (kGemvRows launch-rows), so a
-  // group never mixes tensors; out_off is the tensor's real column offset
-  int64_t row0 = 0, out_off = 0;
-  for (int i = 0; i < n; ++i) {
-    a.seg[i] = make_seg(L, tensors[i], true, int32_t(row0), int32_t(out_off));
-    row0 += (a.seg[i].rows + kGemvRows - 1) / kGemvRows * kGemvRows;
-    out_off += a.seg[i].rows;
-  }
-  if (row0 > INT32_MAX) {
-    set_error("cloak_linear: too many output rows");
-    return CLOAK_ESHAPE;
-  }
-  for (int i = n; i < 4; ++i) a.seg[i] = a.seg[0], a.seg[i].row0 = INT32_MAX;
-  a.groups = int32_t(row0 / kGemvRows);
-  a.x = d_x;
-  a.x_perm = any_down ? L->dev.perms + L->ffn[t0.perm_layer].dev_off : nullptr;
-  a.y = d_y;
-  a.ldx = K;
-  a.ldy = total;
-  a.mode = kStore;
-  return run_gemv(L, a, wtype_of(dtype), M, st, "cloak_linear");
+  return CLOAK_OK;
 }
 
-extern "C" int cloak_linear(const cloak_layout* L, const void* d_pool, int32_t tensor, const void* d_x, int64_t M,
-                            void* d_y, void* d_ws, uint64_t ws_bytes, void* stream) {
-  return cloak_linear_fused(L, d_pool, &tensor, 1, d_x, M, d_y, d_ws, ws_bytes, stream);
-}
-
-namespace {
-
-// Shared checks of the FFN entry points; fills the three tensors.
-int ffn_tensors(const cloak_layout* L, const void* d_pool, int32_t layer, int64_t M, const char* fn,
-                const FfnPerm** out) {
-  if (int rc = check_device_state(L, fn)) return rc;
-  if (int rc = check_pool(L, d_pool, fn)) return rc;
+// Gate/up (SwiGLU) or down projection of one layer.
+int ffn_proj(const cloak_layout* L, int32_t layer, bool swiglu, Proj& p, int64_t& dm, int64_t& dff, const char* fn) {
   const FfnPerm* f = L->ffn_of_layer(layer);
   if (!f || f->gate < 0 || f->up < 0 || f->down < 0) {
     set_error("%s: layer %d lacks gate, up or down", fn, layer);
-    return CLOAK_EINVAL;
-  }
-  if (M < 0 || M > INT32_MAX) {
-    set_error("%s: bad M", fn);
     return CLOAK_EINVAL;
   }
   const TensorInfo& tg = L->tensors[f->gate];
@@ -461,130 +506,148 @@ int ffn_tensors(const cloak_layout* L, const void* d_pool, int32_t layer, int64_
     return CLOAK_ESHAPE;
   }
   const int elt = elt_bytes(dtype);
-  const int64_t dm = tg.shape.k_in, dff = f->d_ffn;
+  dm = tg.shape.k_in;
+  dff = f->d_ffn;
   if ((dm * elt) % 16 != 0 || (dff * elt) % 16 != 0 || (dff * elt + 1023) / 1024 > 64 ||
       (dm * elt + 1023) / 1024 > 64) {
     set_error("%s: rows must be multiples of 16 bytes and at most 64 KiB", fn);
     return CLOAK_ESHAPE;
   }
-  *out = f;
+  p.dtype = dtype;
+  if (swiglu) {
+    p.tensors[0] = f->gate;
+    p.tensors[1] = f->up;
+    p.n = 2;
+    p.mode = kSwiGLU;
+    p.K = dm;
+    p.rows = dff;
+  } else {
+    // down's stored columns carry the same permutation as h: no gather
+    p.tensors[0] = f->down;
+    p.n = 1;
+    p.mode = kStore;
+    p.K = dff;
+    p.rows = dm;
+  }
   return CLOAK_OK;
 }
 
 }  // namespace
 
-extern "C" int cloak_swiglu(const cloak_layout* L, const void* d_pool, int32_t layer, const void* d_x, int64_t M,
-                            void* d_h, void* stream) {
+namespace cloak {
+uint64_t linear_fused_ws_bytes(const cloak_layout* L, const int32_t* tensors, int32_t n, int64_t M) {
+  Proj p;
+  if (!L || M < 0 || linear_proj(L, tensors, n, p, "cloak_ws_bytes")) return UINT64_MAX;
+  return proj_ws_bytes(L, p, M);
+}
+}  // namespace cloak
+
+extern "C" uint64_t cloak_linear_fused_ws_bytes(const cloak_layout* L, const int32_t* tensors, int32_t n,
+                                                int64_t M) {
+  return linear_fused_ws_bytes(L, tensors, n, M);
+}
+
+extern "C" uint64_t cloak_ws_bytes(const cloak_layout* L, int32_t op, int32_t index, int64_t M) {
+  if (!L || M < 0) return UINT64_MAX;
+  if (op == CLOAK_OP_LINEAR) return linear_fused_ws_bytes(L, &index, 1, M);
+  Proj p;
+  int64_t dm = 0, dff = 0;
+  if (op == CLOAK_OP_SWIGLU || op == CLOAK_OP_DOWN) {
+    if (ffn_proj(L, index, op == CLOAK_OP_SWIGLU, p, dm, dff, "cloak_ws_bytes")) return UINT64_MAX;
+    return proj_ws_bytes(L, p, M);
+  }
+  if (op == CLOAK_OP_MLP) {
+    Proj d;
+    if (ffn_proj(L, index, true, p, dm, dff, "cloak_ws_bytes") || ffn_proj(L, index, false, d, dm, dff, "cloak_ws_bytes"))
+      return UINT64_MAX;
+    const int hb = p.dtype == CLOAK_F32 ? 4 : 2;
+    const uint64_t a = proj_ws_bytes(L, p, M), b = proj_ws_bytes(L, d, M);
+    return a256(uint64_t(M) * uint64_t(dff) * uint64_t(hb)) + (a > b ? a : b);
+  }
+  return UINT64_MAX;
+}
+
+extern "C" int cloak_linear_fused(const cloak_layout* L, const void* d_pool, const int32_t* tensors, int32_t n,
+                                  const void* d_x, int64_t M, void* d_y, void* d_ws, uint64_t ws_bytes,
+                                  void* stream) {
   clear_error();
-  const FfnPerm* f = nullptr;
-  if (int rc = ffn_tensors(L, d_pool, layer, M, "cloak_swiglu", &f)) return rc;
-  if (M == 0) return CLOAK_OK;
-  if (!d_x || !d_h) {
-    set_error("cloak_swiglu: null x or h");
+  if (int rc = check_device_state(L, "cloak_linear")) return rc;
+  if (int rc = check_pool(L, d_pool, "cloak_linear")) return rc;
+  if (M < 0 || M > INT32_MAX) {
+    set_error("cloak_linear: bad M");
     return CLOAK_EINVAL;
   }
-  const TensorInfo& tg = L->tensors[f->gate];
-  const int32_t dtype = tg.shape.dtype;
-  const int elt = elt_bytes(dtype);
-  const int64_t dm = tg.shape.k_in, dff = f->d_ffn;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  if (use_gemm(dtype, dm, M)) {
-    GemmArgs g{};
-    fill_gemm(L, d_pool, g, dm, M);
-    g.nseg = 2;
-    g.seg[0] = make_seg(L, f->gate, false, 0, 0);
-    g.seg[1] = make_seg(L, f->up, false, 0, 0);
-    g.seg[2] = g.seg[0];
-    g.seg[3] = g.seg[0];
-    g.mode = kSwiGLU;
-    g.tiles_n = int32_t((dff + gemm_tile_rows() / 2 - 1) / (gemm_tile_rows() / 2));
-    g.x = static_cast<const uint16_t*>(d_x);
-    g.ldx = dm;
-    g.y = d_h;
-    g.ldy = dff;
-    g.vec_store = (dff % 4 == 0 && reinterpret_cast<uintptr_t>(d_h) % 8 == 0) ? 1 : 0;
-    HIP_TRY(launch_gemm(g, !L->native(), st), "cloak_swiglu(gemm)");
-    return CLOAK_OK;
+  Proj p;
+  if (int rc = linear_proj(L, tensors, n, p, "cloak_linear")) return rc;
+  if (M == 0) return CLOAK_OK;
+  if (!d_x || !d_y) {
+    set_error("cloak_linear: null x or y");
+    return CLOAK_EINVAL;
   }
-  // gate + up row pairs in one launch, SwiGLU epilogue -> h in permuted order
-  GemvArgs a{};
-  fill_common(L, d_pool, a, dm, elt);
-  a.nseg = 2;
-  a.seg[0] = make_seg(L, f->gate, false, 0, 0);
-  a.seg[1] = make_seg(L, f->up, false, 0, 0);
-  a.seg[2] = a.seg[0];
-  a.seg[3] = a.seg[0];
-  a.groups = int32_t((dff + kGemvRows / 2 - 1) / (kGemvRows / 2));
-  a.x = d_x;
-  a.x_perm = nullptr;
-  a.y = d_h;
-  a.ldx = dm;
-  a.ldy = dff;
-  a.mode = kSwiGLU;
-  return run_gemv(L, a, wtype_of(dtype), M, st, "cloak_swiglu");
+  return run_proj(L, d_pool, p, d_x, p.K, M, d_y, p.rows, d_ws, ws_bytes, static_cast<hipStream_t>(stream),
+                  "cloak_linear");
+}
+
+extern "C" int cloak_linear(const cloak_layout* L, const void* d_pool, int32_t tensor, const void* d_x, int64_t M,
+                            void* d_y, void* d_ws, uint64_t ws_bytes, void* stream) {
+  return cloak_linear_fused(L, d_pool, &tensor, 1, d_x, M, d_y, d_ws, ws_bytes, stream);
+}
+
+namespace {
+int ffn_call(const cloak_layout* L, const void* d_pool, int32_t layer, bool swiglu, const void* d_in, int64_t M,
+             void* d_out, void* d_ws, uint64_t ws_bytes, void* stream, const char* fn) {
+  clear_error();
+  if (int rc = check_device_state(L, fn)) return rc;
+  if (int rc = check_pool(L, d_pool, fn)) return rc;
+  if (M < 0 || M > INT32_MAX) {
+    set_error("%s: bad M", fn);
+    return CLOAK_EINVAL;
+  }
+  Proj p;
+  int64_t dm = 0, dff = 0;
+  if (int rc = ffn_proj(L, layer, swiglu, p, dm, dff, fn)) return rc;
+  if (M == 0) return CLOAK_OK;
+  if (!d_in || !d_out) {
+    set_error("%s: null input or output", fn);
+    return CLOAK_EINVAL;
+  }
+  const int64_t ldx = swiglu ? dm : dff, ldy = swiglu ? dff : dm;
+  return run_proj(L, d_pool, p, d_in, ldx, M, d_out, ldy, d_ws, ws_bytes, static_cast<hipStream_t>(stream), fn);
+}
+}  // namespace
+
+extern "C" int cloak_swiglu(const cloak_layout* L, const void* d_pool, int32_t layer, const void* d_x, int64_t M,
+                            void* d_h, void* d_ws, uint64_t ws_bytes, void* stream) {
+  return ffn_call(L, d_pool, layer, true, d_x, M, d_h, d_ws, ws_bytes, stream, "cloak_swiglu");
 }
 
 extern "C" int cloak_down(const cloak_layout* L, const void* d_pool, int32_t layer, const void* d_h, int64_t M,
-                          void* d_y, void* stream) {
-  clear_error();
-  const FfnPerm* f = nullptr;
-  if (int rc = ffn_tensors(L, d_pool, layer, M, "cloak_down", &f)) return rc;
-  if (M == 0) return CLOAK_OK;
-  if (!d_h || !d_y) {
-    set_error("cloak_down: null h or y");
-    return CLOAK_EINVAL;
-  }
-  const TensorInfo& tg = L->tensors[f->gate];
-  const int32_t dtype = tg.shape.dtype;
-  const int elt = elt_bytes(dtype);
-  const int64_t dm = tg.shape.k_in, dff = f->d_ffn;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  if (use_gemm(dtype, dff, M)) {
-    // down's stored columns are permuted exactly like h: no gather needed
-    GemmArgs g{};
-    fill_gemm(L, d_pool, g, dff, M);
-    g.nseg = 1;
-    g.seg[0] = make_seg(L, f->down, false, 0, 0);
-    for (int i = 1; i < 4; ++i) g.seg[i] = g.seg[0], g.seg[i].row0 = INT32_MAX;
-    g.mode = kStore;
-    g.tiles_n = int32_t((dm + gemm_tile_rows() - 1) / gemm_tile_rows());
-    g.x = static_cast<const uint16_t*>(d_h);
-    g.ldx = dff;
-    g.y = d_y;
-    g.ldy = dm;
-    g.vec_store = (dm % 4 == 0 && reinterpret_cast<uintptr_t>(d_y) % 8 == 0) ? 1 : 0;
-    HIP_TRY(launch_gemm(g, !L->native(), st), "cloak_down(gemm)");
-    return CLOAK_OK;
-  }
-  // down's stored columns are permuted exactly like h: no gather needed
-  GemvArgs b{};
-  fill_common(L, d_pool, b, dff, elt);
-  b.nseg = 1;
-  b.seg[0] = make_seg(L, f->down, false, 0, 0);
-  for (int i = 1; i < 4; ++i) b.seg[i] = b.seg[0], b.seg[i].row0 = INT32_MAX;
-  b.groups = int32_t((dm + kGemvRows - 1) / kGemvRows);
-  b.x = d_h;
-  b.x_perm = nullptr;
-  b.y = d_y;
-  b.ldx = dff;
-  b.ldy = dm;
-  b.mode = kStore;
-  return run_gemv(L, b, wtype_of(dtype), M, st, "cloak_down");
+                          void* d_y, void* d_ws, uint64_t ws_bytes, void* stream) {
+  return ffn_call(L, d_pool, layer, false, d_h, M, d_y, d_ws, ws_bytes, stream, "cloak_down");
 }
 
 extern "C" int cloak_mlp(const cloak_layout* L, const void* d_pool, int32_t layer, const void* d_x, int64_t M,
                          void* d_y, void* d_ws, uint64_t ws_bytes, void* stream) {
   clear_error();
-  const FfnPerm* f = nullptr;
-  if (int rc = ffn_tensors(L, d_pool, layer, M, "cloak_mlp", &f)) return rc;
+  if (int rc = check_device_state(L, "cloak_mlp")) return rc;
+  Proj p;
+  int64_t dm = 0, dff = 0;
+  if (int rc = ffn_proj(L, layer, true, p, dm, dff, "cloak_mlp")) return rc;
+  if (M < 0 || M > INT32_MAX) {
+    set_error("cloak_mlp: bad M");
+    return CLOAK_EINVAL;
+  }
   if (M == 0) return CLOAK_OK;
   const uint64_t need = cloak_ws_bytes(L, CLOAK_OP_MLP, layer, M);
   if (!d_x || !d_y || !d_ws || ws_bytes < need) {
     set_error("cloak_mlp: null x/y/workspace or workspace below %llu bytes", (unsigned long long)need);
     return CLOAK_EINVAL;
   }
-  if (int rc = cloak_swiglu(L, d_pool, layer, d_x, M, d_ws, stream)) return rc;
-  return cloak_down(L, d_pool, layer, d_ws, M, d_y, stream);
+  const int hb = p.dtype == CLOAK_F32 ? 4 : 2;
+  const uint64_t hbytes = a256(uint64_t(M) * uint64_t(dff) * uint64_t(hb));
+  uint8_t* scratch = static_cast<uint8_t*>(d_ws) + hbytes;
+  if (int rc = cloak_swiglu(L, d_pool, layer, d_x, M, d_ws, scratch, ws_bytes - hbytes, stream)) return rc;
+  return cloak_down(L, d_pool, layer, d_ws, M, d_y, scratch, ws_bytes - hbytes, stream);
 }
 
 extern "C" int cloak_remap(cloak_layout* L, void* d_pool, uint64_t remap_seed, void* stream) {

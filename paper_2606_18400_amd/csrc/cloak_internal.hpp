@@ -90,4 +90,6 @@ void unstream_page(const cloak_layout* L, int32_t t, const uint8_t* page_bytes, 
 std::vector<int32_t> upload_order(const cloak_layout* L, int32_t t);
 std::vector<int32_t> remap_matching(uint64_t remap_seed, int64_t P);
 double contiguity(const cloak_layout* L);
+// workspace of cloak_linear_fused for these tensors at M tokens (UINT64_MAX on bad arguments)
+uint64_t linear_fused_ws_bytes(const cloak_layout* L, const int32_t* tensors, int32_t n, int64_t M);
 }  // namespace cloak

@@ -65,15 +65,15 @@ struct RowRef {
 };
 
 template <bool TR>
-__device__ inline const uint8_t* row_addr(const GemmArgs& a, RowRef& r, int64_t koff) {
+__device__ inline const uint8_t* row_addr(const int32_t* phi, int log2_page, RowRef& r, int64_t koff) {
   const int64_t o = r.rowoff + koff;
-  const int64_t vp = o >> a.log2_page;
+  const int64_t vp = o >> log2_page;
   if (vp != r.cvp) {
     r.cvp = vp;
     const int64_t v = r.vbase + vp;
-    r.cbase = (TR ? int64_t(a.phi[v]) : v) << a.log2_page;
+    r.cbase = (TR ? int64_t(phi[v]) : v) << log2_page;
   }
-  return r.pool + r.cbase + (o & ((int64_t(1) << a.log2_page) - 1));
+  return r.pool + r.cbase + (o & ((int64_t(1) << log2_page) - 1));
 }
 
 template <int EPI>
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(NTHREADS, 1) void gemm_kernel(const GemmArgs a) {
 #pragma unroll
     for (int i = 0; i < LOADS; ++i) {
       gx[i] = xok[i] ? *reinterpret_cast<const u32x4*>(xrow[i] + kb * BK) : u32x4{0u, 0u, 0u, 0u};
-      gw[i] = wr[i].ok ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(row_addr<TR>(a, wr[i], koff)))
+      gw[i] = wr[i].ok ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(row_addr<TR>(a.phi, a.log2_page, wr[i], koff)))
                        : u32x4{0u, 0u, 0u, 0u};
     }
   };
@@ -287,6 +287,159 @@ __global__ __launch_bounds__(256) void gather_cols_kernel(const uint16_t* __rest
   }
 }
 
+// ---------------------------------------------------------------------------
+// Skinny split-K GEMM for decode batches (17..64 tokens).  A 256-row tile
+// leaves a 4096-row projection only 16 workgroups; here a workgroup of 4
+// waves takes 64 weight rows x 64 tokens x one K slice (SBK = 64 per step,
+// 32 KiB of LDS, so several workgroups share a CU), and the K slices of a
+// row tile are spread over workgroups.  Each slice writes FP32 partial sums
+// part[slice][token][launch-row]; skinny_reduce_kernel adds the slices in a
+// fixed order (deterministic) and applies the epilogue.  SwiGLU tiles hold
+// 32 gate rows and the same 32 up rows.
+constexpr int SBM = 64, SBN = 64, SBK = 64, STHREADS = 256;
+constexpr int S_TILE = SBM * ROWB;                     // 8 KiB per operand tile
+constexpr int S_LOADS = SBM * (ROWB / 16) / STHREADS;  // 2
+
+template <int EPI>
+__device__ inline bool skinny_row(const SkinnyArgs& a, int tile_n, int tr, int& seg, int& n) {
+  if (EPI == kSwiGLU) {
+    seg = tr < SBN / 2 ? 0 : 1;
+    n = tile_n * (SBN / 2) + (tr % (SBN / 2));
+    return n < a.seg[0].rows;
+  }
+  const int row = tile_n * SBN + tr;
+  seg = 0;
+#pragma unroll
+  for (int i = 1; i < 4; ++i)
+    if (i < a.nseg && row >= a.seg[i].row0) seg = i;
+  n = row - a.seg[seg].row0;
+  return n < a.seg[seg].rows;
+}
+
+template <bool TR, int EPI>
+__global__ __launch_bounds__(STHREADS) void skinny_kernel(const SkinnyArgs a) {
+  __shared__ __attribute__((aligned(16))) uint8_t smem[4 * S_TILE];
+  auto lds_x = [&](int buf) { return smem + buf * 2 * S_TILE; };
+  auto lds_w = [&](int buf) { return smem + buf * 2 * S_TILE + S_TILE; };
+  const int ks = blockIdx.x % a.ksplit;
+  const int tile_n = blockIdx.x / a.ksplit;
+  const int kb_begin = ks * a.kblocks_per_split;
+  int kb_end = kb_begin + a.kblocks_per_split;
+  if (kb_end > a.K / SBK) kb_end = a.K / SBK;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int ch = tid & 7;
+
+  const uint16_t* xrow[S_LOADS];
+  bool xok[S_LOADS];
+  RowRef wr[S_LOADS];
+#pragma unroll
+  for (int i = 0; i < S_LOADS; ++i) {
+    const int tr = (tid >> 3) + 32 * i;
+    xok[i] = tr < a.M;
+    xrow[i] = a.x + int64_t(xok[i] ? tr : 0) * a.ldx + ch * 8;
+    int seg, n;
+    wr[i].ok = skinny_row<EPI>(a, tile_n, tr, seg, n);
+    wr[i].pool = a.pool;
+    wr[i].vbase = a.seg[seg].vbase;
+    wr[i].rowoff = int64_t(wr[i].ok ? n : 0) * a.row_bytes + ch * 16;
+    wr[i].cvp = -1;
+    wr[i].cbase = 0;
+  }
+  u32x4 gx[S_LOADS], gw[S_LOADS];
+  auto gload = [&](int kb) {
+    const int64_t koff = int64_t(kb) * ROWB;
+#pragma unroll
+    for (int i = 0; i < S_LOADS; ++i) {
+      gx[i] = xok[i] ? *reinterpret_cast<const u32x4*>(xrow[i] + kb * SBK) : u32x4{0u, 0u, 0u, 0u};
+      gw[i] = wr[i].ok ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(row_addr<TR>(a.phi, a.log2_page, wr[i], koff)))
+                       : u32x4{0u, 0u, 0u, 0u};
+    }
+  };
+  auto swrite = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < S_LOADS; ++i) {
+      const int tr = (tid >> 3) + 32 * i;
+      *reinterpret_cast<u32x4*>(lds_x(buf) + swz(tr, ch)) = gx[i];
+      *reinterpret_cast<u32x4*>(lds_w(buf) + swz(tr, ch)) = gw[i];
+    }
+  };
+  f32x4 acc[SBM / 16];
+#pragma unroll
+  for (int j = 0; j < SBM / 16; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int wrow = wave * 16;
+  if (kb_begin < kb_end) {
+    gload(kb_begin);
+    swrite(0);
+  }
+  __syncthreads();
+  for (int kb = kb_begin; kb < kb_end; ++kb) {
+    const int buf = (kb - kb_begin) & 1;
+    if (kb + 1 < kb_end) gload(kb + 1);
+#pragma unroll
+    for (int s = 0; s < SBK / 32; ++s) {
+      const int chunk = s * 4 + (lane >> 4);
+      const bf16x8_t fa = *reinterpret_cast<const bf16x8_t*>(lds_w(buf) + swz(wrow + (lane & 15), chunk));
+#pragma unroll
+      for (int mb = 0; mb < SBM / 16; ++mb) {
+        const bf16x8_t fb = *reinterpret_cast<const bf16x8_t*>(lds_x(buf) + swz(mb * 16 + (lane & 15), chunk));
+        acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[mb], 0, 0, 0);
+      }
+    }
+    if (kb + 1 < kb_end) swrite(buf ^ 1);
+    __syncthreads();
+  }
+  // partial sums: lane holds launch-rows wrow + 4*(lane/16) + r of token mb*16 + lane%16
+  const int row0 = tile_n * SBN + wrow + 4 * (lane >> 4);
+#pragma unroll
+  for (int mb = 0; mb < SBM / 16; ++mb) {
+    const int m = mb * 16 + (lane & 15);
+    if (m >= a.M) continue;
+    float* dst = a.part + (int64_t(ks) * a.M + m) * a.ldp + row0;
+    *reinterpret_cast<f32x4*>(dst) = acc[mb];
+  }
+}
+
+// Sum of the K slices in slice order, then the epilogue.  STORE: one thread
+// per (token, launch-row); SwiGLU: one thread per (token, hidden unit).
+template <int EPI>
+__global__ __launch_bounds__(256) void skinny_reduce_kernel(const SkinnyArgs a) {
+  const int64_t per_tok = EPI == kSwiGLU ? int64_t(a.seg[0].rows) : int64_t(a.ldp);
+  const int64_t total = int64_t(a.M) * per_tok;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
+    const int m = int(i / per_tok);
+    const int c = int(i % per_tok);
+    if constexpr (EPI == kSwiGLU) {
+      const int tile = c / (SBN / 2), j = c % (SBN / 2);
+      const int rg = tile * SBN + j, ru = rg + SBN / 2;
+      float g = 0.f, u = 0.f;
+      for (int ks = 0; ks < a.ksplit; ++ks) {
+        const float* p = a.part + (int64_t(ks) * a.M + m) * a.ldp;
+        g += p[rg];
+        u += p[ru];
+      }
+      if (a.seg[0].scale) g *= a.seg[0].scale[c];
+      if (a.seg[1].scale) u *= a.seg[1].scale[c];
+      static_cast<uint16_t*>(a.y)[int64_t(m) * a.ldy + c] = f32_to_bf16_rne(g / (1.0f + expf(-g)) * u);
+    } else {
+      int seg = 0;
+#pragma unroll
+      for (int k = 1; k < 4; ++k)
+        if (k < a.nseg && c >= a.seg[k].row0) seg = k;
+      const int n = c - a.seg[seg].row0;
+      if (n >= a.seg[seg].rows) continue;
+      float v = 0.f;
+      for (int ks = 0; ks < a.ksplit; ++ks) v += a.part[(int64_t(ks) * a.M + m) * a.ldp + c];
+      if (a.seg[seg].scale) v *= a.seg[seg].scale[n];
+      const int32_t* perm = a.seg[seg].out_perm;
+      static_cast<uint16_t*>(a.y)[int64_t(m) * a.ldy + a.seg[seg].out_off + (perm ? perm[n] : n)] =
+          f32_to_bf16_rne(v);
+    }
+  }
+}
+
 }  // namespace
 
 int gemm_lds_bytes() { return 4 * TILE_BYTES; }
@@ -312,6 +465,30 @@ hipError_t launch_gemm(const GemmArgs& a, bool translate, hipStream_t s) {
     attr_set[key] = true;
   }
   hipLaunchKernelGGL(fn, dim3(blocks), dim3(NTHREADS), lds, s, a);
+  return hipGetLastError();
+}
+
+int skinny_tile_rows() { return SBN; }
+
+hipError_t launch_skinny(const SkinnyArgs& a, bool translate, hipStream_t s) {
+  const int64_t blocks = int64_t(a.tiles_n) * a.ksplit;
+  if (blocks <= 0 || a.M <= 0) return hipSuccess;
+  if (a.M > SBM || a.K % SBK != 0) return hipErrorInvalidValue;
+  void (*fn)(const SkinnyArgs);
+  if (a.mode == kSwiGLU)
+    fn = translate ? skinny_kernel<true, kSwiGLU> : skinny_kernel<false, kSwiGLU>;
+  else
+    fn = translate ? skinny_kernel<true, kStore> : skinny_kernel<false, kStore>;
+  hipLaunchKernelGGL(fn, dim3(unsigned(blocks)), dim3(STHREADS), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t per_tok = a.mode == kSwiGLU ? int64_t(a.seg[0].rows) : int64_t(a.ldp);
+  int64_t rb = (int64_t(a.M) * per_tok + 255) / 256;
+  if (rb > 8192) rb = 8192;
+  if (a.mode == kSwiGLU)
+    hipLaunchKernelGGL(skinny_reduce_kernel<kSwiGLU>, dim3(unsigned(rb)), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(skinny_reduce_kernel<kStore>, dim3(unsigned(rb)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

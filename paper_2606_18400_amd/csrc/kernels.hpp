@@ -72,6 +72,34 @@ struct GemmArgs {
   int32_t vec_store;        // 1 if 8-byte output stores are aligned
 };
 hipError_t launch_gemm(const GemmArgs& a, bool translate, hipStream_t s);
+
+// Skinny split-K GEMM for 17..64 tokens (same fields as GemmArgs, plus the
+// split-K partial-sum buffer).
+struct SkinnyArgs {
+  const uint8_t* pool;
+  const int32_t* phi;
+  int32_t log2_page;
+  int32_t K;
+  int64_t row_bytes;
+  int32_t nseg;
+  int32_t mode;
+  WSeg seg[4];
+  const uint16_t* x;
+  int64_t ldx;
+  void* y;
+  int64_t ldy;
+  int32_t M;
+  int32_t tiles_m, tiles_n;
+  int32_t vec_store;
+  // split-K
+  float* part;              // [ksplit][M][ldp] FP32 partial sums (workspace)
+  int64_t ldp;              // launch-rows (tiles_n * skinny_tile_rows())
+  int32_t ksplit;
+  int32_t kblocks_per_split;
+};
+hipError_t launch_skinny(const SkinnyArgs& a, bool translate, hipStream_t s);
+int skinny_tile_rows();
+constexpr int64_t kSkinnyMaxTokens = 64;
 hipError_t launch_gather_cols(const uint16_t* x, int64_t ldx, const int32_t* perm, uint16_t* out, int64_t M,
                               int64_t K, hipStream_t s);
 int gemm_tile_rows();

@@ -42,10 +42,13 @@ const int32_t kKinds[kPerLayer] = {CLOAK_Q, CLOAK_K, CLOAK_V, CLOAK_O, CLOAK_GAT
 uint64_t align256(uint64_t b) { return (b + 255) / 256 * 256; }
 
 struct WsPlan {
-  uint64_t r, h, qkv, attn, o, f, y, hsel, logits, part_o, part_ml, total;
+  uint64_t r, h, qkv, attn, o, f, y, hsel, logits, part_o, part_ml, scratch, scratch_bytes, total;
 };
 
-WsPlan plan_ws(const cloak_model_config& c, int64_t T, int64_t R, int64_t tiles, int64_t splits) {
+uint64_t umax(uint64_t a, uint64_t b) { return a > b ? a : b; }
+
+WsPlan plan_ws(const cloak_model* m, int64_t T, int64_t R, int64_t tiles, int64_t splits) {
+  const cloak_model_config& c = m->cfg;
   const int64_t D = c.d_model, KVD = int64_t(c.n_kv_heads) * c.head_dim;
   WsPlan p{};
   uint64_t off = 0;
@@ -65,6 +68,15 @@ WsPlan plan_ws(const cloak_model_config& c, int64_t T, int64_t R, int64_t tiles,
   p.logits = take(uint64_t(R > 0 ? R : 1) * c.vocab * 2);
   p.part_o = take(uint64_t(tiles) * splits * c.n_heads * 16 * 128 * 4);
   p.part_ml = take(uint64_t(tiles) * splits * c.n_heads * 16 * 2 * 4);
+  // scratch of the projections (split-K partial sums); all layers share shapes
+  const int32_t* t = m->t.data();
+  uint64_t sc = linear_fused_ws_bytes(m->L, t, 3, T);
+  sc = umax(sc, linear_fused_ws_bytes(m->L, t + 3, 1, T));
+  sc = umax(sc, cloak_ws_bytes(m->L, CLOAK_OP_SWIGLU, 0, T));
+  sc = umax(sc, cloak_ws_bytes(m->L, CLOAK_OP_DOWN, 0, T));
+  sc = umax(sc, linear_fused_ws_bytes(m->L, &m->head, 1, R));
+  p.scratch_bytes = align256(sc);
+  p.scratch = take(p.scratch_bytes);
   p.total = off;
   return p;
 }
@@ -140,7 +152,7 @@ extern "C" int cloak_model_free(cloak_model* m) {
 extern "C" uint64_t cloak_model_ws_bytes(const cloak_model* m, int64_t max_tokens, int64_t max_logits,
                                          int64_t max_tiles, int64_t max_splits) {
   if (!m || max_tokens < 0 || max_logits < 0 || max_tiles < 0 || max_splits < 0) return UINT64_MAX;
-  return plan_ws(m->cfg, max_tokens, max_logits, max_tiles, max_splits).total;
+  return plan_ws(m, max_tokens, max_logits, max_tiles, max_splits).total;
 }
 
 extern "C" int cloak_model_step(cloak_model* m, const cloak_step* s, void* d_ws, uint64_t ws_bytes, void* stream) {
@@ -157,7 +169,7 @@ extern "C" int cloak_model_step(cloak_model* m, const cloak_step* s, void* d_ws,
     set_error("cloak_model_step: bad batch description");
     return CLOAK_EINVAL;
   }
-  const WsPlan p = plan_ws(c, T, R, s->n_tiles, s->n_splits);
+  const WsPlan p = plan_ws(m, T, R, s->n_tiles, s->n_splits);
   if (ws_bytes < p.total) {
     set_error("cloak_model_step: workspace of %llu bytes, step needs %llu", (unsigned long long)ws_bytes,
               (unsigned long long)p.total);
@@ -170,6 +182,8 @@ extern "C" int cloak_model_step(cloak_model* m, const cloak_step* s, void* d_ws,
   uint16_t *r = bf(p.r), *h = bf(p.h), *qkv = bf(p.qkv), *attn = bf(p.attn), *o = bf(p.o), *f = bf(p.f),
            *y = bf(p.y), *hsel = bf(p.hsel);
   uint16_t* logits = s->d_out_logits ? static_cast<uint16_t*>(s->d_out_logits) : bf(p.logits);
+  void* scratch = base + p.scratch;
+  const uint64_t sb = p.scratch_bytes;
   const int64_t D = c.d_model, KVD = int64_t(c.n_kv_heads) * c.head_dim;
   const int64_t layer_kv = int64_t(c.num_blocks) * c.n_kv_heads * c.block_size * c.head_dim;
 
@@ -201,7 +215,7 @@ extern "C" int cloak_model_step(cloak_model* m, const cloak_step* s, void* d_ws,
     na.D = int32_t(D);
     na.eps = c.norm_eps;
     HIP_TRY(launch_rmsnorm(na, int(T), st), "cloak_model_step(norm)");
-    if (int rc = cloak_linear_fused(L, m->pool, t, 3, h, T, qkv, nullptr, 0, stream)) return rc;
+    if (int rc = cloak_linear_fused(L, m->pool, t, 3, h, T, qkv, scratch, sb, stream)) return rc;
     uint16_t* kc = m->kv + int64_t(2 * l) * layer_kv;
     uint16_t* vc = kc + layer_kv;
     RopeArgs ra{};
@@ -244,14 +258,14 @@ extern "C" int cloak_model_step(cloak_model* m, const cloak_step* s, void* d_ws,
     aa.out = attn;
     aa.ldo = D;
     HIP_TRY(launch_attention(aa, st), "cloak_model_step(attention)");
-    if (int rc = cloak_linear(L, m->pool, t[3], attn, T, o, nullptr, 0, stream)) return rc;
+    if (int rc = cloak_linear(L, m->pool, t[3], attn, T, o, scratch, sb, stream)) return rc;
     NormArgs nb = na;
     nb.add = o;
     nb.r_out = r;
     nb.gain = m->gains ? m->gains + int64_t(2 * l + 1) * D : nullptr;
     HIP_TRY(launch_rmsnorm(nb, int(T), st), "cloak_model_step(norm)");
-    if (int rc = cloak_swiglu(L, m->pool, l, h, T, f, stream)) return rc;
-    if (int rc = cloak_down(L, m->pool, l, f, T, y, stream)) return rc;
+    if (int rc = cloak_swiglu(L, m->pool, l, h, T, f, scratch, sb, stream)) return rc;
+    if (int rc = cloak_down(L, m->pool, l, f, T, y, scratch, sb, stream)) return rc;
   }
   if (R == 0) return CLOAK_OK;
   NormArgs nf{};
@@ -264,7 +278,7 @@ extern "C" int cloak_model_step(cloak_model* m, const cloak_step* s, void* d_ws,
   nf.D = int32_t(D);
   nf.eps = c.norm_eps;
   HIP_TRY(launch_rmsnorm(nf, int(R), st), "cloak_model_step(final norm)");
-  if (int rc = cloak_linear(L, m->pool, m->head, hsel, R, logits, nullptr, 0, stream)) return rc;
+  if (int rc = cloak_linear(L, m->pool, m->head, hsel, R, logits, scratch, sb, stream)) return rc;
   HIP_TRY(launch_argmax(logits, R, c.vocab, s->d_out_tokens, st), "cloak_model_step(argmax)");
   return CLOAK_OK;
 }

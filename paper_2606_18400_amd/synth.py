@@ -57,12 +57,15 @@ def weight_f32(tensor_index, n_out, k_in, base_seed=1234):
     return w
 
 
-def quantize_fp8_rows(w_f32):
+def quantize_fp8_rows(w_f32, rows_per_block=1024):
     """Per-output-row FP8 quantisation: returns (q bits [N][K] uint8, s [N] f32)."""
     amax = np.max(np.abs(w_f32), axis=1).astype(np.float32)
     s = (amax / np.float32(448.0)).astype(np.float32)
     s = np.where(s == 0, np.float32(1.0), s).astype(np.float32)
-    q = f32_to_e4m3_rne(w_f32.astype(np.float64) / s.astype(np.float64)[:, None])
+    q = np.empty(w_f32.shape, dtype=np.uint8)
+    for r0 in range(0, w_f32.shape[0], rows_per_block):   # bounded temporaries
+        blk = w_f32[r0:r0 + rows_per_block].astype(np.float64) / s[r0:r0 + rows_per_block].astype(np.float64)[:, None]
+        q[r0:r0 + rows_per_block] = f32_to_e4m3_rne(blk)
     return q, s
 
 

@@ -269,8 +269,9 @@ def test_empty_batch_and_argument_errors(C):
 
 # ---------------------------------------------------------------- prefill GEMM (MFMA)
 
-@pytest.mark.parametrize("M", [17, 100, 300, 600])
+@pytest.mark.parametrize("M", [17, 32, 64, 100, 300, 600])
 def test_prefill_gemm_vs_fp64(C, M):
+    # 17..64 tokens: skinny split-K MFMA GEMM; above: the 256x256 MFMA GEMM
     # K = 1024 / 2816 (multiples of 64): the BF16 MFMA GEMM path; N = 1000 and
     # d_ffn 2816 leave ragged row tiles, M leaves ragged token tiles
     shapes = decoder_shapes(1024, 2816, 256, "bf16", layers=1, extra=[(-1, "head", 1000, 1024, "bf16")])
@@ -305,7 +306,8 @@ def test_prefill_gemm_one_hot_bit_exact(C):
     cw.close()
 
 
-def test_prefill_gemm_cloaked_equals_native(C):
+@pytest.mark.parametrize("M", [48, 333])
+def test_prefill_gemm_cloaked_equals_native(C, M):
     import torch
     shapes = decoder_shapes(1024, 2816, 256, "bf16", layers=1)
     ws, scs = make_weights(shapes)
@@ -314,7 +316,6 @@ def test_prefill_gemm_cloaked_equals_native(C):
     nat = C.CloakedWeights(shapes, B, B * P, seed=23, flags=C.CLOAK_IDENTITY | C.CLOAK_NATIVE)
     cl.load(ws, scs)
     nat.load(ws, scs)
-    M = 333
     for t, s in enumerate(shapes):
         if s[1] == "down":
             continue
