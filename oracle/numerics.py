@@ -97,3 +97,55 @@ def f32_to_bf16_bits_rne(f):
     r = ((u + 0x7FFF + lsb) >> 16) & 0xFFFF
     r = np.where(is_nan, ((u >> 16) | 0x40) & 0xFFFF, r)
     return r.astype(np.uint16)
+
+
+# ----------------------------------------------------------------------------
+# FP8 activations for the FP8 x FP8 prefill product.
+#
+# Reading (the paper names FP8 weights with per-channel scales but no
+# activation format): each token's activation row is quantised to E4M3 with
+# one FP32 scale s_m = max_k |x[m][k]| / 448 (1 for an all-zero row), the
+# quotient x / s_m taken in binary32, then rounded to the nearest E4M3 value
+# (ties to the even code, saturating at +-448).  The product is then
+# y[m][n] = (sum_k q_x[m][k] q_w[n][k]) * s_m * s_w[n].
+# ----------------------------------------------------------------------------
+
+def _e4m3_nonneg_table():
+    """Values of the non-negative finite E4M3 codes 0x00..0x7E, ascending."""
+    return e4m3_bits_to_f64(np.arange(0x7F, dtype=np.uint8))
+
+
+def f64_to_e4m3_bits_rne(v):
+    """Nearest E4M3FN code by search over the code values: ties go to the even
+    code, magnitudes above 448 saturate to 448, the sign bit is kept (also for
+    zeros), NaN maps to 0x7F."""
+    v = np.asarray(v, dtype=np.float64)
+    table = _e4m3_nonneg_table()
+    a = np.abs(v)
+    hi = np.clip(np.searchsorted(table, a, side="left"), 0, 0x7E)
+    lo = np.clip(hi - 1, 0, 0x7E)
+    d_lo = a - table[lo]
+    d_hi = table[hi] - a
+    pick_hi = (d_hi < d_lo) | ((d_hi == d_lo) & (hi % 2 == 0))
+    code = np.where(pick_hi, hi, lo)
+    code = np.where(a >= table[0x7E], 0x7E, code)   # saturate
+    code = np.where(a == 0, 0, code)
+    code = code | np.where(np.signbit(v), 0x80, 0)
+    code = np.where(np.isnan(v), 0x7F, code)
+    return code.astype(np.uint8)
+
+
+def quantize_rows_e4m3(x32):
+    """Per-row E4M3 quantisation of binary32 activations: (codes uint8 [M][K],
+    scales float32 [M])."""
+    x32 = np.atleast_2d(np.asarray(x32, dtype=np.float32))
+    amax = np.max(np.abs(x32), axis=1) if x32.shape[1] else np.zeros(x32.shape[0], np.float32)
+    s = (amax.astype(np.float32) / np.float32(448.0)).astype(np.float32)
+    s = np.where(s == 0, np.float32(1.0), s).astype(np.float32)
+    quot = (x32 / s[:, None]).astype(np.float32)      # binary32 quotient
+    return f64_to_e4m3_bits_rne(quot.astype(np.float64)), s
+
+
+def fp8_activations_f64(q, s):
+    """Exact value of quantised activation rows: decode(q) * s."""
+    return e4m3_bits_to_f64(q) * np.asarray(s, np.float32).astype(np.float64)[:, None]

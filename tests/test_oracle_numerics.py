@@ -168,3 +168,85 @@ def test_causal_attention_brute_force():
             np.testing.assert_allclose(out[t, h * d:(h + 1) * d], want, rtol=1e-12, atol=1e-12)
     # the first token attends only to itself
     np.testing.assert_allclose(out[0, :d], v[0, 0], rtol=1e-13)
+
+
+# ---------------------------------------------------------------- FP8 activations
+
+def _nearest_e4m3_bruteforce(v):
+    """Exact-rational nearest search over all 256 codes (ties: even code)."""
+    from fractions import Fraction
+    best = None
+    target = Fraction(abs(v))
+    for code in range(0x7F):
+        val = Fraction(float(N.e4m3_bits_to_f64(np.array([code], np.uint8))[0]))
+        d = abs(val - target)
+        if best is None or d < best[0] or (d == best[0] and code % 2 == 0):
+            best = (d, code)
+    code = best[1]
+    if abs(v) > 448:
+        code = 0x7E
+    return code | (0x80 if np.signbit(v) else 0)
+
+
+def test_e4m3_encode_known_values_and_ties():
+    cases = {1.0: 0x38, 0.5: 0x30, 448.0: 0x7E, 500.0: 0x7E, 1e9: 0x7E, 2.0 ** -9: 0x01,
+             1.5 * 2.0 ** -9: 0x02,          # tie 1 / 2 -> even
+             0.5 * 2.0 ** -9: 0x00,          # tie 0 / 1 -> even (zero)
+             1.0625: 0x38,                    # tie 1.0 / 1.125 -> even
+             1.1875: 0x3A,                    # tie 1.125 / 1.25 -> even
+             432.0: 0x7E,                     # tie 416 / 448 -> even (0x7E)
+             2.0 ** -6: 0x08, 7 * 2.0 ** -9: 0x07, 15 * 2.0 ** -10: 0x08,   # tie 7 / 8 sub->normal
+             -1.0: 0xB8}
+    got = N.f64_to_e4m3_bits_rne(np.array(list(cases)))
+    assert list(got) == list(cases.values())
+    assert list(N.f64_to_e4m3_bits_rne(np.array([0.0, -0.0]))) == [0x00, 0x80]
+    assert N.f64_to_e4m3_bits_rne(np.array([np.nan]))[0] == 0x7F
+
+
+def test_e4m3_encode_roundtrips_every_finite_code():
+    codes = np.array([c for c in range(256) if (c & 0x7F) != 0x7F], np.uint8)
+    vals = N.e4m3_bits_to_f64(codes)
+    assert np.array_equal(N.f64_to_e4m3_bits_rne(vals), codes)
+
+
+def test_e4m3_encode_matches_bruteforce_on_random_values():
+    rng = np.random.Generator(np.random.PCG64(41))
+    v = np.concatenate([rng.standard_normal(300) * 40, rng.standard_normal(100) * 1e-2,
+                        rng.uniform(-520, 520, 100)])
+    got = N.f64_to_e4m3_bits_rne(v)
+    want = [_nearest_e4m3_bruteforce(float(x)) for x in v]
+    assert list(got) == want
+
+
+def test_quantize_rows_scale_and_error_bounds():
+    rng = np.random.Generator(np.random.PCG64(42))
+    x = rng.standard_normal((7, 333)).astype(np.float32)
+    x[3] = 0.0
+    x[5, 17] = -9.5                          # a negative row maximum
+    q, s = N.quantize_rows_e4m3(x)
+    assert q.dtype == np.uint8 and s.dtype == np.float32
+    assert s[3] == 1.0 and np.all(q[3] == 0)
+    for m in range(7):
+        if m == 3:
+            continue
+        k = int(np.argmax(np.abs(x[m])))
+        assert q[m, k] & 0x7F == 0x7E        # the row maximum lands on +-448
+        assert s[m] == np.float32(np.max(np.abs(x[m])) / np.float32(448.0))
+    assert q[5, 17] == 0xFE
+    # each dequantised element is within half an E4M3 step (relative 2^-4) or
+    # half the subnormal step of its value
+    deq = N.fp8_activations_f64(q, s)
+    step = np.maximum(np.abs(x.astype(np.float64)) * 2.0 ** -4, 2.0 ** -10 * s[:, None].astype(np.float64))
+    assert np.all(np.abs(deq - x) <= step * (1 + 1e-9))
+
+
+def test_fp8_product_reduces_to_exact_integers():
+    # codes of small integers are exact, and with unit scales the product is
+    # plain integer arithmetic
+    xq = N.f64_to_e4m3_bits_rne(np.array([[1.0, 2.0, -3.0, 4.0]]))
+    wq = N.f64_to_e4m3_bits_rne(np.array([[5.0, -6.0, 7.0, 8.0], [1.0, 1.0, 1.0, 1.0]]))
+    x = N.fp8_activations_f64(xq, np.array([0.5], np.float32))
+    w = N.weights_f64(wq, "fp8", np.array([2.0, 0.25], np.float32))
+    y = N.linear(x, w)
+    assert y[0, 0] == (5 - 12 - 21 + 32) * 0.5 * 2.0
+    assert y[0, 1] == (1 + 2 - 3 + 4) * 0.5 * 0.25
