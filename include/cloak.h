@@ -177,9 +177,11 @@ int cloak_pack_host(const cloak_layout* layout, int32_t tensor, const void* h_sr
                     void* h_pool, uint64_t h_pool_bytes);
 
 /* Bytes of device workspace `op` needs for `index` at M tokens: the FP32
- * partial sums of the split-K decode GEMM (17..64 tokens) and, for a down
- * projection called through cloak_linear, its activations gathered through
- * pi.  0 if none; UINT64_MAX on bad arguments. */
+ * partial sums of the split-K decode GEMM (5..64 tokens), for a down
+ * projection called through cloak_linear its activations gathered through
+ * pi, and for FP8 weights above 64 tokens the per-token E4M3 activations and
+ * their scales (M*K + 4*M bytes, each rounded up to 256).  0 if none;
+ * UINT64_MAX on bad arguments. */
 uint64_t cloak_ws_bytes(const cloak_layout* layout, int32_t op, int32_t index, int64_t M);
 
 /* Workspace of cloak_linear_fused for these n tensors at M tokens. */
@@ -221,6 +223,20 @@ int cloak_swiglu(const cloak_layout* layout, const void* d_pool, int32_t layer, 
  * with CLOAK_OP_SWIGLU / CLOAK_OP_DOWN. */
 int cloak_down(const cloak_layout* layout, const void* d_pool, int32_t layer, const void* d_h,
                int64_t M, void* d_y, void* d_ws, uint64_t ws_bytes, void* stream);
+
+/* Per-token FP8 quantisation of activations, as the FP8 x FP8 MFMA path
+ * applies it to x before a projection with FP8 weights and more than 64
+ * tokens (the paper names FP8 weights with per-channel scales; this
+ * activation format is this library's reading): for each row m of the bf16
+ * array d_x ([M][ldx] elements, ldx >= K),
+ *   s[m] = max_k |x[m][k]| / 448 in binary32 (1 if the row is all zero),
+ *   q[m][k] = E4M3 code nearest to the binary32 quotient x[m][k] / s[m]
+ *             (ties to the even code, saturating at +-448, OCP E4M3FN).
+ * d_q receives [M][K] bytes, d_s M floats (caller-owned device buffers).
+ * Enqueues on `stream`.  M = 0 is a no-op; EINVAL on null buffers, K < 1 or
+ * ldx < K. */
+int cloak_quantize_fp8(const void* d_x, int64_t M, int64_t K, int64_t ldx, void* d_q, void* d_s,
+                       void* stream);
 
 /* Re-randomise page placement in place (Section 4.2, periodic remapping
  * with no extra memory footprint): draw the matching tau from remap_seed,

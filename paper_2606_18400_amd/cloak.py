@@ -87,6 +87,7 @@ _SIGS = {
     "cloak_mlp": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _u64, _vp], _i32),
     "cloak_swiglu": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _u64, _vp], _i32),
     "cloak_down": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _u64, _vp], _i32),
+    "cloak_quantize_fp8": ([_vp, _i64, _i64, _i64, _vp, _vp, _vp], _i32),
     "cloak_remap": ([_vp, _vp, _u64, _vp], _i32),
     "cloak_remap_host": ([_vp, _vp, _u64, _u64], _i32),
     "cloak_model_create": ([_vp, _vp, ctypes.POINTER(cloak_model_config), _vp, _vp, ctypes.POINTER(_vp)], _i32),
@@ -250,6 +251,13 @@ def cloak_down(layout, pool, layer, h, M, y, ws=None, ws_bytes=0, stream=None):
 
 def cloak_remap(layout, pool, remap_seed, stream=None):
     _check(_lib.cloak_remap(layout, _ptr(pool), remap_seed & ((1 << 64) - 1), _stream(stream)), "cloak_remap")
+
+
+def cloak_quantize_fp8(x, M, q, s, stream=None):
+    """Per-token E4M3 quantisation of bf16 rows x[M][K] into q [M][K] uint8 and s [M] f32."""
+    K = x.shape[-1]
+    ldx = x.stride(0) if x.dim() > 1 else K
+    _check(_lib.cloak_quantize_fp8(_ptr(x), M, K, ldx, _ptr(q), _ptr(s), _stream(stream)), "cloak_quantize_fp8")
 
 
 def cloak_remap_host(layout, pool_image, remap_seed):

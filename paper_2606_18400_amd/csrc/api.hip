@@ -281,7 +281,7 @@ namespace {
 enum Path { kPathGemv, kPathSkinny, kPathGemm };
 
 Path pick_path(int32_t dtype, int64_t K, int64_t M) {
-  if (dtype == CLOAK_BF16 && K % gemm_k_step() == 0 && M >= kGemmMinTokens)
+  if ((dtype == CLOAK_BF16 || dtype == CLOAK_FP8_E4M3) && K % gemm_k_step() == 0 && M >= kGemmMinTokens)
     return M <= kSkinnyMaxTokens ? kPathSkinny : kPathGemm;
   return kPathGemv;
 }
@@ -325,10 +325,19 @@ int64_t launch_rows(const cloak_layout* L, const Proj& p, int64_t tile) {
   return r;
 }
 
+// FP8 weights on the 256x256 GEMM: FP8 x FP8 MFMA on activations quantised
+// per token (the quantisation also applies the gather of a down projection)
+bool use_a8(const Proj& p, Path path) {
+  return path == kPathGemm && p.dtype == CLOAK_FP8_E4M3 && p.K % gemm_k_step_a8() == 0;
+}
+
 uint64_t proj_ws_bytes(const cloak_layout* L, const Proj& p, int64_t M) {
   const Path path = pick_path(p.dtype, p.K, M);
   uint64_t b = 0;
-  if (p.gather && path != kPathGemv) b += a256(uint64_t(M) * uint64_t(p.K) * 2);
+  if (use_a8(p, path))
+    b += a256(uint64_t(M) * uint64_t(p.K)) + a256(uint64_t(M) * 4);
+  else if (p.gather && path != kPathGemv)
+    b += a256(uint64_t(M) * uint64_t(p.K) * 2);
   if (path == kPathSkinny) {
     const int64_t lr = launch_rows(L, p, skinny_tile_rows());
     const SplitPlan sp = plan_split(lr / skinny_tile_rows(), p.K);
@@ -350,6 +359,7 @@ int run_proj(const cloak_layout* L, const void* pool, const Proj& p, const void*
   if (path == kPathGemv) {
     GemvArgs a{};
     fill_common(L, pool, a, p.K, elt);
+    const int64_t kGemvRows = gemv_rows(a.nchunks);
     if (p.mode == kSwiGLU) {
       a.nseg = 2;
       a.seg[0] = make_seg(L, p.tensors[0], false, 0, 0);
@@ -380,7 +390,18 @@ int run_proj(const cloak_layout* L, const void* pool, const Proj& p, const void*
   // MFMA paths read x in the tensors' stored column order
   uint8_t* wsb = static_cast<uint8_t*>(ws);
   const void* xin = x;
-  if (p.gather) {
+  const bool a8 = use_a8(p, path);
+  float* sx = nullptr;
+  if (a8) {
+    uint8_t* q = wsb;
+    sx = reinterpret_cast<float*>(wsb + a256(uint64_t(M) * uint64_t(p.K)));
+    HIP_TRY(launch_quant_rows(static_cast<const uint16_t*>(x), ldx, p.gather ? p.x_perm : nullptr, q, sx, M, p.K,
+                              st),
+            fn);
+    xin = q;
+    ldx = p.K;
+    wsb += a256(uint64_t(M) * uint64_t(p.K)) + a256(uint64_t(M) * 4);
+  } else if (p.gather) {
     HIP_TRY(launch_gather_cols(static_cast<const uint16_t*>(x), ldx, p.x_perm, reinterpret_cast<uint16_t*>(wsb), M,
                                p.K, st),
             fn);
@@ -394,7 +415,10 @@ int run_proj(const cloak_layout* L, const void* pool, const Proj& p, const void*
   g.phi = L->dev.phi;
   g.log2_page = L->log2_page;
   g.K = int32_t(p.K);
-  g.row_bytes = p.K * 2;
+  g.row_bytes = p.K * elt;
+  g.f8 = p.dtype == CLOAK_FP8_E4M3 ? 1 : 0;
+  g.a8 = a8 ? 1 : 0;
+  g.sx = sx;
   g.M = int32_t(M);
   g.mode = p.mode;
   g.x = static_cast<const uint16_t*>(xin);
@@ -648,6 +672,24 @@ extern "C" int cloak_mlp(const cloak_layout* L, const void* d_pool, int32_t laye
   uint8_t* scratch = static_cast<uint8_t*>(d_ws) + hbytes;
   if (int rc = cloak_swiglu(L, d_pool, layer, d_x, M, d_ws, scratch, ws_bytes - hbytes, stream)) return rc;
   return cloak_down(L, d_pool, layer, d_ws, M, d_y, scratch, ws_bytes - hbytes, stream);
+}
+
+extern "C" int cloak_quantize_fp8(const void* d_x, int64_t M, int64_t K, int64_t ldx, void* d_q, void* d_s,
+                                  void* stream) {
+  using namespace cloak;
+  if (M < 0 || M > INT32_MAX || K < 1 || ldx < K) {
+    set_error("cloak_quantize_fp8: bad sizes M=%lld K=%lld ldx=%lld", (long long)M, (long long)K, (long long)ldx);
+    return CLOAK_EINVAL;
+  }
+  if (M == 0) return CLOAK_OK;
+  if (!d_x || !d_q || !d_s) {
+    set_error("cloak_quantize_fp8: null buffer");
+    return CLOAK_EINVAL;
+  }
+  HIP_TRY(launch_quant_rows(static_cast<const uint16_t*>(d_x), ldx, nullptr, static_cast<uint8_t*>(d_q),
+                            static_cast<float*>(d_s), M, K, static_cast<hipStream_t>(stream)),
+          "cloak_quantize_fp8");
+  return CLOAK_OK;
 }
 
 extern "C" int cloak_remap(cloak_layout* L, void* d_pool, uint64_t remap_seed, void* stream) {

@@ -17,6 +17,16 @@
 // 2 MiB pages).  A 128-byte row segment never straddles a page: rows and
 // page sizes are multiples of 128 B.
 //
+// FP8 weights: with BF16 activations (the default) the weight bytes are
+// widened exactly to BF16 as they enter LDS, so only HBM traffic changes.
+// In the FP8 x FP8 mode (a8) the activations were quantised per token to
+// E4M3 beforehand; a K step is then 128 elements (still 128 bytes per tile
+// row) and one v_mfma_f32_16x16x128_f8f6f4 per block consumes 32 bytes per
+// lane of each operand.  Both operands take the same two swizzled 16-byte
+// chunks per lane, so they pair the same k on both sides whatever order the
+// instruction uses inside its 128-wide K slice.  The epilogue multiplies by
+// the token scale, then by the weight-row scale.
+//
 // Output: lane l of an MFMA block holds D[4*(l/16)+r][l%16], i.e. four
 // consecutive weight rows (output columns) of one token, written as one 8 B
 // store.  SwiGLU mode: the tile's 256 rows are 128 gate rows and the same 128
@@ -31,6 +41,7 @@ namespace cloak {
 namespace {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -92,7 +103,69 @@ __device__ inline bool tile_row(const GemmArgs& a, int tile_n, int tr, int& seg,
   return n < a.seg[seg].rows;
 }
 
-template <bool TR, int EPI>
+// Weight tile of ROWS rows x one K step (64 elements) for NT threads.  BF16
+// rows give 128-byte segments (8 loads of 16 B); FP8 rows give 64-byte
+// segments (4 loads of 16 B), widened exactly to BF16 with
+// v_cvt_scalef32_pk_bf16_fp8 when they are written to LDS, so the MFMA path
+// is the same for both while FP8 weights cross HBM at one byte each.  Each
+// thread keeps its rows for the whole K loop (cached page translation).
+template <int ROWS, int NT, bool F8>
+struct WTile {
+  static constexpr int PER_ROW = F8 ? 4 : 8;
+  static constexpr int N = ROWS * PER_ROW / NT;
+  static constexpr int STEP_BYTES = F8 ? 64 : 128;
+  static_assert(NT % PER_ROW == 0, "thread count must cover whole rows");
+  static constexpr int ROW_STRIDE = NT / PER_ROW;   // rows between a thread's slots
+  RowRef r[N];
+  int tr0, c;                                       // first row, 16 B chunk in the row
+  u32x4 g[N];
+
+  template <typename RowFn>
+  __device__ inline void init(int tid, const uint8_t* pool, const WSeg* segs, int64_t row_bytes, RowFn row_of) {
+    tr0 = tid / PER_ROW;
+    c = tid % PER_ROW;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      int seg = 0, n = 0;
+      r[i].ok = row_of(tr0 + ROW_STRIDE * i, seg, n);
+      r[i].pool = pool;
+      r[i].vbase = segs[seg].vbase;
+      r[i].rowoff = int64_t(r[i].ok ? n : 0) * row_bytes + c * 16;
+      r[i].cvp = -1;
+      r[i].cbase = 0;
+    }
+  }
+  template <bool TR>
+  __device__ inline void load(const int32_t* phi, int log2_page, int kb) {
+    const int64_t koff = int64_t(kb) * STEP_BYTES;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      g[i] = r[i].ok ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(row_addr<TR>(phi, log2_page, r[i], koff)))
+                     : u32x4{0u, 0u, 0u, 0u};
+  }
+  __device__ inline void store(uint8_t* tile) const {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      if constexpr (F8) {
+        const uint32_t w[4] = {g[i].x, g[i].y, g[i].z, g[i].w};
+        uint32_t o[8];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          o[2 * j] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w[j], 1.0f, false));
+          o[2 * j + 1] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w[j], 1.0f, true));
+        }
+        const int row = tr0 + ROW_STRIDE * i;
+        *reinterpret_cast<u32x4*>(tile + swz(row, 2 * c)) = u32x4{o[0], o[1], o[2], o[3]};
+        *reinterpret_cast<u32x4*>(tile + swz(row, 2 * c + 1)) = u32x4{o[4], o[5], o[6], o[7]};
+      } else {
+        *reinterpret_cast<u32x4*>(tile + swz(tr0 + ROW_STRIDE * i, c)) = g[i];
+      }
+    }
+  }
+};
+
+// F8: FP8 weights; A8: FP8 x FP8 MFMA on quantised activations (needs F8)
+template <bool TR, int EPI, bool F8, bool A8>
 __global__ __launch_bounds__(NTHREADS, 1) void gemm_kernel(const GemmArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   // buffer b: X tile at smem + 2b*TILE_BYTES, W tile right after it
@@ -100,59 +173,62 @@ __global__ __launch_bounds__(NTHREADS, 1) void gemm_kernel(const GemmArgs a) {
   auto lds_w = [&](int buf) { return smem + buf * 2 * TILE_BYTES + TILE_BYTES; };
 
   // XCD-aware tile order: consecutive workgroup ids go to different XCDs, so
-  // give each XCD a contiguous run of tiles; inside a run, tokens vary
-  // fastest and the run's weight tiles stay in that XCD's L2.
+  // give each XCD a contiguous run of tiles of a grouped order (groups of
+  // GROUP_M token tiles, token tile fastest inside a group).  The 32
+  // workgroups an XCD runs at once then cover about 8 token tiles x 4 weight
+  // tiles, and each X and W slice they fetch serves 4 and 8 of them from the
+  // XCD's L2, instead of 32 token tiles each fetching its own X slice.
+  constexpr int GROUP_M = 8;
   const int ntiles = a.tiles_m * a.tiles_n;
   const int b = blockIdx.x;
   const int per_xcd = (ntiles + 7) / 8;
   const int xcd = b % 8, slot = b / 8;
   const int t_id = xcd * per_xcd + slot;
   if (t_id >= ntiles) return;
-  const int tile_m = t_id % a.tiles_m;
-  const int tile_n = t_id / a.tiles_m;
+  const int per_group = GROUP_M * a.tiles_n;
+  const int first_m = (t_id / per_group) * GROUP_M;
+  const int group_m = min(a.tiles_m - first_m, GROUP_M);
+  const int in_group = t_id % per_group;
+  const int tile_m = first_m + in_group % group_m;
+  const int tile_n = in_group / group_m;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave / WAVES_N, wn = wave % WAVES_N;
 
-  // this thread's load slots: rows (tid >> 3) + 64 i, 16 B chunk (tid & 7)
+  // activation slots: rows (tid >> 3) + 64 i, 16 B chunk (tid & 7); a K step
+  // is 128 bytes of a row in both modes
   const int ch = tid & 7;
-  const uint16_t* xrow[LOADS];
+  const uint8_t* xrow[LOADS];
   bool xok[LOADS];
-  RowRef wr[LOADS];
+  const int64_t ldx_bytes = A8 ? a.ldx : a.ldx * 2;
 #pragma unroll
   for (int i = 0; i < LOADS; ++i) {
     const int tr = (tid >> 3) + 64 * i;
     const int m = tile_m * BM + tr;
     xok[i] = m < a.M;
-    xrow[i] = a.x + int64_t(xok[i] ? m : 0) * a.ldx + ch * 8;
-    int seg, n;
-    wr[i].ok = tile_row<EPI>(a, tile_n, tr, seg, n);
-    wr[i].pool = a.pool;
-    wr[i].vbase = a.seg[seg].vbase;
-    wr[i].rowoff = int64_t(wr[i].ok ? n : 0) * a.row_bytes + ch * 16;
-    wr[i].cvp = -1;
-    wr[i].cbase = 0;
+    xrow[i] = reinterpret_cast<const uint8_t*>(a.x) + int64_t(xok[i] ? m : 0) * ldx_bytes + ch * 16;
   }
+  // a8 reads the FP8 weight bytes as they are (128 elements per K step)
+  WTile<BN, NTHREADS, F8 && !A8> wt;
+  wt.init(tid, a.pool, a.seg, a.row_bytes,
+          [&](int tr, int& seg, int& n) { return tile_row<EPI>(a, tile_n, tr, seg, n); });
 
-  u32x4 gx[LOADS], gw[LOADS];
+  u32x4 gx[LOADS];
   auto gload = [&](int kb) {
-    const int64_t koff = int64_t(kb) * ROWB;
 #pragma unroll
-    for (int i = 0; i < LOADS; ++i) {
-      gx[i] = xok[i] ? *reinterpret_cast<const u32x4*>(xrow[i] + kb * BK) : u32x4{0u, 0u, 0u, 0u};
-      gw[i] = wr[i].ok ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(row_addr<TR>(a.phi, a.log2_page, wr[i], koff)))
-                       : u32x4{0u, 0u, 0u, 0u};
-    }
+    for (int i = 0; i < LOADS; ++i)
+      gx[i] = xok[i] ? *reinterpret_cast<const u32x4*>(xrow[i] + int64_t(kb) * ROWB) : u32x4{0u, 0u, 0u, 0u};
+    wt.template load<TR>(a.phi, a.log2_page, kb);
   };
   auto swrite = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < LOADS; ++i) {
       const int tr = (tid >> 3) + 64 * i;
       *reinterpret_cast<u32x4*>(lds_x(buf) + swz(tr, ch)) = gx[i];
-      *reinterpret_cast<u32x4*>(lds_w(buf) + swz(tr, ch)) = gw[i];
     }
+    wt.store(lds_w(buf));
   };
 
   f32x4 acc[NB][MB];
@@ -173,32 +249,49 @@ __global__ __launch_bounds__(NTHREADS, 1) void gemm_kernel(const GemmArgs a) {
     }
   }
 
-  const int nk = a.K / BK;
+  const int nk = a.K / (A8 ? 2 * BK : BK);
   gload(0);
   swrite(0);
   __syncthreads();
   for (int kb = 0; kb < nk; ++kb) {
     const int buf = kb & 1;
     if (kb + 1 < nk) gload(kb + 1);
+    // weight fragments of the wave's NB row blocks stay in registers while
+    // the MB token fragments are read one at a time
+    if constexpr (A8) {
+      const int c0 = 2 * (lane >> 4);
+      auto frag = [&](const uint8_t* tile, int r) {
+        const u32x4 lo = *reinterpret_cast<const u32x4*>(tile + swz(r, c0));
+        const u32x4 hi = *reinterpret_cast<const u32x4*>(tile + swz(r, c0 + 1));
+        return i32x8{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
+      };
+      i32x8 fa[NB];
 #pragma unroll
-    for (int s = 0; s < BK / 32; ++s) {
-      const int chunk = s * 4 + (lane >> 4);
-      bf16x8_t fa[NB], fb[MB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const int r = wrow[nb] + (lane & 15);
-        fa[nb] = *reinterpret_cast<const bf16x8_t*>(lds_w(buf) + swz(r, chunk));
-      }
+      for (int nb = 0; nb < NB; ++nb) fa[nb] = frag(lds_w(buf), wrow[nb] + (lane & 15));
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
-        const int r = wm * WM + mb * 16 + (lane & 15);
-        fb[mb] = *reinterpret_cast<const bf16x8_t*>(lds_x(buf) + swz(r, chunk));
+        const i32x8 fb = frag(lds_x(buf), wm * WM + mb * 16 + (lane & 15));
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[nb][mb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fa[nb], fb, acc[nb][mb], 0, 0, 0, 0, 0, 0);
       }
+    } else {
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
+      for (int s = 0; s < BK / 32; ++s) {
+        const int chunk = s * 4 + (lane >> 4);
+        bf16x8_t fa[NB];
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-          acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[nb], fb[mb], acc[nb][mb], 0, 0, 0);
+        for (int nb = 0; nb < NB; ++nb)
+          fa[nb] = *reinterpret_cast<const bf16x8_t*>(lds_w(buf) + swz(wrow[nb] + (lane & 15), chunk));
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          const bf16x8_t fb =
+              *reinterpret_cast<const bf16x8_t*>(lds_x(buf) + swz(wm * WM + mb * 16 + (lane & 15), chunk));
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[nb], fb, acc[nb][mb], 0, 0, 0);
+        }
+      }
     }
     if (kb + 1 < nk) swrite(buf ^ 1);
     __syncthreads();
@@ -223,7 +316,9 @@ __global__ __launch_bounds__(NTHREADS, 1) void gemm_kernel(const GemmArgs a) {
         const int m = tile_m * BM + wm * WM + mb * 16 + tok;
         if (m >= a.M) continue;
         uint16_t* yrow = static_cast<uint16_t*>(a.y) + int64_t(m) * a.ldy + out_off;
-        float v[4] = {acc[nb][mb][0], acc[nb][mb][1], acc[nb][mb][2], acc[nb][mb][3]};
+        // a8: the token scale first, then the weight-row scale
+        const float ts = A8 ? a.sx[m] : 1.f;
+        float v[4] = {acc[nb][mb][0] * ts, acc[nb][mb][1] * ts, acc[nb][mb][2] * ts, acc[nb][mb][3] * ts};
         if (!perm && a.vec_store && n0 + 3 < rows) {
           uint32_t lo, hi;
           float s0 = scale ? scale[n0] : 1.f, s1 = scale ? scale[n0 + 1] : 1.f;
@@ -253,13 +348,14 @@ __global__ __launch_bounds__(NTHREADS, 1) void gemm_kernel(const GemmArgs a) {
         const int m = tile_m * BM + wm * WM + mb * 16 + tok;
         if (m >= a.M) continue;
         uint16_t* hrow = static_cast<uint16_t*>(a.y) + int64_t(m) * a.ldy;
+        const float ts = A8 ? a.sx[m] : 1.f;
         uint16_t hv[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int j = j0 + r;
           const int jj = j < dff ? j : dff - 1;
-          const float g = acc[nb][mb][r] * (sg ? sg[jj] : 1.f);
-          const float u = acc[nb + NB / 2][mb][r] * (su ? su[jj] : 1.f);
+          const float g = acc[nb][mb][r] * ts * (sg ? sg[jj] : 1.f);
+          const float u = acc[nb + NB / 2][mb][r] * ts * (su ? su[jj] : 1.f);
           hv[r] = f32_to_bf16_rne(g / (1.0f + expf(-g)) * u);
         }
         if (a.vec_store && j0 + 3 < dff) {
@@ -287,18 +383,95 @@ __global__ __launch_bounds__(256) void gather_cols_kernel(const uint16_t* __rest
   }
 }
 
+// Nearest E4M3 (OCP "FN" variant) code of a binary32 value, ties to the even
+// code, saturating at 448, NaN -> 0x7F.  Below 2^-6 the codes are the
+// multiples of 2^-9 (code = rint(|v| * 512), exact scaling); above, the 23
+// fraction bits are rounded to 3 and a carry out of the fraction moves the
+// code to the next binade by plain addition.
+__device__ inline uint32_t e4m3_code(float v) {
+  const uint32_t u = __float_as_uint(v);
+  const uint32_t sign = (u >> 24) & 0x80u;
+  const uint32_t au = u & 0x7fffffffu;
+  if (au > 0x7f800000u) return 0x7fu;
+  const float a = __uint_as_float(au);
+  if (a >= 448.0f) return sign | 0x7eu;
+  if (a < 0.015625f) return sign | uint32_t(rintf(a * 512.0f));
+  const int e = int(au >> 23) - 127;   // -6 .. 8
+  const uint32_t frac = au & 0x7fffffu;
+  uint32_t keep = frac >> 20;
+  const uint32_t rest = frac & 0xfffffu;
+  if (rest > 0x80000u || (rest == 0x80000u && (keep & 1u))) ++keep;
+  uint32_t code = uint32_t(e + 7) * 8u + keep;
+  if (code > 0x7eu) code = 0x7eu;
+  return sign | code;
+}
+
+__device__ inline float bf16_bits_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
+
+// One workgroup per token row: max |x| over the row, s = max / 448 (1 for a
+// zero row), then q[j] = code(x[perm[j]] / s) with the IEEE binary32 quotient.
+__global__ __launch_bounds__(256) void quant_rows_kernel(const uint16_t* __restrict__ x, int64_t ldx,
+                                                         const int32_t* __restrict__ perm, uint8_t* __restrict__ q,
+                                                         float* __restrict__ s, int64_t K, int vec) {
+  __shared__ float red[4];
+  const int64_t m = blockIdx.x;
+  const uint16_t* xr = x + m * ldx;
+  uint8_t* qr = q + m * K;
+  const int t = threadIdx.x;
+  float amax = 0.f;
+  if (vec) {
+    for (int64_t k = int64_t(t) * 8; k < K; k += 256 * 8) {
+      const u32x4 w = *reinterpret_cast<const u32x4*>(xr + k);
+      const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        amax = fmaxf(amax, fabsf(bf16_bits_to_f32(ww[i] & 0xffffu)));
+        amax = fmaxf(amax, fabsf(bf16_bits_to_f32(ww[i] >> 16)));
+      }
+    }
+  } else {
+    for (int64_t k = t; k < K; k += 256) amax = fmaxf(amax, fabsf(bf16_bits_to_f32(xr[k])));
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) amax = fmaxf(amax, __shfl_xor(amax, d));
+  if ((t & 63) == 0) red[t >> 6] = amax;
+  __syncthreads();
+  amax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  float sc = amax / 448.0f;
+  if (sc == 0.f) sc = 1.0f;
+  if (t == 0) s[m] = sc;
+  if (vec) {
+    for (int64_t k = int64_t(t) * 8; k < K; k += 256 * 8) {
+      const u32x4 w = *reinterpret_cast<const u32x4*>(xr + k);
+      const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+      uint32_t out[2] = {0u, 0u};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t lo = e4m3_code(bf16_bits_to_f32(ww[i] & 0xffffu) / sc);
+        const uint32_t hi = e4m3_code(bf16_bits_to_f32(ww[i] >> 16) / sc);
+        out[i >> 1] |= (lo | (hi << 8)) << (16 * (i & 1));
+      }
+      *reinterpret_cast<uint2*>(qr + k) = make_uint2(out[0], out[1]);
+    }
+  } else {
+    for (int64_t k = t; k < K; k += 256) {
+      const int64_t src = perm ? perm[k] : k;
+      qr[k] = uint8_t(e4m3_code(bf16_bits_to_f32(xr[src]) / sc));
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
-// Skinny split-K GEMM for decode batches (17..64 tokens).  A 256-row tile
+// Skinny split-K GEMM for decode batches (5..64 tokens).  A 256-row tile
 // leaves a 4096-row projection only 16 workgroups; here a workgroup of 4
-// waves takes 64 weight rows x 64 tokens x one K slice (SBK = 64 per step,
-// 32 KiB of LDS, so several workgroups share a CU), and the K slices of a
-// row tile are spread over workgroups.  Each slice writes FP32 partial sums
+// waves takes 64 weight rows x a 16/32/64-token tile x one K slice (SBK = 64
+// per step, at most 32 KiB of LDS, so several workgroups share a CU), and
+// the K slices of a row tile are spread over workgroups.  Each slice writes FP32 partial sums
 // part[slice][token][launch-row]; skinny_reduce_kernel adds the slices in a
 // fixed order (deterministic) and applies the epilogue.  SwiGLU tiles hold
 // 32 gate rows and the same 32 up rows.
-constexpr int SBM = 64, SBN = 64, SBK = 64, STHREADS = 256;
-constexpr int S_TILE = SBM * ROWB;                     // 8 KiB per operand tile
-constexpr int S_LOADS = SBM * (ROWB / 16) / STHREADS;  // 2
+constexpr int SBN = 64, SBK = 64, STHREADS = 256;
+constexpr int S_WTILE = SBN * ROWB;                    // 8 KiB weight tile
 
 template <int EPI>
 __device__ inline bool skinny_row(const SkinnyArgs& a, int tile_n, int tr, int& seg, int& n) {
@@ -316,11 +489,14 @@ __device__ inline bool skinny_row(const SkinnyArgs& a, int tile_n, int tr, int& 
   return n < a.seg[seg].rows;
 }
 
-template <bool TR, int EPI>
+// SBM = token tile (16, 32 or 64): the batch is padded only to SBM.
+template <int SBM, bool TR, int EPI, bool F8>
 __global__ __launch_bounds__(STHREADS) void skinny_kernel(const SkinnyArgs a) {
-  __shared__ __attribute__((aligned(16))) uint8_t smem[4 * S_TILE];
-  auto lds_x = [&](int buf) { return smem + buf * 2 * S_TILE; };
-  auto lds_w = [&](int buf) { return smem + buf * 2 * S_TILE + S_TILE; };
+  constexpr int XTILE = SBM * ROWB;
+  constexpr int XCH = SBM * (ROWB / 16);   // 16-byte chunks of the token tile
+  __shared__ __attribute__((aligned(16))) uint8_t smem[2 * (XTILE + S_WTILE)];
+  auto lds_x = [&](int buf) { return smem + buf * (XTILE + S_WTILE); };
+  auto lds_w = [&](int buf) { return smem + buf * (XTILE + S_WTILE) + XTILE; };
   const int ks = blockIdx.x % a.ksplit;
   const int tile_n = blockIdx.x / a.ksplit;
   const int kb_begin = ks * a.kblocks_per_split;
@@ -332,39 +508,34 @@ __global__ __launch_bounds__(STHREADS) void skinny_kernel(const SkinnyArgs a) {
   const int wave = tid >> 6;
   const int ch = tid & 7;
 
-  const uint16_t* xrow[S_LOADS];
-  bool xok[S_LOADS];
-  RowRef wr[S_LOADS];
+  // token tile: XCH 16-byte chunks, chunk idx = tid + STHREADS*i -> row idx/8, chunk idx%8
+  constexpr int XL = (XCH + STHREADS - 1) / STHREADS;
+  bool xslot[XL], xok[XL];
+  int xr[XL];
+  const uint16_t* xrow[XL];
 #pragma unroll
-  for (int i = 0; i < S_LOADS; ++i) {
-    const int tr = (tid >> 3) + 32 * i;
-    xok[i] = tr < a.M;
-    xrow[i] = a.x + int64_t(xok[i] ? tr : 0) * a.ldx + ch * 8;
-    int seg, n;
-    wr[i].ok = skinny_row<EPI>(a, tile_n, tr, seg, n);
-    wr[i].pool = a.pool;
-    wr[i].vbase = a.seg[seg].vbase;
-    wr[i].rowoff = int64_t(wr[i].ok ? n : 0) * a.row_bytes + ch * 16;
-    wr[i].cvp = -1;
-    wr[i].cbase = 0;
+  for (int i = 0; i < XL; ++i) {
+    const int idx = tid + STHREADS * i;
+    xslot[i] = idx < XCH;
+    xr[i] = idx >> 3;
+    xok[i] = xslot[i] && xr[i] < a.M;
+    xrow[i] = a.x + int64_t(xok[i] ? xr[i] : 0) * a.ldx + ch * 8;
   }
-  u32x4 gx[S_LOADS], gw[S_LOADS];
+  WTile<SBN, STHREADS, F8> wt;
+  wt.init(tid, a.pool, a.seg, a.row_bytes,
+          [&](int tr, int& seg, int& n) { return skinny_row<EPI>(a, tile_n, tr, seg, n); });
+  u32x4 gx[XL];
   auto gload = [&](int kb) {
-    const int64_t koff = int64_t(kb) * ROWB;
 #pragma unroll
-    for (int i = 0; i < S_LOADS; ++i) {
+    for (int i = 0; i < XL; ++i)
       gx[i] = xok[i] ? *reinterpret_cast<const u32x4*>(xrow[i] + kb * SBK) : u32x4{0u, 0u, 0u, 0u};
-      gw[i] = wr[i].ok ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(row_addr<TR>(a.phi, a.log2_page, wr[i], koff)))
-                       : u32x4{0u, 0u, 0u, 0u};
-    }
+    wt.template load<TR>(a.phi, a.log2_page, kb);
   };
   auto swrite = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < S_LOADS; ++i) {
-      const int tr = (tid >> 3) + 32 * i;
-      *reinterpret_cast<u32x4*>(lds_x(buf) + swz(tr, ch)) = gx[i];
-      *reinterpret_cast<u32x4*>(lds_w(buf) + swz(tr, ch)) = gw[i];
-    }
+    for (int i = 0; i < XL; ++i)
+      if (xslot[i]) *reinterpret_cast<u32x4*>(lds_x(buf) + swz(xr[i], ch)) = gx[i];
+    wt.store(lds_w(buf));
   };
   f32x4 acc[SBM / 16];
 #pragma unroll
@@ -445,6 +616,19 @@ __global__ __launch_bounds__(256) void skinny_reduce_kernel(const SkinnyArgs a) 
 int gemm_lds_bytes() { return 4 * TILE_BYTES; }
 int gemm_tile_rows() { return BN; }
 int gemm_k_step() { return BK; }
+int gemm_k_step_a8() { return 2 * BK; }
+
+hipError_t launch_quant_rows(const uint16_t* x, int64_t ldx, const int32_t* perm, uint8_t* q, float* s, int64_t M,
+                             int64_t K, hipStream_t st) {
+  if (M <= 0) return hipSuccess;
+  if (M > INT32_MAX) return hipErrorInvalidValue;
+  const int vec = (!perm && K % 8 == 0 && ldx % 8 == 0 && reinterpret_cast<uintptr_t>(x) % 16 == 0 &&
+                   reinterpret_cast<uintptr_t>(q) % 8 == 0)
+                      ? 1
+                      : 0;
+  hipLaunchKernelGGL(quant_rows_kernel, dim3(unsigned(M)), dim3(256), 0, st, x, ldx, perm, q, s, K, vec);
+  return hipGetLastError();
+}
 
 hipError_t launch_gemm(const GemmArgs& a, bool translate, hipStream_t s) {
   const int ntiles = a.tiles_m * a.tiles_n;
@@ -452,12 +636,20 @@ hipError_t launch_gemm(const GemmArgs& a, bool translate, hipStream_t s) {
   const int blocks = (ntiles + 7) / 8 * 8;
   const size_t lds = size_t(gemm_lds_bytes());
   void (*fn)(const GemmArgs);
-  if (a.mode == kSwiGLU)
-    fn = translate ? gemm_kernel<true, kSwiGLU> : gemm_kernel<false, kSwiGLU>;
+  const bool f8 = a.f8 != 0, a8 = a.a8 != 0;
+  if (a8 && !f8) return hipErrorInvalidValue;
+  const bool sw = a.mode == kSwiGLU;
+  if (a8)
+    fn = translate ? (sw ? gemm_kernel<true, kSwiGLU, true, true> : gemm_kernel<true, kStore, true, true>)
+                   : (sw ? gemm_kernel<false, kSwiGLU, true, true> : gemm_kernel<false, kStore, true, true>);
+  else if (f8)
+    fn = translate ? (sw ? gemm_kernel<true, kSwiGLU, true, false> : gemm_kernel<true, kStore, true, false>)
+                   : (sw ? gemm_kernel<false, kSwiGLU, true, false> : gemm_kernel<false, kStore, true, false>);
   else
-    fn = translate ? gemm_kernel<true, kStore> : gemm_kernel<false, kStore>;
-  static bool attr_set[4] = {false, false, false, false};
-  const int key = (translate ? 2 : 0) + (a.mode == kSwiGLU ? 1 : 0);
+    fn = translate ? (sw ? gemm_kernel<true, kSwiGLU, false, false> : gemm_kernel<true, kStore, false, false>)
+                   : (sw ? gemm_kernel<false, kSwiGLU, false, false> : gemm_kernel<false, kStore, false, false>);
+  static bool attr_set[16] = {};
+  const int key = (translate ? 2 : 0) + (sw ? 1 : 0) + (f8 ? 4 : 0) + (a8 ? 8 : 0);
   if (!attr_set[key]) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                        int(lds));
@@ -470,15 +662,25 @@ hipError_t launch_gemm(const GemmArgs& a, bool translate, hipStream_t s) {
 
 int skinny_tile_rows() { return SBN; }
 
+template <int SBM, bool F8>
+void (*skinny_fn2(bool translate, int mode))(const SkinnyArgs) {
+  if (mode == kSwiGLU) return translate ? skinny_kernel<SBM, true, kSwiGLU, F8> : skinny_kernel<SBM, false, kSwiGLU, F8>;
+  return translate ? skinny_kernel<SBM, true, kStore, F8> : skinny_kernel<SBM, false, kStore, F8>;
+}
+
+template <int SBM>
+void (*skinny_fn(bool translate, int mode, bool f8))(const SkinnyArgs) {
+  return f8 ? skinny_fn2<SBM, true>(translate, mode) : skinny_fn2<SBM, false>(translate, mode);
+}
+
 hipError_t launch_skinny(const SkinnyArgs& a, bool translate, hipStream_t s) {
   const int64_t blocks = int64_t(a.tiles_n) * a.ksplit;
   if (blocks <= 0 || a.M <= 0) return hipSuccess;
-  if (a.M > SBM || a.K % SBK != 0) return hipErrorInvalidValue;
-  void (*fn)(const SkinnyArgs);
-  if (a.mode == kSwiGLU)
-    fn = translate ? skinny_kernel<true, kSwiGLU> : skinny_kernel<false, kSwiGLU>;
-  else
-    fn = translate ? skinny_kernel<true, kStore> : skinny_kernel<false, kStore>;
+  if (a.M > kSkinnyMaxTokens || a.K % SBK != 0) return hipErrorInvalidValue;
+  const bool f8 = a.f8 != 0;
+  void (*fn)(const SkinnyArgs) = a.M <= 16 ? skinny_fn<16>(translate, a.mode, f8)
+                                 : a.M <= 32 ? skinny_fn<32>(translate, a.mode, f8)
+                                             : skinny_fn<64>(translate, a.mode, f8);
   hipLaunchKernelGGL(fn, dim3(unsigned(blocks)), dim3(STHREADS), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

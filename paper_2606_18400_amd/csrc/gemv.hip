@@ -370,14 +370,19 @@ int max_mtile(int wt, int cpw) {
   return cpw <= 2 ? 8 : cpw == 4 ? 4 : 2;
 }
 
+// Rows per group: 8, or 4 for rows of more than 16 KiB (4+ chunks per wave),
+// where 4 rows keep the next-group prefetch within the register budget.
+constexpr int rows_for(int cpw) { return cpw >= 4 ? 4 : 8; }
+
 template <int WT, int CPW, bool TR, int EPI>
 KernelFn pick_mt(int mt) {
   constexpr int kMax = WT == kFP8 ? (CPW <= 1 ? 8 : CPW == 2 ? 4 : CPW == 4 ? 2 : 1)
                                   : (CPW <= 2 ? 8 : CPW == 4 ? 4 : 2);
-  if (mt <= 1) return gemv_kernel<WT, 1, kGemvRows, CPW, TR, EPI>;
-  if (mt <= 2 || kMax == 2) return gemv_kernel<WT, (kMax < 2 ? 1 : 2), kGemvRows, CPW, TR, EPI>;
-  if (mt <= 4 || kMax == 4) return gemv_kernel<WT, (kMax < 4 ? 1 : 4), kGemvRows, CPW, TR, EPI>;
-  return gemv_kernel<WT, (kMax < 8 ? 1 : 8), kGemvRows, CPW, TR, EPI>;
+  constexpr int R = rows_for(CPW);
+  if (mt <= 1) return gemv_kernel<WT, 1, R, CPW, TR, EPI>;
+  if (mt <= 2 || kMax == 2) return gemv_kernel<WT, (kMax < 2 ? 1 : 2), R, CPW, TR, EPI>;
+  if (mt <= 4 || kMax == 4) return gemv_kernel<WT, (kMax < 4 ? 1 : 4), R, CPW, TR, EPI>;
+  return gemv_kernel<WT, (kMax < 8 ? 1 : 8), R, CPW, TR, EPI>;
 }
 
 template <int WT, bool TR, int EPI>
@@ -433,6 +438,8 @@ int gemv_cpw(int nchunks) {
 }
 
 int gemv_max_tokens(int wtype, int nchunks) { return max_mtile(wtype, gemv_cpw(nchunks)); }
+
+int gemv_rows(int nchunks) { return rows_for(gemv_cpw(nchunks)); }
 
 hipError_t launch_gemv(const GemvArgs& a, int wtype, int mtile, bool translate, hipStream_t s) {
   if (a.groups <= 0) return hipSuccess;

@@ -21,8 +21,9 @@ struct WSeg {
 };
 
 enum WType : int { kF32 = 0, kBF16 = 1, kFP8 = 2 };
-// Rows per GEMV row group (a SwiGLU group holds kGemvRows/2 gate/up pairs).
-constexpr int kGemvRows = 8;
+// Rows per GEMV row group for rows of `nchunks` KiB (a SwiGLU group holds
+// half as many gate/up pairs); every tensor of a launch starts on a group.
+int gemv_rows(int nchunks);
 enum Epilogue : int { kStore = 0, kSwiGLU = 1 };
 
 struct GemvArgs {
@@ -70,10 +71,13 @@ struct GemmArgs {
   int32_t M;
   int32_t tiles_m, tiles_n;
   int32_t vec_store;        // 1 if 8-byte output stores are aligned
+  int32_t f8;               // weights are FP8 E4M3 (row_bytes = K)
+  int32_t a8;               // FP8 x FP8 MFMA: x holds E4M3 codes [M][ldx bytes], sx their row scales
+  const float* sx;
 };
 hipError_t launch_gemm(const GemmArgs& a, bool translate, hipStream_t s);
 
-// Skinny split-K GEMM for 17..64 tokens (same fields as GemmArgs, plus the
+// Skinny split-K GEMM for 5..64 tokens (same fields as GemmArgs, plus the
 // split-K partial-sum buffer).
 struct SkinnyArgs {
   const uint8_t* pool;
@@ -91,6 +95,9 @@ struct SkinnyArgs {
   int32_t M;
   int32_t tiles_m, tiles_n;
   int32_t vec_store;
+  int32_t f8;
+  int32_t a8;               // always 0 here
+  const float* sx;
   // split-K
   float* part;              // [ksplit][M][ldp] FP32 partial sums (workspace)
   int64_t ldp;              // launch-rows (tiles_n * skinny_tile_rows())
@@ -104,8 +111,16 @@ hipError_t launch_gather_cols(const uint16_t* x, int64_t ldx, const int32_t* per
                               int64_t K, hipStream_t s);
 int gemm_tile_rows();
 int gemm_k_step();
-// Token count from which BF16 projections use the MFMA GEMM instead of the GEMV.
-constexpr int64_t kGemmMinTokens = 17;
+// K step of the FP8 x FP8 MFMA GEMM (elements)
+int gemm_k_step_a8();
+// Per-row E4M3 quantisation of bf16 activations, optionally gathered through
+// perm: s[m] = max|x[m][:]| / 448 (1 for a zero row), q[m][j] = E4M3(x[m][perm[j]] / s[m])
+// rounded to nearest even, saturating; q is [M][K] bytes.
+hipError_t launch_quant_rows(const uint16_t* x, int64_t ldx, const int32_t* perm, uint8_t* q, float* s, int64_t M,
+                             int64_t K, hipStream_t st);
+// Token count from which BF16 projections use MFMA (skinny split-K up to
+// kSkinnyMaxTokens, the 256x256 GEMM above) instead of the VALU GEMV.
+constexpr int64_t kGemmMinTokens = 5;
 
 // ---- decoder-step kernels (serve.hip)
 struct EmbedArgs {

@@ -1,38 +1,96 @@
-"""Per-kernel summary of a rocprofv3 kernel trace (rocpd SQLite output).
+"""Short text summaries of rocprofv3 output, for the files kept under profiles/.
 
-Usage: python -m paper_2606_18400_amd.profile_summary <results.db> [--top N] [--match SUBSTR]
+Usage:
+  python -m paper_2606_18400_amd.profile_summary stats <kernel_stats.csv | results.db> [--top N]
+  python -m paper_2606_18400_amd.profile_summary pmc <fetch counter_collection.csv> <write counter_collection.csv>
+          [--copy-match MulFunctor] [--copy-bytes 1073741824]
 
-Prints, per kernel name: dispatch count, average / min / max duration in
-microseconds and total milliseconds, sorted by total time.  Used to write the
-short text summaries kept under profiles/.
+`stats` prints, per kernel: dispatch count, average / min / max duration in
+microseconds and total milliseconds, sorted by total time (CSV from
+`--kernel-trace --stats --output-format csv`, or the rocpd SQLite database).
+
+`pmc` reads one `--pmc FETCH_SIZE` and one `--pmc WRITE_SIZE` pass (KiB per
+dispatch) and scales each counter by what it reads for a plain elementwise
+copy of known size (the bench's calibration kernel reads and writes
+`copy-bytes` each): factor = counter KiB * 1024 / copy-bytes; HBM bytes of a
+dispatch = counter KiB * 1024 / factor.
 """
 
 import argparse
+import collections
+import csv
 import sqlite3
 import sys
 
 
-def summarize(db, top=25, match=None):
-    con = sqlite3.connect(db)
-    rows = con.execute("select name, count(*), avg(duration), min(duration), max(duration), sum(duration) "
-                       "from kernels group by name order by sum(duration) desc").fetchall()
+def short_name(name):
+    return name.replace("void cloak::(anonymous namespace)::", "").replace("cloak::(anonymous namespace)::", "")
+
+
+def stats_rows(path):
+    if path.endswith(".db"):
+        con = sqlite3.connect(path)
+        rows = con.execute("select name, count(*), avg(duration), min(duration), max(duration), sum(duration) "
+                           "from kernels group by name").fetchall()
+        return [(n, c, a / 1e3, mn / 1e3, mx / 1e3, t / 1e6) for n, c, a, mn, mx, t in rows]
     out = []
+    for r in csv.DictReader(open(path)):
+        out.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+                    float(r["MaxNs"]) / 1e3, float(r["TotalDurationNs"]) / 1e6))
+    return out
+
+
+def print_stats(path, top):
+    rows = sorted(stats_rows(path), key=lambda r: -r[5])[:top]
+    print(f"{'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'total_ms':>10}  kernel")
     for name, n, avg, mn, mx, tot in rows:
-        if match and match not in name:
+        print(f"{n:6d} {avg:10.2f} {mn:10.2f} {mx:10.2f} {tot:10.2f}  {short_name(name)[:120]}")
+
+
+def counter_means(path):
+    d = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        d[(r["Kernel_Name"], r["Grid_Size"])].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in d.items()}, {k: len(v) for k, v in d.items()}
+
+
+def print_pmc(fetch_csv, write_csv, copy_match, copy_bytes):
+    fetch, n = counter_means(fetch_csv)
+    write, _ = counter_means(write_csv)
+    copy = [k for k in fetch if copy_match in k[0]]
+    if not copy:
+        raise SystemExit(f"no dispatch of a kernel matching {copy_match!r}")
+    ck = copy[0]
+    f_fac = fetch[ck] * 1024 / copy_bytes
+    w_fac = write[ck] * 1024 / copy_bytes
+    print(f"calibration kernel: {short_name(ck[0])[:90]} grid {ck[1]} (reads and writes {copy_bytes} B)")
+    print(f"FETCH_SIZE factor {f_fac:.5f}  WRITE_SIZE factor {w_fac:.5f}")
+    print(f"{'calls':>6} {'fetch_KiB':>14} {'write_KiB':>12} {'hbm_read_B':>14} {'hbm_write_B':>12}  kernel (grid)")
+    for k in sorted(fetch, key=lambda k: -fetch[k]):
+        if k == ck:
             continue
-        out.append((name, n, avg / 1e3, mn / 1e3, mx / 1e3, tot / 1e6))
-    return out[:top]
+        rb = fetch[k] * 1024 / f_fac
+        wb = write.get(k, 0.0) * 1024 / w_fac
+        print(f"{n[k]:6d} {fetch[k]:14.1f} {write.get(k, 0.0):12.1f} {rb:14.0f} {wb:12.0f}  "
+              f"{short_name(k[0])[:80]} ({k[1]})")
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("db")
-    ap.add_argument("--top", type=int, default=25)
-    ap.add_argument("--match", default=None)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("path")
+    s.add_argument("--top", type=int, default=30)
+    p = sub.add_parser("pmc")
+    p.add_argument("fetch_csv")
+    p.add_argument("write_csv")
+    p.add_argument("--copy-match", default="MulFunctor")
+    p.add_argument("--copy-bytes", type=int, default=1 << 30)
     a = ap.parse_args(argv)
-    print(f"{'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'total_ms':>10}  kernel")
-    for name, n, avg, mn, mx, tot in summarize(a.db, a.top, a.match):
-        print(f"{n:6d} {avg:10.2f} {mn:10.2f} {mx:10.2f} {tot:10.2f}  {name}")
+    if a.cmd == "stats":
+        print_stats(a.path, a.top)
+    else:
+        print_pmc(a.fetch_csv, a.write_csv, a.copy_match, a.copy_bytes)
 
 
 if __name__ == "__main__":

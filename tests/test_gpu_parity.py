@@ -154,17 +154,26 @@ def test_fp8_layer_vs_fp64(C, M):
     cw.close()
 
 
+def plus_zero(a):
+    """Signed zeros made +0: a dot product whose only nonzero input meets a -0
+    weight sums -0 with the +0 products of the other terms, and the IEEE sum
+    of zeros of opposite sign is +0 (FP8 weights below half the smallest
+    subnormal quantise to -0 as often as to +0)."""
+    a = np.array(a)
+    if a.dtype == np.float32:
+        return np.where(a == 0, np.float32(0), a)
+    return np.where(a == 0x8000, np.uint16(0), a).astype(a.dtype)
+
+
 def one_hot_expected(shapes, ws, scs, t, ks):
     """y[m][n] for x = e_{ks[m]}: the weight itself, rounded like the kernel's output."""
     s = shapes[t]
-    if s[4] == "f32":
-        return np.stack([ws[t][:, k] for k in ks])
-    if s[4] == "bf16":
-        return np.stack([ws[t][:, k] for k in ks])
+    if s[4] in ("f32", "bf16"):
+        return plus_zero(np.stack([ws[t][:, k] for k in ks]))
     # FP8: acc = e4m3(q) exactly, times the f32 row scale (one f32 rounding), then bf16
     q = ON.e4m3_bits_to_f64(ws[t]).astype(np.float32)
     prod = q * scs[t].astype(np.float32)[:, None]
-    return np.stack([ON.f32_to_bf16_bits_rne(prod[:, k]) for k in ks])
+    return plus_zero(np.stack([ON.f32_to_bf16_bits_rne(prod[:, k]) for k in ks]))
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
@@ -187,7 +196,7 @@ def test_one_hot_probes_are_bit_exact(C, dtype):
             x = np.zeros((len(ks), K), np.uint16)
             for m, k in enumerate(ks):
                 x[m, k] = 0x3F80
-        y = from_device(cw.linear(t, to_device_x(x)))
+        y = plus_zero(from_device(cw.linear(t, to_device_x(x))))
         want = one_hot_expected(shapes, ws, scs, t, ks)
         assert np.array_equal(y.view(np.uint8), want.view(np.uint8)), (t, s)
     cw.close()
@@ -326,6 +335,103 @@ def test_prefill_gemm_cloaked_equals_native(C, M):
     assert err <= 1e-2
     cl.close()
     nat.close()
+
+
+@pytest.mark.parametrize("M", [5, 17, 64, 300])
+def test_fp8_mfma_paths_vs_fp64(C, M):
+    # FP8 weights through the MFMA paths (skinny split-K for 5..64 tokens, the
+    # 256x256 GEMM above): widened to BF16 exactly in LDS, row scales applied
+    # after the contraction; K = 1280 / 3456, d_ffn 3456 and the 700-row head
+    # leave ragged row tiles
+    shapes = decoder_shapes(1280, 3456, 256, "fp8", layers=1, extra=[(-1, "head", 700, 1280, "fp8")])
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, 65536, 65536 * 512, seed=29)
+    cw.load(ws, scs)
+    check_linear_all(C, cw, shapes, ws, scs, M)
+    cw.close()
+
+
+def one_hot_expected_a8(shapes, ws, scs, t, ks):
+    """x = e_k through FP8 x FP8: the row quantises to code 448 with scale
+    fl(1/448); the kernel forms ((448 q_w) * s_x) * s_w in binary32."""
+    sx = np.float32(1.0) / np.float32(448.0)
+    q = ON.e4m3_bits_to_f64(ws[t]).astype(np.float32)
+    acc = np.float32(448.0) * q
+    prod = (acc * sx).astype(np.float32) * scs[t].astype(np.float32)[:, None]
+    return plus_zero(np.stack([ON.f32_to_bf16_bits_rne(prod[:, k]) for k in ks]))
+
+
+@pytest.mark.parametrize("M", [40, 300])
+def test_fp8_mfma_one_hot_bit_exact(C, M):
+    import torch
+    shapes = decoder_shapes(1280, 3456, 256, "fp8", layers=1)
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, 65536, 65536 * 512, seed=37)
+    cw.load(ws, scs)
+    rng = np.random.Generator(np.random.PCG64(9))
+    for t, s in enumerate(shapes):
+        K = s[3]
+        ks = list(rng.choice(K, size=M, replace=False))
+        ks[0], ks[-1] = 0, K - 1
+        x = np.zeros((M, K), np.uint16)
+        for m, k in enumerate(ks):
+            x[m, k] = 0x3F80
+        need = C.cloak_ws_bytes(cw.layout, C.CLOAK_OP_LINEAR, t, M)
+        ws_buf = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+        y = torch.empty((M, s[2]), dtype=torch.bfloat16, device="cuda")
+        C.cloak_linear(cw.layout, cw.pool, t, to_device_x(x), M, y, ws_buf, ws_buf.numel())
+        want = one_hot_expected(shapes, ws, scs, t, ks) if M <= 64 else one_hot_expected_a8(shapes, ws, scs, t, ks)
+        assert np.array_equal(plus_zero(from_device(y)), want), (t, s)
+    cw.close()
+
+
+def test_quantize_fp8_codes_and_scales_bit_exact(C):
+    import torch
+    rng = np.random.Generator(np.random.PCG64(51))
+    for M, K, ld in [(9, 1280, 1280), (5, 333, 400), (3, 27648, 27648), (1, 8, 8)]:
+        x32 = (rng.standard_normal((M, ld)) * rng.uniform(0.01, 50, (M, 1))).astype(np.float32)
+        x32[M // 2] = 0.0                         # an all-zero row
+        x32[0, :min(K, 16)] = [2.0 ** -12, -448.0, 1e-30, 3.0, -0.0, 96.0, 1.0, 0.5, 7.0, 6.5, 0.0, 1.0,
+                               2.0, 2.25, -2.5, 2.75][:min(K, 16)]
+        xb = synth.f32_to_bf16_rne(x32)
+        q = torch.empty((M, K), dtype=torch.uint8, device="cuda")
+        sc = torch.empty(M, dtype=torch.float32, device="cuda")
+        C.cloak_quantize_fp8(to_device_x(xb)[:, :K], M, q, sc)
+        wq, ws_ = ON.quantize_rows_e4m3(synth.bf16_to_f32(xb[:, :K]))
+        assert np.array_equal(q.cpu().numpy(), wq), (M, K)
+        assert np.array_equal(sc.cpu().numpy().view(np.uint32), ws_.view(np.uint32)), (M, K)
+
+
+@pytest.mark.parametrize("M", [65, 300])
+def test_fp8_x_fp8_gemm_vs_oracle(C, M):
+    # above 64 tokens FP8 weights run FP8 x FP8 MFMA on per-token quantised
+    # activations: against the oracle's product of the same quantised
+    # activations the only differences are FP32 summation order and the bf16
+    # output rounding (1e-2); against unquantised FP64 the FP8 bar (5e-2)
+    shapes = decoder_shapes(1280, 3456, 256, "fp8", layers=1)
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, 65536, 65536 * 512, seed=43)
+    cw.load(ws, scs)
+    worst_q, worst_u = 0.0, 0.0
+    for t, s in enumerate(shapes):
+        x_np = synth.activations(M, s[3], "bf16", seed=900 + t)
+        y = values_f64(from_device(cw.linear(t, to_device_x(x_np))))
+        # (a down projection quantises after its gather through pi: a row's
+        # scale and each element's code do not depend on the column order)
+        xq = ON.fp8_activations_f64(*ON.quantize_rows_e4m3(synth.bf16_to_f32(x_np)))
+        w = w64(shapes, ws, scs, t)
+        eq = ON.normwise_err(y, ON.linear(xq, w))
+        eu = ON.normwise_err(y, ON.linear(values_f64(x_np), w))
+        worst_q, worst_u = max(worst_q, eq), max(worst_u, eu)
+        assert eq <= 1e-2, (t, s, eq)
+        assert eu <= TOL["fp8"], (t, s, eu)
+    x_np = synth.activations(M, 1280, "bf16", seed=990)
+    y = values_f64(from_device(cw.mlp(0, to_device_x(x_np))))
+    ref, _ = ON.swiglu_ffn(values_f64(x_np), w64(shapes, ws, scs, 4), w64(shapes, ws, scs, 5), w64(shapes, ws, scs, 6))
+    eu = ON.normwise_err(y, ref)
+    assert eu <= TOL["fp8"], eu
+    print(f"fp8 x fp8 M={M}: vs quantised-activation oracle {worst_q:.2e}, vs FP64 {worst_u:.2e}, mlp {eu:.2e}")
+    cw.close()
 
 
 def test_prefill_full_layer4096_sampled_tokens(C):
