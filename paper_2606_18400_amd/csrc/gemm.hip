@@ -164,140 +164,43 @@ struct WTile {
   }
 };
 
-// F8: FP8 weights; A8: FP8 x FP8 MFMA on quantised activations (needs F8)
-template <bool TR, int EPI, bool F8, bool A8>
-__global__ __launch_bounds__(NTHREADS, 1) void gemm_kernel(const GemmArgs a) {
-  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  // buffer b: X tile at smem + 2b*TILE_BYTES, W tile right after it
-  auto lds_x = [&](int buf) { return smem + buf * 2 * TILE_BYTES; };
-  auto lds_w = [&](int buf) { return smem + buf * 2 * TILE_BYTES + TILE_BYTES; };
-
-  // XCD-aware tile order: consecutive workgroup ids go to different XCDs, so
-  // give each XCD a contiguous run of tiles of a grouped order (groups of
-  // GROUP_M token tiles, token tile fastest inside a group).  The 32
-  // workgroups an XCD runs at once then cover about 8 token tiles x 4 weight
-  // tiles, and each X and W slice they fetch serves 4 and 8 of them from the
-  // XCD's L2, instead of 32 token tiles each fetching its own X slice.
+// XCD-aware tile order: consecutive workgroup ids go to different XCDs, so
+// give each XCD a contiguous run of tiles of a grouped order (groups of
+// GROUP_M token tiles, token tile fastest inside a group).  The 32
+// workgroups an XCD runs at once then cover about 8 token tiles x 4 weight
+// tiles, and each X and W slice they fetch serves 4 and 8 of them from the
+// XCD's L2, instead of 32 token tiles each fetching its own X slice.
+__device__ inline bool tile_coords(const GemmArgs& a, int& tile_m, int& tile_n) {
   constexpr int GROUP_M = 8;
   const int ntiles = a.tiles_m * a.tiles_n;
   const int b = blockIdx.x;
   const int per_xcd = (ntiles + 7) / 8;
   const int xcd = b % 8, slot = b / 8;
   const int t_id = xcd * per_xcd + slot;
-  if (t_id >= ntiles) return;
+  if (t_id >= ntiles) return false;
   const int per_group = GROUP_M * a.tiles_n;
   const int first_m = (t_id / per_group) * GROUP_M;
   const int group_m = min(a.tiles_m - first_m, GROUP_M);
   const int in_group = t_id % per_group;
-  const int tile_m = first_m + in_group % group_m;
-  const int tile_n = in_group / group_m;
+  tile_m = first_m + in_group % group_m;
+  tile_n = in_group / group_m;
+  return true;
+}
 
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+// Tile rows of a wave's NB row blocks.  SwiGLU: two gate blocks, then the two
+// up blocks of the same hidden units.
+template <int EPI>
+__device__ inline void wave_rows(int wn, int (&wrow)[NB]) {
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+    wrow[nb] = EPI == kSwiGLU ? (nb < NB / 2 ? 0 : BN / 2) + wn * (WN / 2) + (nb % (NB / 2)) * 16 : wn * WN + nb * 16;
+}
 
-  // activation slots: rows (tid >> 3) + 64 i, 16 B chunk (tid & 7); a K step
-  // is 128 bytes of a row in both modes
-  const int ch = tid & 7;
-  const uint8_t* xrow[LOADS];
-  bool xok[LOADS];
-  const int64_t ldx_bytes = A8 ? a.ldx : a.ldx * 2;
-#pragma unroll
-  for (int i = 0; i < LOADS; ++i) {
-    const int tr = (tid >> 3) + 64 * i;
-    const int m = tile_m * BM + tr;
-    xok[i] = m < a.M;
-    xrow[i] = reinterpret_cast<const uint8_t*>(a.x) + int64_t(xok[i] ? m : 0) * ldx_bytes + ch * 16;
-  }
-  // a8 reads the FP8 weight bytes as they are (128 elements per K step)
-  WTile<BN, NTHREADS, F8 && !A8> wt;
-  wt.init(tid, a.pool, a.seg, a.row_bytes,
-          [&](int tr, int& seg, int& n) { return tile_row<EPI>(a, tile_n, tr, seg, n); });
-
-  u32x4 gx[LOADS];
-  auto gload = [&](int kb) {
-#pragma unroll
-    for (int i = 0; i < LOADS; ++i)
-      gx[i] = xok[i] ? *reinterpret_cast<const u32x4*>(xrow[i] + int64_t(kb) * ROWB) : u32x4{0u, 0u, 0u, 0u};
-    wt.template load<TR>(a.phi, a.log2_page, kb);
-  };
-  auto swrite = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < LOADS; ++i) {
-      const int tr = (tid >> 3) + 64 * i;
-      *reinterpret_cast<u32x4*>(lds_x(buf) + swz(tr, ch)) = gx[i];
-    }
-    wt.store(lds_w(buf));
-  };
-
-  f32x4 acc[NB][MB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i)
-#pragma unroll
-    for (int j = 0; j < MB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  // tile rows of this wave's row blocks
-  int wrow[NB];
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    if (EPI == kSwiGLU) {
-      // two gate blocks, then the two up blocks of the same hidden units
-      wrow[nb] = (nb < NB / 2 ? 0 : BN / 2) + wn * (WN / 2) + (nb % (NB / 2)) * 16;
-    } else {
-      wrow[nb] = wn * WN + nb * 16;
-    }
-  }
-
-  const int nk = a.K / (A8 ? 2 * BK : BK);
-  gload(0);
-  swrite(0);
-  __syncthreads();
-  for (int kb = 0; kb < nk; ++kb) {
-    const int buf = kb & 1;
-    if (kb + 1 < nk) gload(kb + 1);
-    // weight fragments of the wave's NB row blocks stay in registers while
-    // the MB token fragments are read one at a time
-    if constexpr (A8) {
-      const int c0 = 2 * (lane >> 4);
-      auto frag = [&](const uint8_t* tile, int r) {
-        const u32x4 lo = *reinterpret_cast<const u32x4*>(tile + swz(r, c0));
-        const u32x4 hi = *reinterpret_cast<const u32x4*>(tile + swz(r, c0 + 1));
-        return i32x8{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
-      };
-      i32x8 fa[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) fa[nb] = frag(lds_w(buf), wrow[nb] + (lane & 15));
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const i32x8 fb = frag(lds_x(buf), wm * WM + mb * 16 + (lane & 15));
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          acc[nb][mb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fa[nb], fb, acc[nb][mb], 0, 0, 0, 0, 0, 0);
-      }
-    } else {
-#pragma unroll
-      for (int s = 0; s < BK / 32; ++s) {
-        const int chunk = s * 4 + (lane >> 4);
-        bf16x8_t fa[NB];
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          fa[nb] = *reinterpret_cast<const bf16x8_t*>(lds_w(buf) + swz(wrow[nb] + (lane & 15), chunk));
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-          const bf16x8_t fb =
-              *reinterpret_cast<const bf16x8_t*>(lds_x(buf) + swz(wm * WM + mb * 16 + (lane & 15), chunk));
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb)
-            acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[nb], fb, acc[nb][mb], 0, 0, 0);
-        }
-      }
-    }
-    if (kb + 1 < nk) swrite(buf ^ 1);
-    __syncthreads();
-  }
-
-  // ---------------------------------------------------------------- epilogue
+// Results of a wave's NB x MB blocks: lane l of block (nb, mb) holds rows
+// wrow[nb] + 4*(l/16) + r (r = 0..3) of token mb*16 + l%16.
+template <int EPI, bool A8>
+__device__ inline void gemm_epilogue(const GemmArgs& a, const f32x4 (&acc)[NB][MB], int tile_m, int tile_n, int wm,
+                                     int wn, const int (&wrow)[NB], int lane) {
   const int r4 = 4 * (lane >> 4);
   const int tok = lane & 15;
   if constexpr (EPI == kStore) {
@@ -369,6 +272,232 @@ __global__ __launch_bounds__(NTHREADS, 1) void gemm_kernel(const GemmArgs a) {
       }
     }
   }
+}
+
+// F8: FP8 weights; A8: FP8 x FP8 MFMA on quantised activations (needs F8)
+template <bool TR, int EPI, bool F8, bool A8>
+__global__ __launch_bounds__(NTHREADS, 1) void gemm_kernel(const GemmArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  // buffer b: X tile at smem + 2b*TILE_BYTES, W tile right after it
+  auto lds_x = [&](int buf) { return smem + buf * 2 * TILE_BYTES; };
+  auto lds_w = [&](int buf) { return smem + buf * 2 * TILE_BYTES + TILE_BYTES; };
+
+  int tile_m, tile_n;
+  if (!tile_coords(a, tile_m, tile_n)) return;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+
+  // activation slots: rows (tid >> 3) + 64 i, 16 B chunk (tid & 7); a K step
+  // is 128 bytes of a row in both modes
+  const int ch = tid & 7;
+  const uint8_t* xrow[LOADS];
+  bool xok[LOADS];
+  const int64_t ldx_bytes = A8 ? a.ldx : a.ldx * 2;
+#pragma unroll
+  for (int i = 0; i < LOADS; ++i) {
+    const int tr = (tid >> 3) + 64 * i;
+    const int m = tile_m * BM + tr;
+    xok[i] = m < a.M;
+    xrow[i] = reinterpret_cast<const uint8_t*>(a.x) + int64_t(xok[i] ? m : 0) * ldx_bytes + ch * 16;
+  }
+  // a8 reads the FP8 weight bytes as they are (128 elements per K step)
+  WTile<BN, NTHREADS, F8 && !A8> wt;
+  wt.init(tid, a.pool, a.seg, a.row_bytes,
+          [&](int tr, int& seg, int& n) { return tile_row<EPI>(a, tile_n, tr, seg, n); });
+
+  u32x4 gx[LOADS];
+  auto gload = [&](int kb) {
+#pragma unroll
+    for (int i = 0; i < LOADS; ++i)
+      gx[i] = xok[i] ? *reinterpret_cast<const u32x4*>(xrow[i] + int64_t(kb) * ROWB) : u32x4{0u, 0u, 0u, 0u};
+    wt.template load<TR>(a.phi, a.log2_page, kb);
+  };
+  auto swrite = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < LOADS; ++i) {
+      const int tr = (tid >> 3) + 64 * i;
+      *reinterpret_cast<u32x4*>(lds_x(buf) + swz(tr, ch)) = gx[i];
+    }
+    wt.store(lds_w(buf));
+  };
+
+  f32x4 acc[NB][MB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < MB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  int wrow[NB];
+  wave_rows<EPI>(wn, wrow);
+
+  const int nk = a.K / (A8 ? 2 * BK : BK);
+  gload(0);
+  swrite(0);
+  __syncthreads();
+  for (int kb = 0; kb < nk; ++kb) {
+    const int buf = kb & 1;
+    if (kb + 1 < nk) gload(kb + 1);
+    // weight fragments of the wave's NB row blocks stay in registers while
+    // the MB token fragments are read one at a time
+    if constexpr (A8) {
+      const int c0 = 2 * (lane >> 4);
+      auto frag = [&](const uint8_t* tile, int r) {
+        const u32x4 lo = *reinterpret_cast<const u32x4*>(tile + swz(r, c0));
+        const u32x4 hi = *reinterpret_cast<const u32x4*>(tile + swz(r, c0 + 1));
+        return i32x8{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
+      };
+      i32x8 fa[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) fa[nb] = frag(lds_w(buf), wrow[nb] + (lane & 15));
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const i32x8 fb = frag(lds_x(buf), wm * WM + mb * 16 + (lane & 15));
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[nb][mb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fa[nb], fb, acc[nb][mb], 0, 0, 0, 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < BK / 32; ++s) {
+        const int chunk = s * 4 + (lane >> 4);
+        bf16x8_t fa[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          fa[nb] = *reinterpret_cast<const bf16x8_t*>(lds_w(buf) + swz(wrow[nb] + (lane & 15), chunk));
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          const bf16x8_t fb =
+              *reinterpret_cast<const bf16x8_t*>(lds_x(buf) + swz(wm * WM + mb * 16 + (lane & 15), chunk));
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[nb], fb, acc[nb][mb], 0, 0, 0);
+        }
+      }
+    }
+    if (kb + 1 < nk) swrite(buf ^ 1);
+    __syncthreads();
+  }
+
+  gemm_epilogue<EPI, A8>(a, acc, tile_m, tile_n, wm, wn, wrow, lane);
+}
+
+// ---------------------------------------------------------------------------
+// BF16 prefill GEMM with direct global -> LDS loads.  The register-staged
+// kernel above can keep only one K step in flight (its staging registers and
+// 128 FP32 accumulators fill the 256 VGPRs of two waves per SIMD), so each
+// K step waits out a full memory round trip.  Here global_load_lds_dwordx4
+// writes each lane's 16 bytes straight into LDS, so no registers are spent
+// on staging and the tile ring can be deeper: DSTAGES stages of 32 K
+// elements (64-byte tile rows, 32 KiB per stage for both operands), loads
+// issued DSTAGES - 1 stages ahead.  A wave's load fills 1 KiB of LDS in lane
+// order (16 rows x 4 chunks), so the XOR swizzle that keeps fragment reads
+// conflict-free is applied on the global side: the lane that fills LDS slot
+// s of tile row r fetches chunk s ^ ((r >> 1) & 3) of that row.  Each lane
+// keeps two fixed weight rows for the whole K loop (cached page
+// translation, as above).  Waits are explicit: before consuming stage kb a
+// lane waits until only the loads of the DMA_AHEAD younger stages remain,
+// then the workgroup barrier makes every lane's stage kb visible and frees
+// the buffer the next stage is loaded into.
+constexpr int DBK = 32;                     // K elements per stage
+constexpr int DROWB = DBK * 2;              // 64 bytes per tile row
+constexpr int DTILE = BM * DROWB;           // 16 KiB per operand per stage
+constexpr int DSTAGES = 4;
+constexpr int DSTAGE_BYTES = 2 * DTILE;
+constexpr int DLOADS = BM / 16 / (NTHREADS / 64);   // 16-row loads per wave per operand (2)
+constexpr int DMA_AHEAD = DSTAGES - 2;      // younger stages still in flight at a wait
+
+__device__ inline int dswz(int row, int chunk) { return row * DROWB + ((chunk ^ ((row >> 1) & 3)) << 4); }
+
+// s_waitcnt vmcnt(N) lgkmcnt(0), expcnt untouched
+template <int N>
+__device__ inline void wait_vm_lgkm0() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (0 << 8) | ((N >> 4) << 14));
+}
+
+template <bool TR, int EPI>
+__global__ __launch_bounds__(NTHREADS, 1) void gemm_dma_kernel(const GemmArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  int tile_m, tile_n;
+  if (!tile_coords(a, tile_m, tile_n)) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+
+  // load slots: tile row 16 * (DLOADS * wave + j) + lane / 4 of both operands
+  const uint8_t* xptr[DLOADS];
+  RowRef wr[DLOADS];
+#pragma unroll
+  for (int j = 0; j < DLOADS; ++j) {
+    const int tr = 16 * (DLOADS * wave + j) + (lane >> 2);
+    const int c = (lane & 3) ^ ((tr >> 1) & 3);
+    const int m = tile_m * BM + tr;
+    // rows past M or past the tensor read row 0 (valid memory); their
+    // results are never stored
+    xptr[j] = reinterpret_cast<const uint8_t*>(a.x) + int64_t(m < a.M ? m : 0) * a.ldx * 2 + c * 16;
+    int seg = 0, n = 0;
+    const bool ok = tile_row<EPI>(a, tile_n, tr, seg, n);
+    wr[j].pool = a.pool;
+    wr[j].vbase = a.seg[seg].vbase;
+    wr[j].rowoff = int64_t(ok ? n : 0) * a.row_bytes + c * 16;
+    wr[j].cvp = -1;
+    wr[j].cbase = 0;
+    wr[j].ok = true;
+  }
+
+  f32x4 acc[NB][MB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < MB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  int wrow[NB];
+  wave_rows<EPI>(wn, wrow);
+
+  // iterations kb < 0 only issue the first DSTAGES - 1 stages
+  const int nk = a.K / DBK;
+  for (int kb = 1 - DSTAGES; kb < nk; ++kb) {
+    if (kb >= 0) {
+      if (kb + DMA_AHEAD < nk)
+        wait_vm_lgkm0<DMA_AHEAD * 2 * DLOADS>();
+      else
+        wait_vm_lgkm0<0>();
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+    }
+    const int ks = kb + DSTAGES - 1;   // stage issued now, into the buffer freed by the barrier
+    if (ks < nk) {
+      uint8_t* base = smem + (ks % DSTAGES) * DSTAGE_BYTES;
+#pragma unroll
+      for (int j = 0; j < DLOADS; ++j) {
+        const int r0 = 16 * (DLOADS * wave + j);
+        const uint8_t* xsrc = xptr[j] + int64_t(ks) * DROWB;
+        const uint8_t* wsrc = row_addr<TR>(a.phi, a.log2_page, wr[j], int64_t(ks) * DROWB);
+        __builtin_amdgcn_global_load_lds(xsrc, base + r0 * DROWB, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(wsrc, base + DTILE + r0 * DROWB, 16, 0, 0);
+      }
+    }
+    if (kb < 0) continue;
+    const uint8_t* xs = smem + (kb % DSTAGES) * DSTAGE_BYTES;
+    const uint8_t* ws = xs + DTILE;
+    const int chunk = lane >> 4;
+    bf16x8_t fa[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+      fa[nb] = *reinterpret_cast<const bf16x8_t*>(ws + dswz(wrow[nb] + (lane & 15), chunk));
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const bf16x8_t fb = *reinterpret_cast<const bf16x8_t*>(xs + dswz(wm * WM + mb * 16 + (lane & 15), chunk));
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[nb], fb, acc[nb][mb], 0, 0, 0);
+    }
+    asm volatile("" ::: "memory");
+  }
+  gemm_epilogue<EPI, false>(a, acc, tile_m, tile_n, wm, wn, wrow, lane);
 }
 
 // x_out[m][j] = x[m][perm[j]]: the activations of a down projection put in
@@ -646,8 +775,8 @@ hipError_t launch_gemm(const GemmArgs& a, bool translate, hipStream_t s) {
     fn = translate ? (sw ? gemm_kernel<true, kSwiGLU, true, false> : gemm_kernel<true, kStore, true, false>)
                    : (sw ? gemm_kernel<false, kSwiGLU, true, false> : gemm_kernel<false, kStore, true, false>);
   else
-    fn = translate ? (sw ? gemm_kernel<true, kSwiGLU, false, false> : gemm_kernel<true, kStore, false, false>)
-                   : (sw ? gemm_kernel<false, kSwiGLU, false, false> : gemm_kernel<false, kStore, false, false>);
+    fn = translate ? (sw ? gemm_dma_kernel<true, kSwiGLU> : gemm_dma_kernel<true, kStore>)
+                   : (sw ? gemm_dma_kernel<false, kSwiGLU> : gemm_dma_kernel<false, kStore>);
   static bool attr_set[16] = {};
   const int key = (translate ? 2 : 0) + (sw ? 1 : 0) + (f8 ? 4 : 0) + (a8 ? 8 : 0);
   if (!attr_set[key]) {
