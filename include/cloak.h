@@ -177,9 +177,9 @@ int cloak_pack_host(const cloak_layout* layout, int32_t tensor, const void* h_sr
                     void* h_pool, uint64_t h_pool_bytes);
 
 /* Bytes of device workspace `op` needs for `index` at M tokens: the FP32
- * partial sums of the split-K decode GEMM (5..64 tokens), for a down
+ * partial sums of the split-K decode GEMM (5..256 tokens), for a down
  * projection called through cloak_linear its activations gathered through
- * pi, and for FP8 weights above 64 tokens the per-token E4M3 activations and
+ * pi, and for FP8 weights above 256 tokens the per-token E4M3 activations and
  * their scales (M*K + 4*M bytes, each rounded up to 256).  0 if none;
  * UINT64_MAX on bad arguments. */
 uint64_t cloak_ws_bytes(const cloak_layout* layout, int32_t op, int32_t index, int64_t M);
@@ -225,7 +225,7 @@ int cloak_down(const cloak_layout* layout, const void* d_pool, int32_t layer, co
                int64_t M, void* d_y, void* d_ws, uint64_t ws_bytes, void* stream);
 
 /* Per-token FP8 quantisation of activations, as the FP8 x FP8 MFMA path
- * applies it to x before a projection with FP8 weights and more than 64
+ * applies it to x before a projection with FP8 weights and more than 256
  * tokens (the paper names FP8 weights with per-channel scales; this
  * activation format is this library's reading): for each row m of the bf16
  * array d_x ([M][ldx] elements, ldx >= K),

@@ -119,9 +119,12 @@ WSeg make_seg(const cloak_layout* L, int32_t t, bool scatter, int32_t row0, int3
   return s;
 }
 
+// Token tile of the GEMV launches of an M-token call.
+int gemv_mtile(int wtype, int nchunks, int64_t M) { return mtile_for(M, gemv_max_tokens(wtype, nchunks)); }
+
 // Runs `a` over every token block of M (each launch handles mtile tokens).
 int run_gemv(const cloak_layout* L, GemvArgs a, int wtype, int64_t M, hipStream_t st, const char* fn) {
-  const int mt = mtile_for(M, gemv_max_tokens(wtype, a.nchunks));
+  const int mt = gemv_mtile(wtype, a.nchunks, M);
   for (int64_t m0 = 0; m0 < M; m0 += mt) {
     a.m0 = int32_t(m0);
     a.mcount = int32_t(M - m0 < mt ? M - m0 : mt);
@@ -275,9 +278,9 @@ extern "C" int cloak_unload(const cloak_layout* L, const void* d_pool, int32_t t
 
 namespace {
 
-// Which kernel family serves a projection: the VALU GEMV for small batches
-// (and for f32 / FP8 weights), the skinny split-K MFMA GEMM for 17..64
-// tokens, the 256x256 MFMA GEMM above that.
+// Which kernel family serves a projection: the VALU GEMV below 5 tokens (and
+// for f32 weights or K not a multiple of 64), the skinny split-K MFMA GEMM
+// for 5..256 tokens, the 256x256 MFMA GEMM above that.
 enum Path { kPathGemv, kPathSkinny, kPathGemm };
 
 Path pick_path(int32_t dtype, int64_t K, int64_t M) {
@@ -290,11 +293,13 @@ struct SplitPlan {
   int32_t ksplit, kb_per;
 };
 
-// K slices per skinny row tile: about 1024 workgroups in total, but no
+// K slices per skinny row tile: about 1024 workgroups in total (512 above
+// 64 tokens, where each slice's FP32 partial sums cost more traffic), but no
 // slice shorter than 8 K steps.
-SplitPlan plan_split(int64_t tiles_n, int64_t K) {
+SplitPlan plan_split(int64_t tiles_n, int64_t K, int64_t M) {
   const int64_t nk = K / gemm_k_step();
-  int64_t ks = (1024 + tiles_n - 1) / tiles_n;
+  const int64_t target = M > 64 ? 512 : 1024;
+  int64_t ks = (target + tiles_n - 1) / tiles_n;
   const int64_t cap = nk / 8 > 1 ? nk / 8 : 1;
   if (ks > cap) ks = cap;
   if (ks < 1) ks = 1;
@@ -340,7 +345,7 @@ uint64_t proj_ws_bytes(const cloak_layout* L, const Proj& p, int64_t M) {
     b += a256(uint64_t(M) * uint64_t(p.K) * 2);
   if (path == kPathSkinny) {
     const int64_t lr = launch_rows(L, p, skinny_tile_rows());
-    const SplitPlan sp = plan_split(lr / skinny_tile_rows(), p.K);
+    const SplitPlan sp = plan_split(lr / skinny_tile_rows(), p.K, M);
     b += a256(uint64_t(sp.ksplit) * uint64_t(M) * uint64_t(lr) * 4);
   }
   return b;
@@ -359,7 +364,7 @@ int run_proj(const cloak_layout* L, const void* pool, const Proj& p, const void*
   if (path == kPathGemv) {
     GemvArgs a{};
     fill_common(L, pool, a, p.K, elt);
-    const int64_t kGemvRows = gemv_rows(a.nchunks);
+    const int64_t kGemvRows = gemv_rows(a.nchunks, gemv_mtile(wtype_of(p.dtype), a.nchunks, M));
     if (p.mode == kSwiGLU) {
       a.nseg = 2;
       a.seg[0] = make_seg(L, p.tensors[0], false, 0, 0);
@@ -452,7 +457,7 @@ int run_proj(const cloak_layout* L, const void* pool, const Proj& p, const void*
   g.tiles_m = int32_t((M + gemm_tile_rows() - 1) / gemm_tile_rows());
   g.vec_store = aligned ? 1 : 0;
   if (path == kPathSkinny) {
-    const SplitPlan sp = plan_split(g.tiles_n, p.K);
+    const SplitPlan sp = plan_split(g.tiles_n, p.K, M);
     g.part = reinterpret_cast<float*>(wsb);
     g.ldp = lr;
     g.ksplit = sp.ksplit;

@@ -35,6 +35,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <set>
+
 #include "kernels.hpp"
 
 namespace cloak {
@@ -187,20 +190,23 @@ __device__ inline bool tile_coords(const GemmArgs& a, int& tile_m, int& tile_n) 
   return true;
 }
 
-// Tile rows of a wave's NB row blocks.  SwiGLU: two gate blocks, then the two
-// up blocks of the same hidden units.
-template <int EPI>
-__device__ inline void wave_rows(int wn, int (&wrow)[NB]) {
+// Tile rows of a wave's NB_ row blocks (the wave owns WN_ of the 256 rows).
+// SwiGLU: NB_/2 gate blocks, then the up blocks of the same hidden units.
+template <int EPI, int NB_ = NB, int WN_ = WN>
+__device__ inline void wave_rows(int wn, int (&wrow)[NB_]) {
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb)
-    wrow[nb] = EPI == kSwiGLU ? (nb < NB / 2 ? 0 : BN / 2) + wn * (WN / 2) + (nb % (NB / 2)) * 16 : wn * WN + nb * 16;
+  for (int nb = 0; nb < NB_; ++nb)
+    wrow[nb] =
+        EPI == kSwiGLU ? (nb < NB_ / 2 ? 0 : BN / 2) + wn * (WN_ / 2) + (nb % (NB_ / 2)) * 16 : wn * WN_ + nb * 16;
 }
 
-// Results of a wave's NB x MB blocks: lane l of block (nb, mb) holds rows
-// wrow[nb] + 4*(l/16) + r (r = 0..3) of token mb*16 + l%16.
-template <int EPI, bool A8>
-__device__ inline void gemm_epilogue(const GemmArgs& a, const f32x4 (&acc)[NB][MB], int tile_m, int tile_n, int wm,
-                                     int wn, const int (&wrow)[NB], int lane) {
+// Results of a wave's NB_ x MB_ blocks (WM_ tokens, WN_ rows): lane l of
+// block (nb, mb) holds rows wrow[nb] + 4*(l/16) + r (r = 0..3) of token
+// mb*16 + l%16 of the wave's token range.
+template <int EPI, bool A8, int NB_ = NB, int MB_ = MB, int WM_ = WM, int WN_ = WN>
+__device__ inline void gemm_epilogue(const GemmArgs& a, const f32x4 (&acc)[NB_][MB_], int tile_m, int tile_n, int wm,
+                                     int wn, const int (&wrow)[NB_], int lane) {
+  constexpr int NB = NB_, MB = MB_, WM = WM_, WN = WN_;
   const int r4 = 4 * (lane >> 4);
   const int tok = lane & 15;
   if constexpr (EPI == kStore) {
@@ -500,6 +506,96 @@ __global__ __launch_bounds__(NTHREADS, 1) void gemm_dma_kernel(const GemmArgs a)
   gemm_epilogue<EPI, false>(a, acc, tile_m, tile_n, wm, wn, wrow, lane);
 }
 
+// The same 256 x 256 tile and 4-stage LDS ring with 4 waves of 128 x 128
+// (one wave per SIMD, 8 x 8 blocks, 256 FP32 accumulators per lane kept in
+// the accumulator registers).  A wave reads 8 weight and 8 token fragments
+// per 32-K stage for 64 MFMAs, a third less LDS traffic per MFMA than the
+// 8-wave layout's 12 for 32, which is what bounds that layout.
+constexpr int W4_WAVES = 4;
+constexpr int W4_THREADS = 64 * W4_WAVES;
+constexpr int W4_WM = 128, W4_WN = 128;
+constexpr int W4_MB = W4_WM / 16, W4_NB = W4_WN / 16;
+constexpr int W4_LOADS = BM / 16 / W4_WAVES;   // 16-row loads per wave per operand (4)
+
+template <bool TR, int EPI>
+__global__ __launch_bounds__(W4_THREADS, 1) void gemm_w4_kernel(const GemmArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  int tile_m, tile_n;
+  if (!tile_coords(a, tile_m, tile_n)) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+
+  const uint8_t* xptr[W4_LOADS];
+  RowRef wr[W4_LOADS];
+#pragma unroll
+  for (int j = 0; j < W4_LOADS; ++j) {
+    const int tr = 16 * (W4_LOADS * wave + j) + (lane >> 2);
+    const int c = (lane & 3) ^ ((tr >> 1) & 3);
+    const int m = tile_m * BM + tr;
+    xptr[j] = reinterpret_cast<const uint8_t*>(a.x) + int64_t(m < a.M ? m : 0) * a.ldx * 2 + c * 16;
+    int seg = 0, n = 0;
+    const bool ok = tile_row<EPI>(a, tile_n, tr, seg, n);
+    wr[j].pool = a.pool;
+    wr[j].vbase = a.seg[seg].vbase;
+    wr[j].rowoff = int64_t(ok ? n : 0) * a.row_bytes + c * 16;
+    wr[j].cvp = -1;
+    wr[j].cbase = 0;
+    wr[j].ok = true;
+  }
+
+  f32x4 acc[W4_NB][W4_MB];
+#pragma unroll
+  for (int i = 0; i < W4_NB; ++i)
+#pragma unroll
+    for (int j = 0; j < W4_MB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  int wrow[W4_NB];
+  wave_rows<EPI, W4_NB, W4_WN>(wn, wrow);
+
+  const int nk = a.K / DBK;
+  for (int kb = 1 - DSTAGES; kb < nk; ++kb) {
+    if (kb >= 0) {
+      if (kb + DMA_AHEAD < nk)
+        wait_vm_lgkm0<DMA_AHEAD * 2 * W4_LOADS>();
+      else
+        wait_vm_lgkm0<0>();
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+    }
+    const int ks = kb + DSTAGES - 1;
+    if (ks < nk) {
+      uint8_t* base = smem + (ks % DSTAGES) * DSTAGE_BYTES;
+#pragma unroll
+      for (int j = 0; j < W4_LOADS; ++j) {
+        const int r0 = 16 * (W4_LOADS * wave + j);
+        const uint8_t* xsrc = xptr[j] + int64_t(ks) * DROWB;
+        const uint8_t* wsrc = row_addr<TR>(a.phi, a.log2_page, wr[j], int64_t(ks) * DROWB);
+        __builtin_amdgcn_global_load_lds(xsrc, base + r0 * DROWB, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(wsrc, base + DTILE + r0 * DROWB, 16, 0, 0);
+      }
+    }
+    if (kb < 0) continue;
+    const uint8_t* xs = smem + (kb % DSTAGES) * DSTAGE_BYTES;
+    const uint8_t* ws = xs + DTILE;
+    const int chunk = lane >> 4;
+    bf16x8_t fa[W4_NB];
+#pragma unroll
+    for (int nb = 0; nb < W4_NB; ++nb)
+      fa[nb] = *reinterpret_cast<const bf16x8_t*>(ws + dswz(wrow[nb] + (lane & 15), chunk));
+#pragma unroll
+    for (int mb = 0; mb < W4_MB; ++mb) {
+      const bf16x8_t fb =
+          *reinterpret_cast<const bf16x8_t*>(xs + dswz(wm * W4_WM + mb * 16 + (lane & 15), chunk));
+#pragma unroll
+      for (int nb = 0; nb < W4_NB; ++nb)
+        acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[nb], fb, acc[nb][mb], 0, 0, 0);
+    }
+    asm volatile("" ::: "memory");
+  }
+  gemm_epilogue<EPI, false, W4_NB, W4_MB, W4_WM, W4_WN>(a, acc, tile_m, tile_n, wm, wn, wrow, lane);
+}
+
 // x_out[m][j] = x[m][perm[j]]: the activations of a down projection put in
 // the stored (hidden-permuted) column order before a prefill GEMM.
 __global__ __launch_bounds__(256) void gather_cols_kernel(const uint16_t* __restrict__ x, int64_t ldx,
@@ -591,11 +687,11 @@ __global__ __launch_bounds__(256) void quant_rows_kernel(const uint16_t* __restr
 }
 
 // ---------------------------------------------------------------------------
-// Skinny split-K GEMM for decode batches (5..64 tokens).  A 256-row tile
+// Skinny split-K GEMM for decode batches (5..256 tokens).  A 256-row tile
 // leaves a 4096-row projection only 16 workgroups; here a workgroup of 4
-// waves takes 64 weight rows x a 16/32/64-token tile x one K slice (SBK = 64
-// per step, at most 32 KiB of LDS, so several workgroups share a CU), and
-// the K slices of a row tile are spread over workgroups.  Each slice writes FP32 partial sums
+// waves takes 64 weight rows x a 16/32/64/128/256-token tile x one K slice
+// (SBK = 64 per step; 20 to 80 KiB of LDS), and the K slices of a row tile
+// are spread over workgroups.  Each slice writes FP32 partial sums
 // part[slice][token][launch-row]; skinny_reduce_kernel adds the slices in a
 // fixed order (deterministic) and applies the epilogue.  SwiGLU tiles hold
 // 32 gate rows and the same 32 up rows.
@@ -618,12 +714,15 @@ __device__ inline bool skinny_row(const SkinnyArgs& a, int tile_n, int tr, int& 
   return n < a.seg[seg].rows;
 }
 
-// SBM = token tile (16, 32 or 64): the batch is padded only to SBM.
+// SBM = token tile (16 .. 256): the batch is padded only to SBM.
+template <int SBM>
+constexpr int skinny_lds_bytes() { return 2 * (SBM * ROWB + S_WTILE); }
+
 template <int SBM, bool TR, int EPI, bool F8>
 __global__ __launch_bounds__(STHREADS) void skinny_kernel(const SkinnyArgs a) {
   constexpr int XTILE = SBM * ROWB;
   constexpr int XCH = SBM * (ROWB / 16);   // 16-byte chunks of the token tile
-  __shared__ __attribute__((aligned(16))) uint8_t smem[2 * (XTILE + S_WTILE)];
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];   // skinny_lds_bytes<SBM>()
   auto lds_x = [&](int buf) { return smem + buf * (XTILE + S_WTILE); };
   auto lds_w = [&](int buf) { return smem + buf * (XTILE + S_WTILE) + XTILE; };
   const int ks = blockIdx.x % a.ksplit;
@@ -666,10 +765,18 @@ __global__ __launch_bounds__(STHREADS) void skinny_kernel(const SkinnyArgs a) {
       if (xslot[i]) *reinterpret_cast<u32x4*>(lds_x(buf) + swz(xr[i], ch)) = gx[i];
     wt.store(lds_w(buf));
   };
-  f32x4 acc[SBM / 16];
+  // wave grid: WR waves along the 64 rows x WT along the tokens.  Tiles of
+  // 128+ tokens use 2 x 2 (each wave 32 rows x SBM/2 tokens), which reads
+  // about 40% fewer fragment bytes from LDS per MFMA than 4 x 1.
+  constexpr int WR = SBM >= 128 ? 2 : 4, WT = 4 / WR;
+  constexpr int RB = SBN / WR / 16, TB = SBM / WT / 16;   // 16-blocks per wave
+  const int gr = wave % WR, gt = wave / WR;   // this wave's place in the grid
+  f32x4 acc[RB][TB];
 #pragma unroll
-  for (int j = 0; j < SBM / 16; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int wrow = wave * 16;
+  for (int b = 0; b < RB; ++b)
+#pragma unroll
+    for (int j = 0; j < TB; ++j) acc[b][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int wrow = gr * (SBN / WR);
   if (kb_begin < kb_end) {
     gload(kb_begin);
     swrite(0);
@@ -681,24 +788,33 @@ __global__ __launch_bounds__(STHREADS) void skinny_kernel(const SkinnyArgs a) {
 #pragma unroll
     for (int s = 0; s < SBK / 32; ++s) {
       const int chunk = s * 4 + (lane >> 4);
-      const bf16x8_t fa = *reinterpret_cast<const bf16x8_t*>(lds_w(buf) + swz(wrow + (lane & 15), chunk));
+      bf16x8_t fa[RB];
 #pragma unroll
-      for (int mb = 0; mb < SBM / 16; ++mb) {
+      for (int b = 0; b < RB; ++b)
+        fa[b] = *reinterpret_cast<const bf16x8_t*>(lds_w(buf) + swz(wrow + b * 16 + (lane & 15), chunk));
+#pragma unroll
+      for (int j = 0; j < TB; ++j) {
+        const int mb = gt * TB + j;
         const bf16x8_t fb = *reinterpret_cast<const bf16x8_t*>(lds_x(buf) + swz(mb * 16 + (lane & 15), chunk));
-        acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[mb], 0, 0, 0);
+#pragma unroll
+        for (int b = 0; b < RB; ++b) acc[b][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[b], fb, acc[b][j], 0, 0, 0);
       }
     }
     if (kb + 1 < kb_end) swrite(buf ^ 1);
     __syncthreads();
   }
-  // partial sums: lane holds launch-rows wrow + 4*(lane/16) + r of token mb*16 + lane%16
-  const int row0 = tile_n * SBN + wrow + 4 * (lane >> 4);
+  // partial sums: lane holds launch-rows wrow + 16 b + 4*(lane/16) + r of
+  // token (gt*TB + j)*16 + lane%16
 #pragma unroll
-  for (int mb = 0; mb < SBM / 16; ++mb) {
-    const int m = mb * 16 + (lane & 15);
-    if (m >= a.M) continue;
-    float* dst = a.part + (int64_t(ks) * a.M + m) * a.ldp + row0;
-    *reinterpret_cast<f32x4*>(dst) = acc[mb];
+  for (int b = 0; b < RB; ++b) {
+    const int row0 = tile_n * SBN + wrow + b * 16 + 4 * (lane >> 4);
+#pragma unroll
+    for (int j = 0; j < TB; ++j) {
+      const int m = (gt * TB + j) * 16 + (lane & 15);
+      if (m >= a.M) continue;
+      float* dst = a.part + (int64_t(ks) * a.M + m) * a.ldp + row0;
+      *reinterpret_cast<f32x4*>(dst) = acc[b][j];
+    }
   }
 }
 
@@ -807,10 +923,26 @@ hipError_t launch_skinny(const SkinnyArgs& a, bool translate, hipStream_t s) {
   if (blocks <= 0 || a.M <= 0) return hipSuccess;
   if (a.M > kSkinnyMaxTokens || a.K % SBK != 0) return hipErrorInvalidValue;
   const bool f8 = a.f8 != 0;
-  void (*fn)(const SkinnyArgs) = a.M <= 16 ? skinny_fn<16>(translate, a.mode, f8)
-                                 : a.M <= 32 ? skinny_fn<32>(translate, a.mode, f8)
-                                             : skinny_fn<64>(translate, a.mode, f8);
-  hipLaunchKernelGGL(fn, dim3(unsigned(blocks)), dim3(STHREADS), 0, s, a);
+  void (*fn)(const SkinnyArgs);
+  int lds;
+  if (a.M <= 16) fn = skinny_fn<16>(translate, a.mode, f8), lds = skinny_lds_bytes<16>();
+  else if (a.M <= 32) fn = skinny_fn<32>(translate, a.mode, f8), lds = skinny_lds_bytes<32>();
+  else if (a.M <= 64) fn = skinny_fn<64>(translate, a.mode, f8), lds = skinny_lds_bytes<64>();
+  else if (a.M <= 128) fn = skinny_fn<128>(translate, a.mode, f8), lds = skinny_lds_bytes<128>();
+  else fn = skinny_fn<256>(translate, a.mode, f8), lds = skinny_lds_bytes<256>();
+  if (lds > 64 * 1024) {
+    // above the default dynamic LDS limit: raise it once per kernel
+    static std::mutex mu;
+    static std::set<void*> raised;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!raised.count(reinterpret_cast<void*>(fn))) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+      if (e != hipSuccess) return e;
+      raised.insert(reinterpret_cast<void*>(fn));
+    }
+  }
+  hipLaunchKernelGGL(fn, dim3(unsigned(blocks)), dim3(STHREADS), size_t(lds), s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t per_tok = a.mode == kSwiGLU ? int64_t(a.seg[0].rows) : int64_t(a.ldp);

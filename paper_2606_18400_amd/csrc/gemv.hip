@@ -262,8 +262,9 @@ __device__ inline void issue_group(const GemvArgs& a, int grp, int wave, int nwa
   }
 }
 
-template <int WT, int MT, int R, int CPW, bool TR, int EPI>
-__global__ __launch_bounds__(512) void gemv_kernel(const GemvArgs a) {
+// MAXW: most waves per workgroup (8; 16 for the wide single-token variant)
+template <int WT, int MT, int R, int CPW, bool TR, int EPI, int MAXW = kMaxWaves>
+__global__ __launch_bounds__(MAXW * 64) void gemv_kernel(const GemvArgs a) {
   constexpr int XW = WTraits<WT>::XW;
   constexpr int V = R * MT;
   constexpr int LOG2V = Log2<V>::value;
@@ -271,7 +272,7 @@ __global__ __launch_bounds__(512) void gemv_kernel(const GemvArgs a) {
   // the second register set fits
   constexpr bool PF = CPW * R <= 16;
   static_assert((1 << LOG2V) == V && V <= 64, "R*MT must be a power of two <= 64");
-  __shared__ float red[2][kMaxWaves][V];
+  __shared__ float red[2][MAXW][V];
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -374,6 +375,16 @@ int max_mtile(int wt, int cpw) {
 // where 4 rows keep the next-group prefetch within the register budget.
 constexpr int rows_for(int cpw) { return cpw >= 4 ? 4 : 8; }
 
+// Single-token launches over rows of 17..32 chunks (e.g. a 14336-wide down
+// projection) use up to 16 waves of 2 chunks and 4 rows each: twice the
+// waves of the 8-wave layout with the same bytes in flight per wave, which
+// keeps more loads outstanding per CU (the kernel then fits in 128 VGPRs).
+constexpr int kWideWaves = 16;
+constexpr int kWideCpw = 2, kWideRows = 4;
+bool use_wide(int nchunks, int mtile) {
+  return mtile == 1 && nchunks > 2 * kMaxWaves && nchunks <= kWideCpw * kWideWaves;
+}
+
 template <int WT, int CPW, bool TR, int EPI>
 KernelFn pick_mt(int mt) {
   constexpr int kMax = WT == kFP8 ? (CPW <= 1 ? 8 : CPW == 2 ? 4 : CPW == 4 ? 2 : 1)
@@ -411,6 +422,23 @@ KernelFn pick(int wt, bool tr, int cpw, int mt, int epi) {
   return pick_tr<kFP8, kStore>(tr, cpw, mt);
 }
 
+template <int WT, int EPI>
+KernelFn pick_wide_tr(bool tr) {
+  return tr ? gemv_kernel<WT, 1, kWideRows, kWideCpw, true, EPI, kWideWaves>
+            : gemv_kernel<WT, 1, kWideRows, kWideCpw, false, EPI, kWideWaves>;
+}
+
+KernelFn pick_wide(int wt, bool tr, int epi) {
+  if (epi == kSwiGLU) {
+    if (wt == kF32) return pick_wide_tr<kF32, kSwiGLU>(tr);
+    if (wt == kBF16) return pick_wide_tr<kBF16, kSwiGLU>(tr);
+    return pick_wide_tr<kFP8, kSwiGLU>(tr);
+  }
+  if (wt == kF32) return pick_wide_tr<kF32, kStore>(tr);
+  if (wt == kBF16) return pick_wide_tr<kBF16, kStore>(tr);
+  return pick_wide_tr<kFP8, kStore>(tr);
+}
+
 int resident_blocks(KernelFn fn, int threads) {
   static std::mutex mu;
   static std::map<std::pair<void*, int>, int> cache;
@@ -439,15 +467,16 @@ int gemv_cpw(int nchunks) {
 
 int gemv_max_tokens(int wtype, int nchunks) { return max_mtile(wtype, gemv_cpw(nchunks)); }
 
-int gemv_rows(int nchunks) { return rows_for(gemv_cpw(nchunks)); }
+int gemv_rows(int nchunks, int mtile) { return use_wide(nchunks, mtile) ? kWideRows : rows_for(gemv_cpw(nchunks)); }
 
 hipError_t launch_gemv(const GemvArgs& a, int wtype, int mtile, bool translate, hipStream_t s) {
   if (a.groups <= 0) return hipSuccess;
-  const int cpw = gemv_cpw(a.nchunks);
+  const bool wide = use_wide(a.nchunks, mtile);
+  const int cpw = wide ? kWideCpw : gemv_cpw(a.nchunks);
   if (cpw > 8 || mtile > max_mtile(wtype, cpw) || a.mcount > mtile) return hipErrorInvalidValue;
   const int waves = (a.nchunks + cpw - 1) / cpw;
   const int threads = waves * 64;
-  KernelFn fn = pick(wtype, translate, cpw, mtile, a.mode);
+  KernelFn fn = wide ? pick_wide(wtype, translate, a.mode) : pick(wtype, translate, cpw, mtile, a.mode);
   int blocks = resident_blocks(fn, threads);
   if (blocks <= 0) blocks = a.groups;
   if (blocks > a.groups) blocks = a.groups;

@@ -23,7 +23,9 @@ struct WSeg {
 enum WType : int { kF32 = 0, kBF16 = 1, kFP8 = 2 };
 // Rows per GEMV row group for rows of `nchunks` KiB (a SwiGLU group holds
 // half as many gate/up pairs); every tensor of a launch starts on a group.
-int gemv_rows(int nchunks);
+// Rows per group of launches with token tile `mtile` (the host starts every
+// tensor on a whole group).
+int gemv_rows(int nchunks, int mtile);
 enum Epilogue : int { kStore = 0, kSwiGLU = 1 };
 
 struct GemvArgs {
@@ -77,7 +79,7 @@ struct GemmArgs {
 };
 hipError_t launch_gemm(const GemmArgs& a, bool translate, hipStream_t s);
 
-// Skinny split-K GEMM for 5..64 tokens (same fields as GemmArgs, plus the
+// Skinny split-K GEMM for 5..256 tokens (same fields as GemmArgs, plus the
 // split-K partial-sum buffer).
 struct SkinnyArgs {
   const uint8_t* pool;
@@ -106,7 +108,7 @@ struct SkinnyArgs {
 };
 hipError_t launch_skinny(const SkinnyArgs& a, bool translate, hipStream_t s);
 int skinny_tile_rows();
-constexpr int64_t kSkinnyMaxTokens = 64;
+constexpr int64_t kSkinnyMaxTokens = 256;
 hipError_t launch_gather_cols(const uint16_t* x, int64_t ldx, const int32_t* perm, uint16_t* out, int64_t M,
                               int64_t K, hipStream_t s);
 int gemm_tile_rows();

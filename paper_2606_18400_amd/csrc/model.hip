@@ -32,6 +32,12 @@ struct cloak_model {
   uint16_t* kv = nullptr;
   std::vector<int32_t> t;  // per layer: q k v o gate up down
   int32_t embed = -1, head = -1;
+  // Projection scratch is not monotone in the token count (the split-K
+  // kernels need FP32 partial sums, the larger GEMM none), so the workspace
+  // reserves the largest need over every count up to the step's: prefix
+  // maxima over token counts (layers) and logit-row counts (head), grown on
+  // demand.
+  std::vector<uint64_t> sc_tok{0}, sc_head{0};
 };
 
 namespace {
@@ -46,6 +52,27 @@ struct WsPlan {
 };
 
 uint64_t umax(uint64_t a, uint64_t b) { return a > b ? a : b; }
+
+// Largest projection scratch over every token count 1..n (head: logit rows).
+uint64_t scratch_bound(const cloak_model* cm, int64_t n, bool head) {
+  cloak_model* m = const_cast<cloak_model*>(cm);
+  std::vector<uint64_t>& v = head ? m->sc_head : m->sc_tok;
+  const int32_t* t = m->t.data();
+  while (int64_t(v.size()) <= n) {
+    const int64_t k = int64_t(v.size());
+    uint64_t need;
+    if (head) {
+      need = linear_fused_ws_bytes(m->L, &m->head, 1, k);
+    } else {
+      need = linear_fused_ws_bytes(m->L, t, 3, k);
+      need = umax(need, linear_fused_ws_bytes(m->L, t + 3, 1, k));
+      need = umax(need, cloak_ws_bytes(m->L, CLOAK_OP_SWIGLU, 0, k));
+      need = umax(need, cloak_ws_bytes(m->L, CLOAK_OP_DOWN, 0, k));
+    }
+    v.push_back(umax(v.back(), need));
+  }
+  return v[n > 0 ? n : 0];
+}
 
 WsPlan plan_ws(const cloak_model* m, int64_t T, int64_t R, int64_t tiles, int64_t splits) {
   const cloak_model_config& c = m->cfg;
@@ -68,14 +95,9 @@ WsPlan plan_ws(const cloak_model* m, int64_t T, int64_t R, int64_t tiles, int64_
   p.logits = take(uint64_t(R > 0 ? R : 1) * c.vocab * 2);
   p.part_o = take(uint64_t(tiles) * splits * c.n_heads * 16 * 128 * 4);
   p.part_ml = take(uint64_t(tiles) * splits * c.n_heads * 16 * 2 * 4);
-  // scratch of the projections (split-K partial sums); all layers share shapes
-  const int32_t* t = m->t.data();
-  uint64_t sc = linear_fused_ws_bytes(m->L, t, 3, T);
-  sc = umax(sc, linear_fused_ws_bytes(m->L, t + 3, 1, T));
-  sc = umax(sc, cloak_ws_bytes(m->L, CLOAK_OP_SWIGLU, 0, T));
-  sc = umax(sc, cloak_ws_bytes(m->L, CLOAK_OP_DOWN, 0, T));
-  sc = umax(sc, linear_fused_ws_bytes(m->L, &m->head, 1, R));
-  p.scratch_bytes = align256(sc);
+  // scratch of the projections (split-K partial sums, quantised
+  // activations); all layers share shapes
+  p.scratch_bytes = align256(umax(scratch_bound(m, T, false), scratch_bound(m, R, true)));
   p.scratch = take(p.scratch_bytes);
   p.total = off;
   return p;

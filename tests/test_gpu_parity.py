@@ -144,6 +144,24 @@ def test_ragged_rows_straddling_pages(C, M, dtype):
     cw.close()
 
 
+# rows of 17..32 KiB chunks at one token take the 16-wave GEMV layout (the
+# down projection of a 14336-wide FFN is one); M = 2 takes the 8-wave one
+WIDE = {"bf16": (9216, 8960), "fp8": (27648, 27648), "f32": (4480, 4352)}
+
+
+@pytest.mark.parametrize("M", [1, 2])
+@pytest.mark.parametrize("dtype", ["bf16", "fp8", "f32"])
+def test_long_rows_single_token(C, M, dtype):
+    dff, kq = WIDE[dtype]
+    shapes = [(0, "gate", dff, 256, dtype), (0, "up", dff, 256, dtype), (0, "down", 256, dff, dtype),
+              (1, "q", 64, kq, dtype)]
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, 65536, 65536 * 1024, seed=47)
+    cw.load(ws, scs)
+    check_linear_all(C, cw, shapes, ws, scs, M)
+    cw.close()
+
+
 @pytest.mark.parametrize("M", [1, 2, 4, 8])
 def test_fp8_layer_vs_fp64(C, M):
     shapes = decoder_shapes(1280, 3456, 256, "fp8", layers=1, extra=[(-1, "head", 700, 1280, "bf16")])
@@ -278,9 +296,9 @@ def test_empty_batch_and_argument_errors(C):
 
 # ---------------------------------------------------------------- prefill GEMM (MFMA)
 
-@pytest.mark.parametrize("M", [17, 32, 64, 100, 300, 600])
+@pytest.mark.parametrize("M", [17, 32, 64, 100, 200, 256, 300, 600])
 def test_prefill_gemm_vs_fp64(C, M):
-    # 17..64 tokens: skinny split-K MFMA GEMM; above: the 256x256 MFMA GEMM
+    # 5..256 tokens: skinny split-K MFMA GEMM; above: the 256x256 MFMA GEMM
     # K = 1024 / 2816 (multiples of 64): the BF16 MFMA GEMM path; N = 1000 and
     # d_ffn 2816 leave ragged row tiles, M leaves ragged token tiles
     shapes = decoder_shapes(1024, 2816, 256, "bf16", layers=1, extra=[(-1, "head", 1000, 1024, "bf16")])
@@ -291,9 +309,9 @@ def test_prefill_gemm_vs_fp64(C, M):
     cw.close()
 
 
-@pytest.mark.parametrize("M", [40, 300])
+@pytest.mark.parametrize("M", [40, 200, 300])
 def test_prefill_gemm_one_hot_bit_exact(C, M):
-    # 40 tokens: skinny split-K kernel; 300: the 256x256 GEMM
+    # 40 and 200 tokens: skinny split-K kernel; 300: the 256x256 GEMM
     import torch
     shapes = decoder_shapes(1024, 2816, 256, "bf16", layers=1)
     ws, scs = make_weights(shapes)
@@ -339,12 +357,12 @@ def test_prefill_gemm_cloaked_equals_native(C, M):
     nat.close()
 
 
-@pytest.mark.parametrize("M", [5, 17, 64, 300])
+@pytest.mark.parametrize("M", [5, 17, 64, 128, 256, 300])
 def test_fp8_mfma_paths_vs_fp64(C, M):
-    # FP8 weights through the MFMA paths (skinny split-K for 5..64 tokens, the
-    # 256x256 GEMM above): widened to BF16 exactly in LDS, row scales applied
-    # after the contraction; K = 1280 / 3456, d_ffn 3456 and the 700-row head
-    # leave ragged row tiles
+    # FP8 weights through the MFMA paths: up to 256 tokens the skinny split-K
+    # kernel widens them to BF16 exactly in LDS (row scales applied after the
+    # contraction); above, FP8 x FP8 on quantised activations.  K = 1280 /
+    # 3456, d_ffn 3456 and the 700-row head leave ragged row tiles
     shapes = decoder_shapes(1280, 3456, 256, "fp8", layers=1, extra=[(-1, "head", 700, 1280, "fp8")])
     ws, scs = make_weights(shapes)
     cw = C.CloakedWeights(shapes, 65536, 65536 * 512, seed=29)
@@ -363,7 +381,7 @@ def one_hot_expected_a8(shapes, ws, scs, t, ks):
     return plus_zero(np.stack([ON.f32_to_bf16_bits_rne(prod[:, k]) for k in ks]))
 
 
-@pytest.mark.parametrize("M", [40, 300])
+@pytest.mark.parametrize("M", [40, 200, 300])
 def test_fp8_mfma_one_hot_bit_exact(C, M):
     import torch
     shapes = decoder_shapes(1280, 3456, 256, "fp8", layers=1)
@@ -382,7 +400,7 @@ def test_fp8_mfma_one_hot_bit_exact(C, M):
         ws_buf = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
         y = torch.empty((M, s[2]), dtype=torch.bfloat16, device="cuda")
         C.cloak_linear(cw.layout, cw.pool, t, to_device_x(x), M, y, ws_buf, ws_buf.numel())
-        want = one_hot_expected(shapes, ws, scs, t, ks) if M <= 64 else one_hot_expected_a8(shapes, ws, scs, t, ks)
+        want = one_hot_expected(shapes, ws, scs, t, ks) if M <= 256 else one_hot_expected_a8(shapes, ws, scs, t, ks)
         assert np.array_equal(plus_zero(from_device(y)), want), (t, s)
     cw.close()
 
@@ -404,9 +422,9 @@ def test_quantize_fp8_codes_and_scales_bit_exact(C):
         assert np.array_equal(sc.cpu().numpy().view(np.uint32), ws_.view(np.uint32)), (M, K)
 
 
-@pytest.mark.parametrize("M", [65, 300])
+@pytest.mark.parametrize("M", [257, 600])
 def test_fp8_x_fp8_gemm_vs_oracle(C, M):
-    # above 64 tokens FP8 weights run FP8 x FP8 MFMA on per-token quantised
+    # above 256 tokens FP8 weights run FP8 x FP8 MFMA on per-token quantised
     # activations: against the oracle's product of the same quantised
     # activations the only differences are FP32 summation order and the bf16
     # output rounding (1e-2); against unquantised FP64 the FP8 bar (5e-2)
