@@ -204,13 +204,13 @@ __device__ inline void wave_rows(int wn, int (&wrow)[NB_]) {
 // block (nb, mb) holds rows wrow[nb] + 4*(l/16) + r (r = 0..3) of token
 // mb*16 + l%16 of the wave's token range.
 template <int EPI, bool A8, int NB_ = NB, int MB_ = MB, int WM_ = WM, int WN_ = WN>
-__device__ inline void gemm_epilogue(const GemmArgs& a, const f32x4 (&acc)[NB_][MB_], int tile_m, int tile_n, int wm,
+__device__ __forceinline__ void gemm_epilogue(const GemmArgs& a, const f32x4 (&acc)[NB_][MB_], int tile_m, int tile_n, int wm,
                                      int wn, const int (&wrow)[NB_], int lane) {
   constexpr int NB = NB_, MB = MB_, WM = WM_, WN = WN_;
   const int r4 = 4 * (lane >> 4);
   const int tok = lane & 15;
   if constexpr (EPI == kStore) {
-#pragma unroll
+#pragma clang loop unroll(full)
     for (int nb = 0; nb < NB; ++nb) {
       const int tr0 = wrow[nb] + r4;  // first of this lane's 4 tile rows
       int seg, n0;
@@ -220,7 +220,7 @@ __device__ inline void gemm_epilogue(const GemmArgs& a, const f32x4 (&acc)[NB_][
       const int32_t* perm = a.seg[seg].out_perm;
       const float* scale = a.seg[seg].scale;
       const int out_off = a.seg[seg].out_off;
-#pragma unroll
+#pragma clang loop unroll(full)
       for (int mb = 0; mb < MB; ++mb) {
         const int m = tile_m * BM + wm * WM + mb * 16 + tok;
         if (m >= a.M) continue;
@@ -236,7 +236,7 @@ __device__ inline void gemm_epilogue(const GemmArgs& a, const f32x4 (&acc)[NB_][
           hi = uint32_t(f32_to_bf16_rne(v[2] * s2)) | (uint32_t(f32_to_bf16_rne(v[3] * s3)) << 16);
           *reinterpret_cast<uint2*>(yrow + n0) = make_uint2(lo, hi);
         } else {
-#pragma unroll
+#pragma clang loop unroll(full)
           for (int r = 0; r < 4; ++r) {
             const int n = n0 + r;
             if (n < rows) yrow[perm ? perm[n] : n] = f32_to_bf16_rne(v[r] * (scale ? scale[n] : 1.f));
@@ -248,18 +248,18 @@ __device__ inline void gemm_epilogue(const GemmArgs& a, const f32x4 (&acc)[NB_][
     const float* sg = a.seg[0].scale;
     const float* su = a.seg[1].scale;
     const int dff = a.seg[0].rows;
-#pragma unroll
+#pragma clang loop unroll(full)
     for (int nb = 0; nb < NB / 2; ++nb) {
       const int j0 = tile_n * (BN / 2) + wn * (WN / 2) + nb * 16 + r4;
       if (j0 >= dff) continue;
-#pragma unroll
+#pragma clang loop unroll(full)
       for (int mb = 0; mb < MB; ++mb) {
         const int m = tile_m * BM + wm * WM + mb * 16 + tok;
         if (m >= a.M) continue;
         uint16_t* hrow = static_cast<uint16_t*>(a.y) + int64_t(m) * a.ldy;
         const float ts = A8 ? a.sx[m] : 1.f;
         uint16_t hv[4];
-#pragma unroll
+#pragma clang loop unroll(full)
         for (int r = 0; r < 4; ++r) {
           const int j = j0 + r;
           const int jj = j < dff ? j : dff - 1;
@@ -271,7 +271,7 @@ __device__ inline void gemm_epilogue(const GemmArgs& a, const f32x4 (&acc)[NB_][
           *reinterpret_cast<uint2*>(hrow + j0) =
               make_uint2(uint32_t(hv[0]) | (uint32_t(hv[1]) << 16), uint32_t(hv[2]) | (uint32_t(hv[3]) << 16));
         } else {
-#pragma unroll
+#pragma clang loop unroll(full)
           for (int r = 0; r < 4; ++r)
             if (j0 + r < dff) hrow[j0 + r] = hv[r];
         }
@@ -504,96 +504,6 @@ __global__ __launch_bounds__(NTHREADS, 1) void gemm_dma_kernel(const GemmArgs a)
     asm volatile("" ::: "memory");
   }
   gemm_epilogue<EPI, false>(a, acc, tile_m, tile_n, wm, wn, wrow, lane);
-}
-
-// The same 256 x 256 tile and 4-stage LDS ring with 4 waves of 128 x 128
-// (one wave per SIMD, 8 x 8 blocks, 256 FP32 accumulators per lane kept in
-// the accumulator registers).  A wave reads 8 weight and 8 token fragments
-// per 32-K stage for 64 MFMAs, a third less LDS traffic per MFMA than the
-// 8-wave layout's 12 for 32, which is what bounds that layout.
-constexpr int W4_WAVES = 4;
-constexpr int W4_THREADS = 64 * W4_WAVES;
-constexpr int W4_WM = 128, W4_WN = 128;
-constexpr int W4_MB = W4_WM / 16, W4_NB = W4_WN / 16;
-constexpr int W4_LOADS = BM / 16 / W4_WAVES;   // 16-row loads per wave per operand (4)
-
-template <bool TR, int EPI>
-__global__ __launch_bounds__(W4_THREADS, 1) void gemm_w4_kernel(const GemmArgs a) {
-  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  int tile_m, tile_n;
-  if (!tile_coords(a, tile_m, tile_n)) return;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm = wave >> 1, wn = wave & 1;
-
-  const uint8_t* xptr[W4_LOADS];
-  RowRef wr[W4_LOADS];
-#pragma unroll
-  for (int j = 0; j < W4_LOADS; ++j) {
-    const int tr = 16 * (W4_LOADS * wave + j) + (lane >> 2);
-    const int c = (lane & 3) ^ ((tr >> 1) & 3);
-    const int m = tile_m * BM + tr;
-    xptr[j] = reinterpret_cast<const uint8_t*>(a.x) + int64_t(m < a.M ? m : 0) * a.ldx * 2 + c * 16;
-    int seg = 0, n = 0;
-    const bool ok = tile_row<EPI>(a, tile_n, tr, seg, n);
-    wr[j].pool = a.pool;
-    wr[j].vbase = a.seg[seg].vbase;
-    wr[j].rowoff = int64_t(ok ? n : 0) * a.row_bytes + c * 16;
-    wr[j].cvp = -1;
-    wr[j].cbase = 0;
-    wr[j].ok = true;
-  }
-
-  f32x4 acc[W4_NB][W4_MB];
-#pragma unroll
-  for (int i = 0; i < W4_NB; ++i)
-#pragma unroll
-    for (int j = 0; j < W4_MB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  int wrow[W4_NB];
-  wave_rows<EPI, W4_NB, W4_WN>(wn, wrow);
-
-  const int nk = a.K / DBK;
-  for (int kb = 1 - DSTAGES; kb < nk; ++kb) {
-    if (kb >= 0) {
-      if (kb + DMA_AHEAD < nk)
-        wait_vm_lgkm0<DMA_AHEAD * 2 * W4_LOADS>();
-      else
-        wait_vm_lgkm0<0>();
-      __builtin_amdgcn_s_barrier();
-      asm volatile("" ::: "memory");
-    }
-    const int ks = kb + DSTAGES - 1;
-    if (ks < nk) {
-      uint8_t* base = smem + (ks % DSTAGES) * DSTAGE_BYTES;
-#pragma unroll
-      for (int j = 0; j < W4_LOADS; ++j) {
-        const int r0 = 16 * (W4_LOADS * wave + j);
-        const uint8_t* xsrc = xptr[j] + int64_t(ks) * DROWB;
-        const uint8_t* wsrc = row_addr<TR>(a.phi, a.log2_page, wr[j], int64_t(ks) * DROWB);
-        __builtin_amdgcn_global_load_lds(xsrc, base + r0 * DROWB, 16, 0, 0);
-        __builtin_amdgcn_global_load_lds(wsrc, base + DTILE + r0 * DROWB, 16, 0, 0);
-      }
-    }
-    if (kb < 0) continue;
-    const uint8_t* xs = smem + (kb % DSTAGES) * DSTAGE_BYTES;
-    const uint8_t* ws = xs + DTILE;
-    const int chunk = lane >> 4;
-    bf16x8_t fa[W4_NB];
-#pragma unroll
-    for (int nb = 0; nb < W4_NB; ++nb)
-      fa[nb] = *reinterpret_cast<const bf16x8_t*>(ws + dswz(wrow[nb] + (lane & 15), chunk));
-#pragma unroll
-    for (int mb = 0; mb < W4_MB; ++mb) {
-      const bf16x8_t fb =
-          *reinterpret_cast<const bf16x8_t*>(xs + dswz(wm * W4_WM + mb * 16 + (lane & 15), chunk));
-#pragma unroll
-      for (int nb = 0; nb < W4_NB; ++nb)
-        acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[nb], fb, acc[nb][mb], 0, 0, 0);
-    }
-    asm volatile("" ::: "memory");
-  }
-  gemm_epilogue<EPI, false, W4_NB, W4_MB, W4_WM, W4_WN>(a, acc, tile_m, tile_n, wm, wn, wrow, lane);
 }
 
 // x_out[m][j] = x[m][perm[j]]: the activations of a down projection put in
@@ -893,6 +803,7 @@ hipError_t launch_gemm(const GemmArgs& a, bool translate, hipStream_t s) {
   else
     fn = translate ? (sw ? gemm_dma_kernel<true, kSwiGLU> : gemm_dma_kernel<true, kStore>)
                    : (sw ? gemm_dma_kernel<false, kSwiGLU> : gemm_dma_kernel<false, kStore>);
+
   static bool attr_set[16] = {};
   const int key = (translate ? 2 : 0) + (sw ? 1 : 0) + (f8 ? 4 : 0) + (a8 ? 8 : 0);
   if (!attr_set[key]) {
