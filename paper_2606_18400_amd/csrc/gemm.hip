@@ -474,6 +474,22 @@ __global__ __launch_bounds__(NTHREADS, 1) void gemm_dma_kernel(const GemmArgs a)
       __builtin_amdgcn_s_barrier();
       asm volatile("" ::: "memory");
     }
+    // fragment reads of stage kb go out first, so their latency overlaps the
+    // address work and issue of the next stage's loads
+    const uint8_t* xs = smem + ((kb < 0 ? 0 : kb) % DSTAGES) * DSTAGE_BYTES;
+    const uint8_t* ws = xs + DTILE;
+    const int chunk = lane >> 4;
+    auto tok_frag = [&](int mb) {
+      return *reinterpret_cast<const bf16x8_t*>(xs + dswz(wm * WM + mb * 16 + (lane & 15), chunk));
+    };
+    bf16x8_t fa[NB], fb0, fb1;
+    if (kb >= 0) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        fa[nb] = *reinterpret_cast<const bf16x8_t*>(ws + dswz(wrow[nb] + (lane & 15), chunk));
+      fb0 = tok_frag(0);
+      fb1 = tok_frag(1);
+    }
     const int ks = kb + DSTAGES - 1;   // stage issued now, into the buffer freed by the barrier
     if (ks < nk) {
       uint8_t* base = smem + (ks % DSTAGES) * DSTAGE_BYTES;
@@ -487,19 +503,21 @@ __global__ __launch_bounds__(NTHREADS, 1) void gemm_dma_kernel(const GemmArgs a)
       }
     }
     if (kb < 0) continue;
-    const uint8_t* xs = smem + (kb % DSTAGES) * DSTAGE_BYTES;
-    const uint8_t* ws = xs + DTILE;
-    const int chunk = lane >> 4;
-    bf16x8_t fa[NB];
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-      fa[nb] = *reinterpret_cast<const bf16x8_t*>(ws + dswz(wrow[nb] + (lane & 15), chunk));
+    // token fragments two blocks ahead of the MFMAs that use them
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
-      const bf16x8_t fb = *reinterpret_cast<const bf16x8_t*>(xs + dswz(wm * WM + mb * 16 + (lane & 15), chunk));
+      bf16x8_t fbn = fb1;
+      if (mb + 2 < MB) fbn = tok_frag(mb + 2);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
-        acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[nb], fb, acc[nb][mb], 0, 0, 0);
+        acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[nb], fb0, acc[nb][mb], 0, 0, 0);
+      fb0 = fb1;
+      fb1 = fbn;
+    }
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      __builtin_amdgcn_sched_group_barrier(0x008, NB, 0);
+      if (mb + 2 < MB) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
     }
     asm volatile("" ::: "memory");
   }
