@@ -39,3 +39,39 @@ def remap(pool, phi, remap_seed, page_bytes):
         out[q * B:(q + 1) * B] = pool[p * B:(p + 1) * B]
     phi2 = [tau[phi[v]] for v in range(P)]
     return out, phi2
+
+
+# ----------------------------------------------------------------------------
+# Incremental remap.  The paper amortises the remap's synchronisation cost by
+# choosing when it runs (Section 4.2; Figure 7 sweeps the cadence).  Reading
+# for spreading one remap over several serving steps: the pairs of tau, taken
+# in ascending order of their lower page, are applied in consecutive slices;
+# after each slice the moved pages' entries of phi are updated, so between
+# slices the pool and phi are a consistent layout (the pairs are disjoint
+# transpositions, so the slices commute and together equal tau).
+# ----------------------------------------------------------------------------
+
+def pairs(remap_seed, P):
+    """Pairs (p, tau[p]) with p < tau[p], ascending in p."""
+    tau = matching(remap_seed, P)
+    return [(p, tau[p]) for p in range(P) if tau[p] > p]
+
+
+def remap_in_slices(pool, phi, remap_seed, page_bytes, slice_pairs):
+    """Yield (pool_i, phi_i) after each slice of at most slice_pairs pairs."""
+    if slice_pairs < 1:
+        raise ValueError("slice_pairs must be positive")
+    B = page_bytes
+    pool = pool.copy()
+    phi = list(phi)
+    where = {phi[v]: v for v in range(len(phi))}   # physical page -> virtual page
+    todo = pairs(remap_seed, len(phi))
+    for i0 in range(0, len(todo), slice_pairs):
+        for a, b in todo[i0:i0 + slice_pairs]:
+            pa = pool[a * B:(a + 1) * B].copy()
+            pool[a * B:(a + 1) * B] = pool[b * B:(b + 1) * B]
+            pool[b * B:(b + 1) * B] = pa
+            va, vb = where[a], where[b]
+            phi[va], phi[vb] = b, a
+            where[a], where[b] = vb, va
+        yield pool.copy(), list(phi)

@@ -68,3 +68,33 @@ def test_two_remaps_compose():
     lay2 = L.Layout(**{**lay.__dict__, "phi": f2})
     for t in range(lay.T):
         assert np.array_equal(L.unpack(lay2, p2, t), ws[t])
+
+
+@pytest.mark.parametrize("slice_pairs", [1, 5, 1000])
+def test_remap_in_slices_keeps_every_tensor_between_slices(slice_pairs):
+    shapes = tiny_shapes("bf16")
+    lay = L.build_layout(8, shapes, 64, 64 * 257)       # odd pool: one page stays
+    ws = random_weights(shapes, 4)
+    pool = L.pack(lay, ws)
+    states = list(R.remap_in_slices(pool, lay.phi, 77, 64, slice_pairs))
+    assert len(states) == -(-(257 // 2) // slice_pairs)
+    for pool_i, phi_i in states:
+        assert sorted(phi_i) == list(range(lay.P))
+        lay_i = L.Layout(**{**lay.__dict__, "phi": phi_i})
+        for t in range(lay.T):
+            assert np.array_equal(L.unpack(lay_i, pool_i, t), ws[t])
+    # all slices together are the whole remap
+    full_pool, full_phi = R.remap(pool, lay.phi, 77, 64)
+    assert np.array_equal(states[-1][0], full_pool) and states[-1][1] == full_phi
+
+
+def test_remap_slices_touch_only_their_pairs():
+    P, B = 12, 4
+    pool = np.arange(P * B, dtype=np.uint64).astype(np.uint8)
+    todo = R.pairs(3, P)
+    assert all(a < b for a, b in todo) and [a for a, _ in todo] == sorted(a for a, _ in todo)
+    first = next(R.remap_in_slices(pool, list(range(P)), 3, B, 2))
+    moved = {p for pr in todo[:2] for p in pr}
+    for p in range(P):
+        same = np.array_equal(first[0][p * B:(p + 1) * B], pool[p * B:(p + 1) * B])
+        assert same == (p not in moved)
