@@ -275,23 +275,50 @@ def bench_serve(args):
     weights = [layer_w[t % TENSORS_PER_LAYER] for t in range(len(shapes) - 2)] + [emb, head]
     rates = [float(r) for r in args.rates.split(",")]
     results = {}
-    for name, flags, every in [("cloaked", 0, 256), ("native", C.CLOAK_IDENTITY | C.CLOAK_NATIVE, 0)]:
+    every_default = 256
+    for name, flags, every in [("cloaked", 0, every_default), ("native", C.CLOAK_IDENTITY | C.CLOAK_NATIVE, 0)]:
         log(f"{name}: loading 32 layers into a 16 GiB pool")
         eng = serve.Engine(cfg, pool_bytes=16 << 30, page_bytes=2 << 20, seed=1, flags=flags, kv_blocks=24576,
                            max_tokens=2048, prefill_chunk=512, max_seqs=64, split_keys=512, remap_every=every,
                            weights=weights, max_context=8192)
         results[name] = {}
-        for rate in rates:
+
+        def one_run(rate):
             trace = synth.poisson_trace(args.requests, rate, 128, 4096, 64, 1024, cfg["vocab"], seed=7)
             reqs = [serve.Request(t["id"], t["prompt"], t["max_new"], t["arrival"]) for t in trace]
-            steps0, remaps0 = eng.steps, eng.remaps
+            steps0, remaps0, ms0, ev0 = eng.steps, eng.remaps, len(eng.step_ms), len(eng.remap_events)
             rep = eng.run(reqs)
             rep["steps"] = eng.steps - steps0
             rep["remaps"] = eng.remaps - remaps0
+            sm = np.array(eng.step_ms[ms0:])
+            rep.update({f"step_ms_p{q}": float(np.percentile(sm, q)) for q in (50, 99, 99.9)})
+            rep["step_ms_max"] = float(sm.max())
+            rm = eng.remap_ms(ev0)
+            rep["remap_slices_run"] = len(rm)
+            rep["remap_slice_ms_max"] = max(rm) if rm else 0.0
+            rep["remap_ms_total"] = float(sum(rm))
+            rep["remap_share_of_step_time"] = float(sum(rm)) / float(sm.sum()) if sm.size else 0.0
+            return rep
+
+        for rate in rates:
+            rep = one_run(rate)
             results[name][str(rate)] = rep
             log(f"{name} rate {rate}/s: ttft p50 {rep['ttft_ms_p50']:.0f} p99 {rep['ttft_ms_p99']:.0f} ms, "
                 f"tpot p50 {rep['tpot_ms_p50']:.1f} p99 {rep['tpot_ms_p99']:.1f} ms, "
                 f"{rep['output_tok_per_s']:.0f} tok/s, {rep['steps']} steps, {rep['remaps']} remaps")
+        if name == "cloaked" and args.remap_sweep:
+            # cadence sweep at the first rate: remap every N steps, spread over S steps (N=0: never)
+            results["cadence"] = {}
+            for item in args.remap_sweep.split(","):
+                every, slices = (int(v) for v in item.split(":"))
+                eng.remap_every, eng.remap_slices = every, slices
+                rep = one_run(rates[0])
+                results["cadence"][item] = rep
+                log(f"cadence every {every} over {slices} steps: itl p50 {rep['itl_ms_p50']:.1f} p99 "
+                    f"{rep['itl_ms_p99']:.1f} p99.9 {rep['itl_ms_p999']:.1f} ms, {rep['remaps']} remaps, "
+                    f"largest remap stall {rep['remap_slice_ms_max']:.2f} ms, remap share of step time "
+                    f"{100 * rep['remap_share_of_step_time']:.2f}%")
+            eng.remap_every, eng.remap_slices = every_default, 1
         eng.close()
         torch.cuda.empty_cache()
     first = str(rates[0])
@@ -406,6 +433,8 @@ def main():
                     help="layer: the headline decode layer (default); serve: serving trace; stack: 64-layer FP8")
     ap.add_argument("--rates", default="2,8", help="serve: Poisson arrival rates (req/s)")
     ap.add_argument("--requests", type=int, default=32, help="serve: requests per rate")
+    ap.add_argument("--remap-sweep", default="",
+                    help="serve: cadence sweep 'every:slices,...' (e.g. 64:1,256:1,256:32,0:1) at the first rate")
     ap.add_argument("--stack-batches", default="1,8,32,64,256", help="stack: decode batch sizes")
     args = ap.parse_args()
     if args.gpus != 1:

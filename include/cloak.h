@@ -121,6 +121,8 @@ typedef struct {
 #define CLOAK_QUERY_TENSOR      13  /* int64: index of tensor (layer = index >> 8,
                                        kind = index & 255), or -1                        */
 #define CLOAK_QUERY_DFFN        14  /* int64: hidden size of layer `index` (0 if no FFN) */
+#define CLOAK_QUERY_REMAP_PENDING 15 /* int64: page pairs of the remap in progress not yet
+                                        swapped (0 if none)                              */
 
 /* Workspace selectors for cloak_ws_bytes(). */
 #define CLOAK_OP_LINEAR 1   /* index = tensor */
@@ -241,8 +243,28 @@ int cloak_quantize_fp8(const void* d_x, int64_t M, int64_t K, int64_t ldx, void*
 /* Re-randomise page placement in place (Section 4.2, periodic remapping
  * with no extra memory footprint): draw the matching tau from remap_seed,
  * swap every page pair in the pool on `stream`, and set phi' = tau o phi on
- * host and device.  Refused (ESTATE) on CLOAK_NATIVE layouts. */
+ * host and device.  Refused (ESTATE) on CLOAK_NATIVE layouts and while an
+ * incremental remap is in progress. */
 int cloak_remap(cloak_layout* layout, void* d_pool, uint64_t remap_seed, void* stream);
+
+/* Incremental remap (spreads one remap over several serving steps, so no
+ * single step pays the whole move; the paper leaves the cadence to the
+ * operator, Section 4.2 and Figure 7).  cloak_remap_begin draws the matching
+ * tau from remap_seed; each cloak_remap_step then swaps the next max_pairs
+ * page pairs (all remaining if max_pairs <= 0; pairs in ascending order of
+ * their lower page) on `stream` and updates phi for exactly those pages,
+ * host and device, in stream order.  Between steps the pool and phi are a
+ * complete, consistent layout, so any cloak_* call may run between them;
+ * after the last pair the result equals cloak_remap(remap_seed).
+ * *remaining (may be NULL) receives the pairs still to swap.
+ * cloak_remap_begin: ESTATE on native layouts or while a remap is in
+ * progress.  cloak_remap_step: ESTATE when none is in progress.  The host
+ * variant applies a step to a pool image (tests; no device needed). */
+int cloak_remap_begin(cloak_layout* layout, uint64_t remap_seed);
+int cloak_remap_step(cloak_layout* layout, void* d_pool, int64_t max_pairs, int64_t* remaining,
+                     void* stream);
+int cloak_remap_step_host(cloak_layout* layout, void* h_pool, uint64_t h_pool_bytes, int64_t max_pairs,
+                          int64_t* remaining);
 
 /* Host-side remap of a pool image h_pool (pool_bytes) and of the layout's
  * page map; the same result cloak_remap produces on the device.  Updates

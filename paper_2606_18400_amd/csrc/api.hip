@@ -697,42 +697,53 @@ extern "C" int cloak_quantize_fp8(const void* d_x, int64_t M, int64_t K, int64_t
   return CLOAK_OK;
 }
 
+extern "C" int cloak_remap_step(cloak_layout* L, void* d_pool, int64_t max_pairs, int64_t* remaining, void* stream) {
+  clear_error();
+  if (int rc = check_device_state(L, "cloak_remap_step")) return rc;
+  if (int rc = check_pool(L, d_pool, "cloak_remap_step")) return rc;
+  RemapEpoch& e = L->epoch;
+  if (!e.active) {
+    set_error("cloak_remap_step: no remap in progress (cloak_remap_begin)");
+    return CLOAK_ESTATE;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t left = e.npairs() - e.next;
+  const int64_t n = max_pairs <= 0 || max_pairs > left ? left : max_pairs;
+  hipEvent_t ev = static_cast<hipEvent_t>(L->dev.stage_event);
+  // the staging buffer may still feed earlier asynchronous copies
+  HIP_TRY(hipEventSynchronize(ev), "hipEventSynchronize");
+  int32_t* pairs = L->dev.h_stage;
+  int32_t* new_phi = L->dev.h_stage + L->P + 1;
+  if (!e.uploaded) {
+    // the whole pair list once per epoch; later slices index into it
+    std::memcpy(pairs, e.pairs.data(), e.pairs.size() * 4);
+    if (!e.pairs.empty())
+      HIP_TRY(hipMemcpyAsync(L->dev.remap_pairs, pairs, e.pairs.size() * 4, hipMemcpyHostToDevice, st),
+              "upload pairs");
+    e.uploaded = true;
+  }
+  if (n > 0) {
+    SwapArgs sa{};
+    sa.pool = static_cast<uint8_t*>(d_pool);
+    sa.pairs = L->dev.remap_pairs + 2 * e.next;
+    sa.npairs = n;
+    sa.log2_page = L->log2_page;
+    HIP_TRY(launch_swap(sa, st), "swap kernel");
+  }
+  remap_epoch_advance(L, n);
+  // the device map follows in stream order, so the next kernel sees the
+  // pages where they now are
+  std::memcpy(new_phi, L->phi.data(), size_t(L->P) * 4);
+  HIP_TRY(hipMemcpyAsync(L->dev.phi, new_phi, size_t(L->P) * 4, hipMemcpyHostToDevice, st), "upload page map");
+  HIP_TRY(hipEventRecord(ev, st), "hipEventRecord");
+  if (remaining) *remaining = left - n;
+  return CLOAK_OK;
+}
+
 extern "C" int cloak_remap(cloak_layout* L, void* d_pool, uint64_t remap_seed, void* stream) {
   clear_error();
   if (int rc = check_device_state(L, "cloak_remap")) return rc;
   if (int rc = check_pool(L, d_pool, "cloak_remap")) return rc;
-  if (L->native()) {
-    set_error("cloak_remap: native (untranslated) layouts cannot be remapped");
-    return CLOAK_ESTATE;
-  }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const std::vector<int32_t> tau = remap_matching(remap_seed, L->P);
-  hipEvent_t ev = static_cast<hipEvent_t>(L->dev.stage_event);
-  // the staging buffer may still feed the previous remap's copies
-  HIP_TRY(hipEventSynchronize(ev), "hipEventSynchronize");
-  int32_t* pairs = L->dev.h_stage;
-  int32_t* new_phi = L->dev.h_stage + L->P + 1;
-  int64_t np = 0;
-  for (int64_t p = 0; p < L->P; ++p) {
-    if (tau[p] > p) {
-      pairs[2 * np] = int32_t(p);
-      pairs[2 * np + 1] = tau[p];
-      ++np;
-    }
-  }
-  for (int64_t v = 0; v < L->P; ++v) new_phi[v] = tau[L->phi[v]];
-  if (np > 0) {
-    HIP_TRY(hipMemcpyAsync(L->dev.remap_pairs, pairs, size_t(np) * 8, hipMemcpyHostToDevice, st), "upload pairs");
-    SwapArgs s{};
-    s.pool = static_cast<uint8_t*>(d_pool);
-    s.pairs = L->dev.remap_pairs;
-    s.npairs = np;
-    s.log2_page = L->log2_page;
-    HIP_TRY(launch_swap(s, st), "swap kernel");
-  }
-  HIP_TRY(hipMemcpyAsync(L->dev.phi, new_phi, size_t(L->P) * 4, hipMemcpyHostToDevice, st), "upload page map");
-  HIP_TRY(hipEventRecord(ev, st), "hipEventRecord");
-  std::memcpy(L->phi.data(), new_phi, size_t(L->P) * 4);
-  L->remaps += 1;
-  return CLOAK_OK;
+  if (int rc = cloak_remap_begin(L, remap_seed)) return rc;
+  return cloak_remap_step(L, d_pool, 0, nullptr, stream);
 }

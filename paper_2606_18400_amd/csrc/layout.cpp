@@ -87,6 +87,41 @@ std::vector<int32_t> remap_matching(uint64_t remap_seed, int64_t P) {
   return tau;
 }
 
+bool remap_epoch_begin(cloak_layout* L, uint64_t remap_seed) {
+  RemapEpoch& e = L->epoch;
+  if (e.active) return false;
+  const std::vector<int32_t> tau = remap_matching(remap_seed, L->P);
+  e.pairs.clear();
+  for (int64_t p = 0; p < L->P; ++p)
+    if (tau[p] > p) {
+      e.pairs.push_back(int32_t(p));
+      e.pairs.push_back(tau[p]);
+    }
+  e.where.assign(size_t(L->P), 0);
+  for (int64_t v = 0; v < L->P; ++v) e.where[size_t(L->phi[v])] = int32_t(v);
+  e.next = 0;
+  e.uploaded = false;
+  e.active = true;
+  return true;
+}
+
+void remap_epoch_advance(cloak_layout* L, int64_t n) {
+  RemapEpoch& e = L->epoch;
+  for (int64_t i = e.next; i < e.next + n; ++i) {
+    const int32_t a = e.pairs[2 * i], b = e.pairs[2 * i + 1];
+    const int32_t va = e.where[a], vb = e.where[b];
+    L->phi[va] = b;
+    L->phi[vb] = a;
+    e.where[a] = vb;
+    e.where[b] = va;
+  }
+  e.next += n;
+  if (e.next >= e.npairs()) {
+    e.active = false;
+    L->remaps += 1;
+  }
+}
+
 double contiguity(const cloak_layout* L) {
   int64_t hits = 0, total = 0;
   for (const auto& ti : L->tensors) {
@@ -344,6 +379,11 @@ extern "C" int cloak_query(const cloak_layout* L, int32_t what, int64_t index, v
   };
   const int64_t T = int64_t(L->tensors.size());
   switch (what) {
+    case CLOAK_QUERY_REMAP_PENDING: {
+      if (!need(8)) return CLOAK_EINVAL;
+      *static_cast<int64_t*>(out) = L->epoch.active ? L->epoch.npairs() - L->epoch.next : 0;
+      return CLOAK_OK;
+    }
     case CLOAK_QUERY_P:
     case CLOAK_QUERY_V:
     case CLOAK_QUERY_T:
@@ -439,6 +479,55 @@ extern "C" int cloak_pack_host(const cloak_layout* L, int32_t tensor, const void
   return CLOAK_OK;
 }
 
+extern "C" int cloak_remap_begin(cloak_layout* L, uint64_t remap_seed) {
+  clear_error();
+  if (!L) {
+    set_error("cloak_remap_begin: null layout");
+    return CLOAK_EINVAL;
+  }
+  if (L->native()) {
+    set_error("cloak_remap_begin: native (untranslated) layouts cannot be remapped");
+    return CLOAK_ESTATE;
+  }
+  if (!remap_epoch_begin(L, remap_seed)) {
+    set_error("cloak_remap_begin: a remap is in progress (finish it with cloak_remap_step)");
+    return CLOAK_ESTATE;
+  }
+  return CLOAK_OK;
+}
+
+extern "C" int cloak_remap_step_host(cloak_layout* L, void* h_pool, uint64_t h_pool_bytes, int64_t max_pairs,
+                                     int64_t* remaining) {
+  clear_error();
+  if (!L || !h_pool) {
+    set_error("cloak_remap_step_host: null argument");
+    return CLOAK_EINVAL;
+  }
+  if (!L->epoch.active) {
+    set_error("cloak_remap_step_host: no remap in progress (cloak_remap_begin)");
+    return CLOAK_ESTATE;
+  }
+  if (h_pool_bytes < uint64_t(L->pool_bytes)) {
+    set_error("cloak_remap_step_host: pool image too small");
+    return CLOAK_EINVAL;
+  }
+  RemapEpoch& e = L->epoch;
+  const int64_t left = e.npairs() - e.next;
+  const int64_t n = max_pairs <= 0 || max_pairs > left ? left : max_pairs;
+  auto* pool = static_cast<uint8_t*>(h_pool);
+  std::vector<uint8_t> tmp(size_t(L->page_bytes));
+  for (int64_t i = e.next; i < e.next + n; ++i) {
+    uint8_t* a = pool + int64_t(e.pairs[2 * i]) * L->page_bytes;
+    uint8_t* b = pool + int64_t(e.pairs[2 * i + 1]) * L->page_bytes;
+    std::memcpy(tmp.data(), a, size_t(L->page_bytes));
+    std::memcpy(a, b, size_t(L->page_bytes));
+    std::memcpy(b, tmp.data(), size_t(L->page_bytes));
+  }
+  remap_epoch_advance(L, n);
+  if (remaining) *remaining = left - n;
+  return CLOAK_OK;
+}
+
 extern "C" int cloak_remap_host(cloak_layout* L, void* h_pool, uint64_t h_pool_bytes, uint64_t remap_seed) {
   clear_error();
   if (!L || !h_pool) {
@@ -452,6 +541,10 @@ extern "C" int cloak_remap_host(cloak_layout* L, void* h_pool, uint64_t h_pool_b
   if (h_pool_bytes < uint64_t(L->pool_bytes)) {
     set_error("cloak_remap_host: pool image too small");
     return CLOAK_EINVAL;
+  }
+  if (L->epoch.active) {
+    set_error("cloak_remap_host: a remap is in progress (finish it with cloak_remap_step_host)");
+    return CLOAK_ESTATE;
   }
   std::vector<int32_t> tau = remap_matching(remap_seed, L->P);
   auto* pool = static_cast<uint8_t*>(h_pool);

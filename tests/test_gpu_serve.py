@@ -99,18 +99,22 @@ def test_remap_between_steps_changes_nothing(S):
     rng = np.random.Generator(np.random.PCG64(13))
     prompts = [rng.integers(0, TINY["vocab"], n).astype(np.int32) for n in (20, 45, 3)]
     outs = []
-    for every in (0, 1):
-        eng = make_engine(S, TINY, ws, remap_every=every)
+    # no remap; a whole remap after every step; remaps spread over 3 steps each
+    for every, slices in ((0, 1), (1, 1), (2, 3)):
+        eng = make_engine(S, TINY, ws, remap_every=every, remap_slices=slices)
         reqs = [S.Request(i, p, 10) for i, p in enumerate(prompts)]
         eng.run(reqs, realtime=False)
-        if every:
+        if every == 1:
             assert eng.remaps == eng.steps > 0
+        if slices > 1:
+            assert eng.remaps >= 2
         outs.append([(r.out, [l.copy() for l in r.logits]) for r in reqs])
         eng.close()
-    for (oa, la), (ob, lb) in zip(*outs):
-        assert oa == ob
-        for x, y in zip(la, lb):
-            assert np.array_equal(x, y)
+    for other in outs[1:]:
+        for (oa, la), (ob, lb) in zip(outs[0], other):
+            assert oa == ob
+            for x, y in zip(la, lb):
+                assert np.array_equal(x, y)
 
 
 def test_admission_never_overcommits_kv(S):

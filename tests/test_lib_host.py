@@ -134,6 +134,33 @@ def test_remap_host_matches_oracle(remap_seed):
     C.cloak_layout_free(lay_c)
 
 
+@pytest.mark.parametrize("slice_pairs", [1, 37, 0])
+def test_incremental_remap_host_matches_oracle_slices(slice_pairs):
+    shapes = small_model("bf16", layers=1, d=128, ffn=256, dkv=32, vocab=100)
+    P, B = 513, 1024   # odd P: one page stays put
+    ws = [synth.weight(t, s[2], s[3], "bf16")[0] for t, s in enumerate(shapes)]
+    lay_c = C.cloak_layout_build(9, shapes, B, P * B)
+    lay_o = OL.build_layout(9, oracle_shapes(shapes), B, P * B)
+    img = np.zeros(P * B, np.uint8)
+    for t, w in enumerate(ws):
+        C.cloak_pack_host(lay_c, t, w, img)
+    pool_o = OL.pack(lay_o, ws)
+    C.cloak_remap_begin(lay_c, 4242)
+    assert C.cloak_query(lay_c, "REMAP_PENDING") == P // 2
+    expect_error(C.CLOAK_ESTATE, C.cloak_remap_begin, lay_c, 1)          # one remap at a time
+    expect_error(C.CLOAK_ESTATE, C.cloak_remap_host, lay_c, img, 1)
+    states = list(OR.remap_in_slices(pool_o, lay_o.phi, 4242, B, slice_pairs if slice_pairs > 0 else P))
+    for k, (pool_k, phi_k) in enumerate(states):
+        left = C.cloak_remap_step_host(lay_c, img, slice_pairs)
+        assert left == C.cloak_query(lay_c, "REMAP_PENDING")
+        assert list(C.cloak_query(lay_c, "PHI")) == phi_k
+        assert np.array_equal(img, pool_k)
+        assert C.cloak_query(lay_c, "REMAPS") == (1 if left == 0 else 0)
+    assert left == 0
+    expect_error(C.CLOAK_ESTATE, C.cloak_remap_step_host, lay_c, img, 1)  # nothing in progress
+    C.cloak_layout_free(lay_c)
+
+
 def expect_error(code, fn, *args):
     with pytest.raises(C.CloakError) as e:
         fn(*args)
@@ -167,6 +194,7 @@ def test_error_codes_without_device():
         C.cloak_layout_free(L)
     N = C.cloak_layout_build(1, good, 1024, 1024 * 64, C.CLOAK_IDENTITY | C.CLOAK_NATIVE)
     expect_error(C.CLOAK_ESTATE, C.cloak_remap_host, N, np.zeros(1024 * 64, np.uint8), 1)
+    expect_error(C.CLOAK_ESTATE, C.cloak_remap_begin, N, 1)
     C.cloak_layout_free(N)
 
 
