@@ -193,6 +193,18 @@ def test_long_rows_single_token(C, M, dtype):
     cw.close()
 
 
+@pytest.mark.parametrize("M", [1, 3])
+def test_fp8_two_chunk_waves(C, M):
+    # one token over 6144+ FP8 rows of 2..8 KiB takes two chunks per wave
+    shapes = [(0, "gate", 3072, 4096, "fp8"), (0, "up", 3072, 4096, "fp8"), (0, "down", 4096, 3072, "fp8"),
+              (1, "q", 6400, 2048, "fp8"), (1, "k", 64, 2048, "fp8")]
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, 65536, 65536 * 1024, seed=53)
+    cw.load(ws, scs)
+    check_linear_all(C, cw, shapes, ws, scs, M)
+    cw.close()
+
+
 @pytest.mark.parametrize("M", [1, 2, 4, 8])
 def test_fp8_layer_vs_fp64(C, M):
     shapes = decoder_shapes(1280, 3456, 256, "fp8", layers=1, extra=[(-1, "head", 700, 1280, "bf16")])
