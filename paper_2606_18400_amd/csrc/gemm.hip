@@ -408,14 +408,20 @@ __global__ __launch_bounds__(NTHREADS, 1) void gemm_kernel(const GemmArgs a) {
 // then the workgroup barrier makes every lane's stage kb visible and frees
 // the buffer the next stage is loaded into.
 constexpr int DBK = 32;                     // K elements per stage
-constexpr int DROWB = DBK * 2;              // 64 bytes per tile row
-constexpr int DTILE = BM * DROWB;           // 16 KiB per operand per stage
+constexpr int DROWB = DBK * 2;              // bytes per tile row (64)
+constexpr int DCH = DROWB / 16;             // 16-byte chunks per tile row
+constexpr int DRPL = 1024 / DROWB;          // tile rows one wave load fills
+constexpr int DTILE = BM * DROWB;           // bytes per operand per stage
 constexpr int DSTAGES = 4;
 constexpr int DSTAGE_BYTES = 2 * DTILE;
-constexpr int DLOADS = BM / 16 / (NTHREADS / 64);   // 16-row loads per wave per operand (2)
+constexpr int DLOADS = BM / DRPL / (NTHREADS / 64);   // wave loads per operand per stage
 constexpr int DMA_AHEAD = DSTAGES - 2;      // younger stages still in flight at a wait
+static_assert(DSTAGES * DSTAGE_BYTES <= 4 * TILE_BYTES, "ring exceeds the dynamic LDS reserved");
 
-__device__ inline int dswz(int row, int chunk) { return row * DROWB + ((chunk ^ ((row >> 1) & 3)) << 4); }
+// chunk swizzle: the 8 consecutive rows one LDS pass serves land on 8
+// distinct 16-byte slots of a 128-byte bank window
+__device__ inline int dkey(int row) { return DCH == 4 ? (row >> 1) & 3 : row & 7; }
+__device__ inline int dswz(int row, int chunk) { return row * DROWB + ((chunk ^ dkey(row)) << 4); }
 
 // s_waitcnt vmcnt(N) lgkmcnt(0), expcnt untouched
 template <int N>
@@ -434,13 +440,13 @@ __global__ __launch_bounds__(NTHREADS, 1) void gemm_dma_kernel(const GemmArgs a)
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WAVES_N, wn = wave % WAVES_N;
 
-  // load slots: tile row 16 * (DLOADS * wave + j) + lane / 4 of both operands
+  // load slots: tile row DRPL * (DLOADS * wave + j) + lane / DCH of both operands
   const uint8_t* xptr[DLOADS];
   RowRef wr[DLOADS];
 #pragma unroll
   for (int j = 0; j < DLOADS; ++j) {
-    const int tr = 16 * (DLOADS * wave + j) + (lane >> 2);
-    const int c = (lane & 3) ^ ((tr >> 1) & 3);
+    const int tr = DRPL * (DLOADS * wave + j) + lane / DCH;
+    const int c = (lane % DCH) ^ dkey(tr);
     const int m = tile_m * BM + tr;
     // rows past M or past the tensor read row 0 (valid memory); their
     // results are never stored
@@ -478,24 +484,24 @@ __global__ __launch_bounds__(NTHREADS, 1) void gemm_dma_kernel(const GemmArgs a)
     // address work and issue of the next stage's loads
     const uint8_t* xs = smem + ((kb < 0 ? 0 : kb) % DSTAGES) * DSTAGE_BYTES;
     const uint8_t* ws = xs + DTILE;
-    const int chunk = lane >> 4;
-    auto tok_frag = [&](int mb) {
+    auto tok_frag = [&](int mb, int chunk) {
       return *reinterpret_cast<const bf16x8_t*>(xs + dswz(wm * WM + mb * 16 + (lane & 15), chunk));
     };
     bf16x8_t fa[NB], fb0, fb1;
     if (kb >= 0) {
+      const int chunk = lane >> 4;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
         fa[nb] = *reinterpret_cast<const bf16x8_t*>(ws + dswz(wrow[nb] + (lane & 15), chunk));
-      fb0 = tok_frag(0);
-      fb1 = tok_frag(1);
+      fb0 = tok_frag(0, chunk);
+      fb1 = tok_frag(1, chunk);
     }
     const int ks = kb + DSTAGES - 1;   // stage issued now, into the buffer freed by the barrier
     if (ks < nk) {
       uint8_t* base = smem + (ks % DSTAGES) * DSTAGE_BYTES;
 #pragma unroll
       for (int j = 0; j < DLOADS; ++j) {
-        const int r0 = 16 * (DLOADS * wave + j);
+        const int r0 = DRPL * (DLOADS * wave + j);
         const uint8_t* xsrc = xptr[j] + int64_t(ks) * DROWB;
         const uint8_t* wsrc = row_addr<TR>(a.phi, a.log2_page, wr[j], int64_t(ks) * DROWB);
         __builtin_amdgcn_global_load_lds(xsrc, base + r0 * DROWB, 16, 0, 0);
@@ -503,21 +509,32 @@ __global__ __launch_bounds__(NTHREADS, 1) void gemm_dma_kernel(const GemmArgs a)
       }
     }
     if (kb < 0) continue;
-    // token fragments two blocks ahead of the MFMAs that use them
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      bf16x8_t fbn = fb1;
-      if (mb + 2 < MB) fbn = tok_frag(mb + 2);
+    for (int s = 0; s < DBK / 32; ++s) {
+      const int chunk = s * 4 + (lane >> 4);
+      if (s > 0) {
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[nb], fb0, acc[nb][mb], 0, 0, 0);
-      fb0 = fb1;
-      fb1 = fbn;
-    }
+        for (int nb = 0; nb < NB; ++nb)
+          fa[nb] = *reinterpret_cast<const bf16x8_t*>(ws + dswz(wrow[nb] + (lane & 15), chunk));
+        fb0 = tok_frag(0, chunk);
+        fb1 = tok_frag(1, chunk);
+      }
+      // token fragments two blocks ahead of the MFMAs that use them
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      __builtin_amdgcn_sched_group_barrier(0x008, NB, 0);
-      if (mb + 2 < MB) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      for (int mb = 0; mb < MB; ++mb) {
+        bf16x8_t fbn = fb1;
+        if (mb + 2 < MB) fbn = tok_frag(mb + 2, chunk);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[nb], fb0, acc[nb][mb], 0, 0, 0);
+        fb0 = fb1;
+        fb1 = fbn;
+      }
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        __builtin_amdgcn_sched_group_barrier(0x008, NB, 0);
+        if (mb + 2 < MB) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
     }
     asm volatile("" ::: "memory");
   }
