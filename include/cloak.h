@@ -266,6 +266,25 @@ int cloak_remap_step(cloak_layout* layout, void* d_pool, int64_t max_pairs, int6
 int cloak_remap_step_host(cloak_layout* layout, void* h_pool, uint64_t h_pool_bytes, int64_t max_pairs,
                           int64_t* remaining);
 
+/* Hardware-translated twin (the paper's own mechanism, Section 4.2: the
+ * shuffled placement is resolved by the GPU's MMU and kernels read plain
+ * contiguous addresses).  Allocates every physical page of the pool as its
+ * own virtual-memory allocation (page_bytes must be a multiple of the
+ * device's allocation granularity, 2 MiB on MI355X) and maps them twice: in
+ * physical order at *d_pool_view, which the caller then passes as d_pool to
+ * every cloak_* call (cloak_pool_init, cloak_load, cloak_linear, ...), and in
+ * virtual order (virtual page v on physical page phi[v]) at a tensor view the
+ * library keeps.  While the twin exists the weight-reading kernels of that
+ * layout run untranslated on the tensor view; a remap swaps pages through
+ * the pool view, synchronises `stream`, then re-points the swapped pages'
+ * virtual addresses (host calls, not stream-ordered: no other stream may be
+ * reading the layout).  The library owns the memory; cloak_vmm_pool_free
+ * (or cloak_layout_free) releases it.  ESTATE before cloak_layout_to_device,
+ * on native layouts, during a remap, or where the device has no virtual
+ * memory management; EINVAL on a page size below the granularity. */
+int cloak_vmm_pool_create(cloak_layout* layout, void** d_pool_view);
+int cloak_vmm_pool_free(cloak_layout* layout);
+
 /* Host-side remap of a pool image h_pool (pool_bytes) and of the layout's
  * page map; the same result cloak_remap produces on the device.  Updates
  * only the host copy of phi: do not mix with device calls on one layout. */

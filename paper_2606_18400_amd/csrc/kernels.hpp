@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+struct cloak_layout;
+
 namespace cloak {
 
 // One weight tensor taking part in a launch.  Its stored rows are read from
@@ -123,6 +125,9 @@ hipError_t launch_quant_rows(const uint16_t* x, int64_t ldx, const int32_t* perm
 // Token count from which BF16 projections use MFMA (skinny split-K up to
 // kSkinnyMaxTokens, the 256x256 GEMM above) instead of the VALU GEMV.
 constexpr int64_t kGemmMinTokens = 5;
+
+// Re-point tensor-view pages va -> physical b, vb -> physical a (vmm.hip).
+hipError_t vmm_repoint(cloak_layout* L, int32_t va, int32_t vb, int32_t a, int32_t b);
 
 // ---- decoder-step kernels (serve.hip)
 struct EmbedArgs {

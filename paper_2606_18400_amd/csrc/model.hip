@@ -213,10 +213,10 @@ extern "C" int cloak_model_step(cloak_model* m, const cloak_step* s, void* d_ws,
   {
     const TensorInfo& te = L->tensors[m->embed];
     EmbedArgs e{};
-    e.pool = static_cast<const uint8_t*>(m->pool);
+    e.pool = static_cast<const uint8_t*>(L->kernel_pool(m->pool));
     e.phi = L->dev.phi;
     e.log2_page = L->log2_page;
-    e.translate = L->native() ? 0 : 1;
+    e.translate = L->kernel_translate() ? 1 : 0;
     e.vbase = te.vbase;
     e.vocab = c.vocab;
     e.row_bytes = int32_t(D * 2);
