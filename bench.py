@@ -63,8 +63,8 @@ def layer_bytes(cfg, M):
 class Variant:
     """A pool holding COPIES layer copies, plus activation buffers."""
 
-    def __init__(self, C, shapes, weights, cfg, flags, seed):
-        self.cw = C.CloakedWeights(shapes, cfg["page_bytes"], cfg["pool_bytes"], seed=seed, flags=flags)
+    def __init__(self, C, shapes, weights, cfg, flags, seed, vmm=False):
+        self.cw = C.CloakedWeights(shapes, cfg["page_bytes"], cfg["pool_bytes"], seed=seed, flags=flags, vmm=vmm)
         self.cw.load(weights)
         self.C = C
         self.cfg = cfg
@@ -179,18 +179,22 @@ def time_prefill(var, M, reps, warmup):
     return ms, k_ms
 
 
-def time_remap(var, reps):
+def time_remap(var, reps, with_copy=True):
     import torch
     pool_bytes = var.cfg["pool_bytes"]
     var.cw.remap(1000)   # warm
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
     start.record()
     for r in range(reps):
         var.cw.remap(1001 + r)
     stop.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / reps
+    wall_ms = (time.perf_counter() - t0) * 1e3 / reps
+    if not with_copy:
+        return dict(pool_bytes=pool_bytes, ms=ms, wall_ms=wall_ms, gbs=2 * pool_bytes / ms / 1e6)
     # device-to-device copy of the same number of bytes (read once, written once)
     half = pool_bytes // 2
     src = var.cw.pool[:half]
@@ -427,6 +431,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--batches", default="8,32,64", help="extra decode batch sizes reported beside M=1")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--vmm", action="store_true",
+                    help="also time the hardware-translated (VMM-mapped) twin of the cloaked layout")
     ap.add_argument("--remap-reps", type=int, default=5)
     ap.add_argument("--prefill-tokens", type=int, default=8192, help="prefill batch (0 skips the prefill pass)")
     ap.add_argument("--workload", default="layer", choices=["layer", "serve", "stack"],
@@ -505,6 +511,32 @@ def main():
     log("timing remap of the whole pool")
     remap = time_remap(cl, args.remap_reps)
     log(f"remap {remap['gbs']:.0f} GB/s vs device copy {remap['memcpy_gbs']:.0f} GB/s")
+    vmm = None
+    if args.vmm:
+        # the paper's own arrangement: the same cloaked layout with its pages
+        # mapped into a virtual range by the MMU, kernels untranslated
+        try:
+            log("uploading 16 copies into the hardware-translated (VMM) twin")
+            hw = Variant(C, shapes, weights, cfg, 0, seed=1, vmm=True)
+        except C.CloakError as e:
+            log(f"no VMM twin: {e}")
+            hw = None
+        if hw is not None:
+            v_ms, _ = time_steps(hw, 1, args.steps, args.warmup)
+            vmm = {"decode": {"1": dict(gbs=step_bytes / v_ms / 1e6, ms=v_ms, ratio_to_native=ms_nat / v_ms,
+                                        ratio_to_software=ms / v_ms)}}
+            for M in [int(m) for m in args.batches.split(",") if m]:
+                b = sum(layer_bytes(cfg, M))
+                m_hw, _ = time_steps(hw, M, max(args.steps // 4, 10), args.warmup)
+                vmm["decode"][str(M)] = dict(gbs=b / m_hw / 1e6, ms=m_hw)
+            if pm > 0:
+                h_ms, _ = time_prefill(hw, pm, max(args.steps // 20, 5), 2)
+                vmm["prefill"] = dict(tflops=layer_flops(cfg, pm) / h_ms / 1e9, ms=h_ms)
+            vmm["remap"] = time_remap(hw, max(1, args.remap_reps // 2), with_copy=False)
+            vmm["swiglu_kernel_ms"] = time_swiglu_loop(hw, 1, max(args.steps, 64))
+            log(f"VMM twin: M=1 {vmm['decode']['1']['gbs']:.0f} GB/s, remap {vmm['remap']['ms']:.1f} ms on the "
+                f"stream / {vmm['remap']['wall_ms']:.1f} ms wall")
+            hw.cw.close()
 
     achieved = swiglu_bytes / k_ms / 1e6
     digest = kernel_sources_digest()
@@ -532,6 +564,7 @@ def main():
         "decode": decode,
         "prefill": prefill,
         "remap": remap,
+        "vmm_twin": vmm,
         "copy_calibration": calib,
         "roofline": roofline,
         "cpu_baseline": cpu,
