@@ -543,6 +543,73 @@ def test_fp8_x_fp8_gemm_vs_oracle(C, M):
     cw.close()
 
 
+def test_decode_full_layer4096_bench_calls(C):
+    """The bench's decode step at full size (4096/14336/1024 BF16 layer, 2 MiB
+    pages over an 8 GiB pool) at every batch it reports, through the same
+    calls (fused q/k/v, o, cloak_swiglu then cloak_down with one workspace),
+    against FP64 on every output."""
+    import torch
+    cfg = synth.LAYER4096
+    d, f, kv = cfg["d_model"], cfg["d_ffn"], cfg["d_kv"]
+    shapes = decoder_shapes(d, f, kv, "bf16", layers=1)
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, cfg["page_bytes"], cfg["pool_bytes"], seed=1)
+    cw.load(ws, scs)
+    L = cw.layout
+    W = [w64(shapes, ws, scs, t) for t in range(len(shapes))]
+    for M in (1, 8, 32, 64):
+        x_np = synth.activations(M, d, "bf16", seed=100 + M)
+        x, x64 = to_device_x(x_np), values_f64(x_np)
+        need = max(C.cloak_linear_fused_ws_bytes(L, [0, 1, 2], M), C.cloak_ws_bytes(L, C.CLOAK_OP_LINEAR, 3, M),
+                   C.cloak_ws_bytes(L, C.CLOAK_OP_SWIGLU, 0, M), C.cloak_ws_bytes(L, C.CLOAK_OP_DOWN, 0, M))
+        wsb = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+        qkv = torch.empty((M, d + 2 * kv), dtype=torch.bfloat16, device="cuda")
+        o = torch.empty((M, d), dtype=torch.bfloat16, device="cuda")
+        h = torch.empty((M, f), dtype=torch.bfloat16, device="cuda")
+        y = torch.empty((M, d), dtype=torch.bfloat16, device="cuda")
+        C.cloak_linear_fused(L, cw.pool, [0, 1, 2], x, M, qkv, wsb, wsb.numel())
+        C.cloak_linear(L, cw.pool, 3, x, M, o, wsb, wsb.numel())
+        C.cloak_swiglu(L, cw.pool, 0, x, M, h, wsb, wsb.numel())
+        C.cloak_down(L, cw.pool, 0, h, M, y, wsb, wsb.numel())
+        ref_qkv = np.concatenate([ON.linear(x64, W[t]) for t in (0, 1, 2)], axis=1)
+        assert ON.normwise_err(values_f64(from_device(qkv)), ref_qkv) <= 1e-2, M
+        assert ON.normwise_err(values_f64(from_device(o)), ON.linear(x64, W[3])) <= 1e-2, M
+        ref_y, _ = ON.swiglu_ffn(x64, W[4], W[5], W[6])
+        assert ON.normwise_err(values_f64(from_device(y)), ref_y) <= 1e-2, M
+    cw.close()
+    torch.cuda.empty_cache()
+
+
+def test_fp8_stack_layer5120_full_size_sampled(C):
+    """One layer of the 64-layer FP8 stack at full size (5120/27648/1024 E4M3
+    with row scales) and the 152064 x 5120 BF16 head, 2 MiB pages, at decode
+    batches 1, 64 and 256, against FP64 on sampled tokens."""
+    import torch
+    cfg = synth.STACK5120
+    d, f, kv, V = cfg["d_model"], cfg["d_ffn"], cfg["d_kv"], cfg["vocab"]
+    shapes = decoder_shapes(d, f, kv, "fp8", layers=1, extra=[(-1, "head", V, d, "bf16")])
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, cfg["page_bytes"], 4 << 30, seed=9)
+    cw.load(ws, scs)
+    rng = np.random.Generator(np.random.PCG64(17))
+    W = {t: w64(shapes, ws, scs, t) for t in (0, 3, 4, 5, 6, 7)}
+    for M in (1, 64, 256):
+        x_np = synth.activations(M, d, "bf16", seed=200 + M)
+        x = to_device_x(x_np)
+        rows = np.unique(np.concatenate([[0, M - 1], rng.choice(M, size=min(M, 10), replace=False)]))
+        x64 = values_f64(x_np[rows])
+        for t in (0, 3, 7):        # q, o and the head
+            y = from_device(cw.linear(t, x))[rows]
+            tol = TOL[shapes[t][4]]
+            assert ON.normwise_err(values_f64(y), ON.linear(x64, W[t])) <= tol, (M, t)
+        y = from_device(cw.mlp(0, x))[rows]
+        ref, _ = ON.swiglu_ffn(x64, W[4], W[5], W[6])
+        assert ON.normwise_err(values_f64(y), ref) <= TOL["fp8"], M
+    del W
+    cw.close()
+    torch.cuda.empty_cache()
+
+
 def test_prefill_full_layer4096_sampled_tokens(C):
     """The 4096/14336 layer at M = 8192 prefill tokens, 2 MiB pages over an
     8 GiB pool, checked against FP64 on 48 sampled tokens."""
