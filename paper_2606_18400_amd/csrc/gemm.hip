@@ -413,8 +413,8 @@ constexpr int DCH = DROWB / 16;             // 16-byte chunks per tile row
 constexpr int DRPL = 1024 / DROWB;          // tile rows one wave load fills
 constexpr int DTILE = BM * DROWB;           // bytes per operand per stage
 constexpr int DSTAGES = 4;
+constexpr int DWAVES = 8;                   // waves per workgroup of the BF16 prefill GEMM
 constexpr int DSTAGE_BYTES = 2 * DTILE;
-constexpr int DLOADS = BM / DRPL / (NTHREADS / 64);   // wave loads per operand per stage
 constexpr int DMA_AHEAD = DSTAGES - 2;      // younger stages still in flight at a wait
 static_assert(DSTAGES * DSTAGE_BYTES <= 4 * TILE_BYTES, "ring exceeds the dynamic LDS reserved");
 
@@ -430,15 +430,29 @@ __device__ inline void wait_vm_lgkm0() {
   __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (0 << 8) | ((N >> 4) << 14));
 }
 
-template <bool TR, int EPI>
-__global__ __launch_bounds__(NTHREADS, 1) void gemm_dma_kernel(const GemmArgs a) {
+// WAVES = 8: a 2 x 4 wave grid of 128 x 64 wave tiles (two waves per SIMD);
+// WAVES = 4: 2 x 2 of 128 x 128 (one wave per SIMD, accumulators in the
+// accumulator registers).
+template <int WAVES>
+struct DmaGeom {
+  static constexpr int NT = 64 * WAVES;
+  static constexpr int WGN = WAVES / 2;          // waves along the weight rows
+  static constexpr int WTM = BM / 2, WTN = BN / WGN;
+  static constexpr int MBK = WTM / 16, NBK = WTN / 16;
+  static constexpr int LOADS = BM / DRPL / WAVES;   // wave loads per operand per stage
+};
+
+template <bool TR, int EPI, int WAVES>
+__global__ __launch_bounds__(64 * WAVES, 1) void gemm_dma_kernel(const GemmArgs a) {
+  using G = DmaGeom<WAVES>;
+  constexpr int NB = G::NBK, MB = G::MBK, WM = G::WTM, WN = G::WTN, DLOADS = G::LOADS;
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   int tile_m, tile_n;
   if (!tile_coords(a, tile_m, tile_n)) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+  const int wm = wave / G::WGN, wn = wave % G::WGN;
 
   // load slots: tile row DRPL * (DLOADS * wave + j) + lane / DCH of both operands
   const uint8_t* xptr[DLOADS];
@@ -467,7 +481,7 @@ __global__ __launch_bounds__(NTHREADS, 1) void gemm_dma_kernel(const GemmArgs a)
 #pragma unroll
     for (int j = 0; j < MB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   int wrow[NB];
-  wave_rows<EPI>(wn, wrow);
+  wave_rows<EPI, NB, WN>(wn, wrow);
 
   // iterations kb < 0 only issue the first DSTAGES - 1 stages
   const int nk = a.K / DBK;
@@ -538,7 +552,7 @@ __global__ __launch_bounds__(NTHREADS, 1) void gemm_dma_kernel(const GemmArgs a)
     }
     asm volatile("" ::: "memory");
   }
-  gemm_epilogue<EPI, false>(a, acc, tile_m, tile_n, wm, wn, wrow, lane);
+  gemm_epilogue<EPI, false, NB, MB, WM, WN>(a, acc, tile_m, tile_n, wm, wn, wrow, lane);
 }
 
 // x_out[m][j] = x[m][perm[j]]: the activations of a down projection put in
@@ -836,8 +850,9 @@ hipError_t launch_gemm(const GemmArgs& a, bool translate, hipStream_t s) {
     fn = translate ? (sw ? gemm_kernel<true, kSwiGLU, true, false> : gemm_kernel<true, kStore, true, false>)
                    : (sw ? gemm_kernel<false, kSwiGLU, true, false> : gemm_kernel<false, kStore, true, false>);
   else
-    fn = translate ? (sw ? gemm_dma_kernel<true, kSwiGLU> : gemm_dma_kernel<true, kStore>)
-                   : (sw ? gemm_dma_kernel<false, kSwiGLU> : gemm_dma_kernel<false, kStore>);
+    fn = translate ? (sw ? gemm_dma_kernel<true, kSwiGLU, DWAVES> : gemm_dma_kernel<true, kStore, DWAVES>)
+                   : (sw ? gemm_dma_kernel<false, kSwiGLU, DWAVES> : gemm_dma_kernel<false, kStore, DWAVES>);
+  const int threads = f8 ? NTHREADS : 64 * DWAVES;
 
   static bool attr_set[16] = {};
   const int key = (translate ? 2 : 0) + (sw ? 1 : 0) + (f8 ? 4 : 0) + (a8 ? 8 : 0);
@@ -847,7 +862,7 @@ hipError_t launch_gemm(const GemmArgs& a, bool translate, hipStream_t s) {
     if (e != hipSuccess) return e;
     attr_set[key] = true;
   }
-  hipLaunchKernelGGL(fn, dim3(blocks), dim3(NTHREADS), lds, s, a);
+  hipLaunchKernelGGL(fn, dim3(blocks), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
 
