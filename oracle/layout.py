@@ -8,7 +8,12 @@ What the paper fixes (CloakLM, arXiv 2606.18400):
   shuffling"; Table 1a).
 * Intra-layer shuffling is named in the abstract without a mechanism.
   Reading: a seeded permutation of each FFN's hidden neurons -- rows of gate
-  and up, columns of down -- which leaves the FFN function unchanged.
+  and up, columns of down -- which leaves the FFN function unchanged.  The
+  same reading extends to attention when q/k/v/o carry a head size: whole
+  key/value head groups are permuted, the query heads inside a group are
+  permuted, and the value dimensions inside a head are permuted, all in ways
+  the attention function cannot see (query/key dimensions stay in place: the
+  rotary embedding pairs them by position inside the head).
 * Physical page remapping: tensors are spread over non-contiguous,
   non-sequential physical pages of a pool (Section 4.2, "Physical page
   remapping"; Table 1b).  Pages are 2 MB in the paper; any power of two works.
@@ -26,6 +31,15 @@ definition, never through code):
 * ``pi[l]`` = Fisher-Yates(d_ffn, tag 2, idx l).  Shuffled storage is
   ``gate_s[j] = gate[pi[j]]``, ``up_s[j] = up[pi[j]]``, ``down_s[:, j] =
   down[:, pi[j]]`` (gather convention: slot ``j`` holds item ``pi[j]``).
+* Attention heads of layer ``l`` (only when its q/k/v/o carry a head size
+  ``hd``; ``Hq = q.n_out / hd`` query heads, ``Hkv = k.n_out / hd`` key/value
+  heads, ``G = Hq / Hkv``): one stream ``g`` = sub-stream(tag 6, idx l) draws,
+  in this order, ``rho`` = Fisher-Yates(Hkv, g), then ``theta[c]`` =
+  Fisher-Yates(G, g) for c = 0..Hkv-1, then ``chi`` = Fisher-Yates(hd, g).
+  Stored key/value head ``c`` holds logical head ``rho[c]``; stored query
+  head ``c*G + i`` holds logical query head ``rho[c]*G + theta[c][i]``; value
+  dimension ``d`` of a stored head holds logical dimension ``chi[d]``.  Rows of
+  q and k keep their dimension order, rows of v and columns of o take ``chi``.
 * ``phi`` = Fisher-Yates(P, tag 3) over all ``P = pool_bytes / page_bytes``
   pages: virtual page ``v`` lives at physical page ``phi[v]``; virtual pages
   ``V..P-1`` are the free pages, which hold zeros.
@@ -39,6 +53,7 @@ import numpy as np
 from . import prng
 
 KINDS = ("q", "k", "v", "o", "gate", "up", "down", "embed", "head")
+ATTN_KINDS = ("q", "k", "v", "o")
 ELT_BYTES = {"f32": 4, "bf16": 2, "fp8": 1}
 STORAGE_DTYPE = {"f32": np.float32, "bf16": np.uint16, "fp8": np.uint8}
 FFN_ROW_PERMUTED = ("gate", "up")   # hidden dim is N: rows permuted
@@ -46,22 +61,30 @@ FFN_COL_PERMUTED = ("down",)        # hidden dim is K: columns permuted
 
 
 class Shape:
-    """One weight tensor: (layer, kind, n_out, k_in, dtype)."""
+    """One weight tensor: (layer, kind, n_out, k_in, dtype[, head_dim]).
 
-    def __init__(self, layer, kind, n_out, k_in, dtype):
+    ``head_dim`` (q/k/v/o only) asks for the attention-head permutation; 0
+    leaves attention unpermuted.
+    """
+
+    def __init__(self, layer, kind, n_out, k_in, dtype, head_dim=0):
         if kind not in KINDS:
             raise ValueError(f"unknown kind {kind}")
         if dtype not in ELT_BYTES:
             raise ValueError(f"unknown dtype {dtype}")
+        if head_dim and kind not in ATTN_KINDS:
+            raise ValueError("only q/k/v/o carry a head size")
         self.layer, self.kind = int(layer), kind
         self.n_out, self.k_in, self.dtype = int(n_out), int(k_in), dtype
+        self.head_dim = int(head_dim)
 
     @property
     def nbytes(self):
         return self.n_out * self.k_in * ELT_BYTES[self.dtype]
 
     def __repr__(self):
-        return f"Shape({self.layer},{self.kind},{self.n_out},{self.k_in},{self.dtype})"
+        hd = f",hd={self.head_dim}" if self.head_dim else ""
+        return f"Shape({self.layer},{self.kind},{self.n_out},{self.k_in},{self.dtype}{hd})"
 
 
 class Layout:
@@ -76,6 +99,43 @@ class Layout:
             return s.n_out
         if s.kind in FFN_COL_PERMUTED:
             return s.k_in
+        return None
+
+    def row_perm(self, t):
+        """Stored row j of tensor t holds logical row p[j] (None: unpermuted)."""
+        s = self.shapes[t]
+        if s.kind in FFN_ROW_PERMUTED:
+            return list(self.pi[s.layer])
+        if s.kind in ("q", "k", "v") and s.layer in self.heads:
+            a = self.heads[s.layer]
+            hd, G = a["head_dim"], a["group"]
+            out = []
+            if s.kind == "q":
+                for c in range(a["n_kv"]):
+                    for i in range(G):
+                        h = a["rho"][c] * G + a["theta"][c][i]
+                        out += [h * hd + d for d in range(hd)]
+            else:
+                dims = a["chi"] if s.kind == "v" else list(range(hd))
+                for c in range(a["n_kv"]):
+                    out += [a["rho"][c] * hd + dims[d] for d in range(hd)]
+            return out
+        return None
+
+    def col_perm(self, t):
+        """Stored column j of tensor t holds logical column p[j] (None: unpermuted)."""
+        s = self.shapes[t]
+        if s.kind in FFN_COL_PERMUTED:
+            return list(self.pi[s.layer])
+        if s.kind == "o" and s.layer in self.heads:
+            a = self.heads[s.layer]
+            hd, G = a["head_dim"], a["group"]
+            out = []
+            for c in range(a["n_kv"]):
+                for i in range(G):
+                    h = a["rho"][c] * G + a["theta"][c][i]
+                    out += [h * hd + a["chi"][d] for d in range(hd)]
+            return out
         return None
 
 
@@ -108,6 +168,9 @@ def build_layout(seed, shapes, page_bytes, pool_bytes, identity=False):
         pi[layer] = list(range(h)) if identity else prng.fisher_yates(
             h, prng.substream(seed, prng.TAG_HIDDEN_PERM, layer))
 
+    heads = {layer: _draw_heads(seed, layer, four, identity)
+             for layer, four in sorted(_attention_groups(shapes).items())}
+
     # Virtual pages: tensors in sigma order, each starting on a fresh page.
     npages = [-(-s.nbytes // page_bytes) for s in shapes]
     vbase = [0] * T
@@ -125,8 +188,43 @@ def build_layout(seed, shapes, page_bytes, pool_bytes, identity=False):
         P, prng.substream(seed, prng.TAG_PAGE_MAP, 0))
 
     return Layout(seed=seed, shapes=list(shapes), page_bytes=page_bytes,
-                  pool_bytes=pool_bytes, P=P, V=V, T=T, sigma=sigma, pi=pi,
+                  pool_bytes=pool_bytes, P=P, V=V, T=T, sigma=sigma, pi=pi, heads=heads,
                   npages=npages, vbase=vbase, phi=phi, identity=identity)
+
+
+def _attention_groups(shapes):
+    """Layers whose q/k/v/o carry a head size -> {kind: Shape}, validated."""
+    groups = {}
+    for s in shapes:
+        if s.head_dim:
+            groups.setdefault(s.layer, {})[s.kind] = s
+    for layer, four in groups.items():
+        if layer < 0:
+            raise ValueError("attention-head permutation needs a layer index >= 0")
+        if set(four) != set(ATTN_KINDS):
+            raise ValueError(f"layer {layer}: q, k, v and o must all carry the head size")
+        hd = four["q"].head_dim
+        q, k, v, o = (four[x] for x in ATTN_KINDS)
+        if any(x.head_dim != hd for x in (k, v, o)):
+            raise ValueError(f"layer {layer}: head sizes disagree")
+        if (q.n_out % hd or k.n_out % hd or k.n_out != v.n_out or o.k_in != q.n_out
+                or not (q.k_in == k.k_in == v.k_in) or (q.n_out // hd) % (k.n_out // hd)):
+            raise ValueError(f"layer {layer}: q/k/v/o sizes do not form whole heads")
+    return groups
+
+
+def _draw_heads(seed, layer, four, identity):
+    hd = four["q"].head_dim
+    n_kv = four["k"].n_out // hd
+    G = four["q"].n_out // hd // n_kv
+    if identity:
+        rho, theta, chi = list(range(n_kv)), [list(range(G)) for _ in range(n_kv)], list(range(hd))
+    else:
+        g = prng.substream(seed, prng.TAG_HEAD_PERM, layer)
+        rho = prng.fisher_yates(n_kv, g)
+        theta = [prng.fisher_yates(G, g) for _ in range(n_kv)]
+        chi = prng.fisher_yates(hd, g)
+    return dict(head_dim=hd, n_kv=n_kv, group=G, rho=rho, theta=theta, chi=chi)
 
 
 def upload_order(layout, t):
@@ -138,37 +236,38 @@ def upload_order(layout, t):
 
 
 def shuffle_tensor(layout, t, w):
-    """Logical nn.Linear array -> stored (hidden-neuron permuted) array."""
+    """Logical nn.Linear array -> stored (hidden-neuron / head permuted) array."""
     s = layout.shapes[t]
     w = np.asarray(w)
     assert w.shape == (s.n_out, s.k_in)
-    if s.kind in FFN_ROW_PERMUTED:
-        return w[np.asarray(layout.pi[s.layer]), :]
-    if s.kind in FFN_COL_PERMUTED:
-        return w[:, np.asarray(layout.pi[s.layer])]
+    rp, cp = layout.row_perm(t), layout.col_perm(t)
+    if rp is not None:
+        w = w[np.asarray(rp), :]
+    if cp is not None:
+        w = w[:, np.asarray(cp)]
     return w
 
 
 def unshuffle_tensor(layout, t, ws):
-    """Inverse of shuffle_tensor (scatter back through pi)."""
-    s = layout.shapes[t]
-    out = np.empty_like(ws)
-    if s.kind in FFN_ROW_PERMUTED:
-        out[np.asarray(layout.pi[s.layer]), :] = ws
-    elif s.kind in FFN_COL_PERMUTED:
-        out[:, np.asarray(layout.pi[s.layer])] = ws
-    else:
-        out[...] = ws
+    """Inverse of shuffle_tensor (scatter back through the permutations)."""
+    rp, cp = layout.row_perm(t), layout.col_perm(t)
+    out = np.array(ws, copy=True)
+    if cp is not None:
+        tmp = np.empty_like(out)
+        tmp[:, np.asarray(cp)] = out
+        out = tmp
+    if rp is not None:
+        tmp = np.empty_like(out)
+        tmp[np.asarray(rp), :] = out
+        out = tmp
     return out
 
 
 def shuffle_scales(layout, t, scales):
     """Per-output-channel scales follow the rows they belong to."""
-    s = layout.shapes[t]
     scales = np.asarray(scales, dtype=np.float32)
-    if s.kind in FFN_ROW_PERMUTED:
-        return scales[np.asarray(layout.pi[s.layer])]
-    return scales
+    rp = layout.row_perm(t)
+    return scales if rp is None else scales[np.asarray(rp)]
 
 
 def tensor_stream(layout, t, w):

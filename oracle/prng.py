@@ -15,7 +15,8 @@ Readings taken here (listed with the other readings in the design notes):
   xor-shift 31, "variant 13" constants).
 * Independent sub-streams: ``state0 = mix64(seed XOR mix64((tag << 32) | idx))``
   with tags 1 tensor order, 2 hidden permutation of layer ``idx``, 3 page map,
-  4 upload order of tensor ``idx``, 5 remap matching (keyed by the remap seed).
+  4 upload order of tensor ``idx``, 5 remap matching (keyed by the remap seed),
+  6 attention-head permutation of layer ``idx``.
 * Bounded draw: rejection of the ``2**64 mod n`` lowest outputs, then
   ``r mod n`` -- exactly uniform on ``[0, n)``.
 * Permutation: Fisher-Yates in Durstenfeld's in-place form, walking ``i`` from
@@ -32,6 +33,7 @@ TAG_HIDDEN_PERM = 2
 TAG_PAGE_MAP = 3
 TAG_UPLOAD_ORDER = 4
 TAG_REMAP = 5
+TAG_HEAD_PERM = 6
 
 
 def mix64(z: int) -> int:
