@@ -4,7 +4,8 @@
  * CloakLM (arXiv 2606.18400) hides where model weights sit in accelerator
  * memory: tensors are placed in a seeded random order (inter-layer shuffle,
  * Section 4.2 and Table 1a), each FFN's hidden neurons are permuted
- * (intra-layer shuffle, named in the abstract), and the resulting byte
+ * (intra-layer shuffle, named in the abstract; optionally the attention
+ * heads too), and the resulting byte
  * streams are cut into pages scattered over a pool through a seeded
  * virtual->physical page map that is re-randomised periodically (Section 4.2,
  * "Physical page remapping", Table 1b).  All randomness is drawn from one seed
@@ -44,13 +45,27 @@
  * Generator: SplitMix64 (Steele, Lea, Flood, OOPSLA 2014).  Sub-stream for
  * (seed, tag, idx) starts from mix64(seed ^ mix64((tag << 32) | idx)).  Tags:
  * 1 tensor order, 2 hidden permutation of layer idx, 3 page map, 4 upload
- * order of tensor idx, 5 remap matching (keyed by the remap seed).
+ * order of tensor idx, 5 remap matching (keyed by the remap seed), 6 attention
+ * heads of layer idx.
  * bounded(n) rejects the (2^64 mod n) lowest outputs and returns r mod n;
  * permutations are Fisher-Yates (Durstenfeld), i from n-1 down to 1 swapping
  * a[i] with a[bounded(i+1)]; gather convention (slot j holds a[j]).
  *   sigma   = FY(T, tag 1)           tensor sigma[i] is i-th in the page stream
  *   pi_l    = FY(d_ffn, tag 2, l)    gate_s[j] = gate[pi[j]], up_s[j] = up[pi[j]],
  *                                    down_s[:, j] = down[:, pi[j]]
+ *   heads_l (only for a layer whose q/k/v/o give head_dim = hd > 0; Hq = q.N/hd,
+ *           Hkv = k.N/hd, G = Hq/Hkv) one stream g = sub-stream(tag 6, l) draws
+ *           rho = FY(Hkv, g), then theta_c = FY(G, g) for c = 0..Hkv-1, then
+ *           chi = FY(hd, g).  Stored kv head c holds logical head rho[c];
+ *           stored query head c*G+i holds logical head rho[c]*G + theta_c[i];
+ *           value dimension d of a head holds logical dimension chi[d]:
+ *             q_s[(c*G+i)*hd + d]    = q[(rho[c]*G + theta_c[i])*hd + d]
+ *             k_s[c*hd + d]          = k[rho[c]*hd + d]
+ *             v_s[c*hd + d]          = v[rho[c]*hd + chi[d]]
+ *             o_s[:, (c*G+i)*hd + d] = o[:, (rho[c]*G + theta_c[i])*hd + chi[d]]
+ *           Attention over the stored heads (query head h reads kv head h/G)
+ *           followed by o_s computes the logical layer exactly (rotary
+ *           dimensions are not moved).
  *   vbase   each tensor starts on a fresh virtual page, tensors in sigma order,
  *           npages = ceil(N*K*elt / page_bytes), zero padded
  *   phi     = FY(P, tag 3) over all P = pool_bytes/page_bytes pages; virtual
@@ -89,14 +104,17 @@ typedef enum {
 
 /* One weight tensor, nn.Linear orientation: n_out rows of k_in elements.
  * `layer` groups gate/up/down under one hidden permutation (any value fits in
- * 32 bits; embed/head conventionally use -1). */
+ * 32 bits; embed/head conventionally use -1) and q/k/v/o under one head
+ * permutation.  `head_dim` > 0 on q, k, v and o of a layer (all four, same
+ * value, layer >= 0) asks for that layer's attention-head permutation; 0
+ * leaves attention unpermuted and must be 0 for every other kind. */
 typedef struct {
   int32_t layer;
   int32_t kind;  /* cloak_kind */
   int64_t n_out;
   int64_t k_in;
   int32_t dtype; /* cloak_dtype */
-  int32_t reserved;
+  int32_t head_dim;
 } cloak_shape;
 
 /* Layout flags. */
@@ -123,6 +141,12 @@ typedef struct {
 #define CLOAK_QUERY_DFFN        14  /* int64: hidden size of layer `index` (0 if no FFN) */
 #define CLOAK_QUERY_REMAP_PENDING 15 /* int64: page pairs of the remap in progress not yet
                                         swapped (0 if none)                              */
+#define CLOAK_QUERY_ROW_PERM    16  /* int32[N] of tensor `index`: stored row j holds
+                                       logical row p[j] (identity if rows stay put)      */
+#define CLOAK_QUERY_COL_PERM    17  /* int32[K] of tensor `index`: stored column j holds
+                                       logical column p[j] (identity if columns stay)   */
+#define CLOAK_QUERY_SHAPE       18  /* int64[4] of tensor `index`: n_out, k_in, dtype,
+                                       head_dim                                          */
 
 /* Workspace selectors for cloak_ws_bytes(). */
 #define CLOAK_OP_LINEAR 1   /* index = tensor */
@@ -133,9 +157,10 @@ typedef struct {
 /* Draw the layout from `seed` for `n_shapes` tensors (Section 5: all
  * permutations and page placements are fixed before any transfer).  Host
  * only, touches no device.  page_bytes must be a power of two >= 1024 and
- * divide pool_bytes.  Errors: EINVAL (sizes, kinds, dtypes), ESHAPE
- * (duplicate (layer, kind), inconsistent hidden sizes), ENOMEM (the tensors
- * need more than P pages).  On success *out owns the layout. */
+ * divide pool_bytes.  Errors: EINVAL (sizes, kinds, dtypes, head_dim on a
+ * non-attention kind), ESHAPE (duplicate (layer, kind), inconsistent hidden
+ * sizes, q/k/v/o of a head-permuted layer missing or not whole heads),
+ * ENOMEM (the tensors need more than P pages).  On success *out owns the layout. */
 int cloak_layout_build(uint64_t seed, const cloak_shape* shapes, int32_t n_shapes,
                        uint64_t page_bytes, uint64_t pool_bytes, uint32_t flags,
                        cloak_layout** out);
@@ -191,8 +216,9 @@ uint64_t cloak_linear_fused_ws_bytes(const cloak_layout* layout, const int32_t* 
                                      int64_t M);
 
 /* y[M][N] = x[M][K] . W^T for tensor `tensor`, with x and y in LOGICAL
- * order: for gate/up the kernel scatters stored row j to column pi[j]; for
- * down it gathers x through pi while staging it.  Weights are read straight
+ * order: for gate/up (and head-permuted q/k/v) the kernel scatters stored
+ * row j to column p[j]; for down (and head-permuted o) it gathers x through
+ * the column permutation while staging it.  Weights are read straight
  * from the scattered pages (virtual tile -> physical page resolved in the
  * kernel).  M = 0 is a no-op.  Workspace as reported by cloak_ws_bytes. */
 int cloak_linear(const cloak_layout* layout, const void* d_pool, int32_t tensor,

@@ -110,8 +110,7 @@ WSeg make_seg(const cloak_layout* L, int32_t t, bool scatter, int32_t row0, int3
   s.vbase = ti.vbase;
   s.npages = ti.npages;
   s.out_perm = nullptr;
-  if (scatter && ti.perm_layer >= 0 && is_row_permuted(ti.shape.kind))
-    s.out_perm = L->dev.perms + L->ffn[ti.perm_layer].dev_off;
+  if (scatter) s.out_perm = L->dev_row_perm(t);
   s.scale = ti.shape.dtype == CLOAK_FP8_E4M3 ? L->dev.scales + ti.scale_off : nullptr;
   s.rows = int32_t(ti.shape.n_out);
   s.row0 = row0;
@@ -164,7 +163,7 @@ extern "C" int cloak_layout_to_device(cloak_layout* L, void* stream) {
   HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
   d.stage_event = ev;
   std::vector<int32_t> perms(size_t(L->n_perm > 0 ? L->n_perm : 1), 0);
-  for (const auto& f : L->ffn) std::memcpy(perms.data() + f.dev_off, f.pi.data(), size_t(f.d_ffn) * 4);
+  for (const auto& pt : L->perms) std::memcpy(perms.data() + pt.dev_off, pt.p.data(), pt.p.size() * 4);
   HIP_TRY(hipMemcpyAsync(d.phi, L->phi.data(), P * 4, hipMemcpyHostToDevice, st), "upload page map");
   HIP_TRY(hipMemcpyAsync(d.perms, perms.data(), perms.size() * 4, hipMemcpyHostToDevice, st), "upload permutations");
   HIP_TRY(hipMemsetAsync(d.scales, 0, size_t(L->n_scales > 0 ? L->n_scales : 1) * 4, st), "clear scales");
@@ -230,10 +229,10 @@ extern "C" int cloak_load(cloak_layout* L, void* d_pool, int32_t tensor, const v
   }
   std::vector<float> s;  // must outlive the copy below (synchronised at the end)
   if (fp8) {
-    // scales follow their rows: stored row j of gate/up carries s[pi[j]]
+    // scales follow their rows: stored row j carries s[p[j]]
     s.resize(size_t(ti.shape.n_out));
-    const int32_t* pi = (ti.perm_layer >= 0 && is_row_permuted(ti.shape.kind)) ? L->ffn[ti.perm_layer].pi.data() : nullptr;
-    for (int64_t j = 0; j < ti.shape.n_out; ++j) s[j] = h_scales[pi ? pi[j] : j];
+    const int32_t* rp = L->row_perm(tensor);
+    for (int64_t j = 0; j < ti.shape.n_out; ++j) s[j] = h_scales[rp ? rp[j] : j];
     HIP_TRY(hipMemcpyAsync(L->dev.scales + ti.scale_off, s.data(), s.size() * 4, hipMemcpyHostToDevice, st),
             "upload scales");
   }
@@ -493,7 +492,7 @@ int linear_proj(const cloak_layout* L, const int32_t* tensors, int32_t n, Proj& 
       set_error("%s: fused tensors must share K and dtype", fn);
       return CLOAK_ESHAPE;
     }
-    any_down |= ti.perm_layer >= 0 && is_col_permuted(ti.shape.kind);
+    any_down |= ti.col_perm >= 0;
     p.rows += ti.shape.n_out;
     p.tensors[i] = tensors[i];
   }
@@ -501,11 +500,11 @@ int linear_proj(const cloak_layout* L, const int32_t* tensors, int32_t n, Proj& 
   p.mode = kStore;
   p.scatter = true;
   if (any_down && n > 1) {
-    set_error("%s: a down projection (permuted K) cannot be fused with other tensors", fn);
+    set_error("%s: a tensor with permuted columns (down, head-permuted o) cannot be fused with others", fn);
     return CLOAK_ESHAPE;
   }
   p.gather = any_down;
-  p.x_perm = (any_down && L->dev.perms) ? L->dev.perms + L->ffn[t0.perm_layer].dev_off : nullptr;
+  p.x_perm = any_down ? L->dev_col_perm(tensors[0]) : nullptr;
   const int elt = elt_bytes(p.dtype);
   if ((p.K * elt) % 16 != 0 || (p.K * elt + 1023) / 1024 > 64) {
     set_error("%s: rows must be a multiple of 16 bytes and at most 64 KiB (K*elt = %lld)", fn,
@@ -617,6 +616,23 @@ extern "C" int cloak_linear_fused(const cloak_layout* L, const void* d_pool, con
   return run_proj(L, d_pool, p, d_x, p.K, M, d_y, p.rows, d_ws, ws_bytes, static_cast<hipStream_t>(stream),
                   "cloak_linear");
 }
+
+namespace cloak {
+// The decoder step's projections: results stay in stored order (permuted
+// rows are not scattered, permuted columns not gathered), since attention and
+// the FFN consume them in that order and cannot tell.
+int linear_stored(const cloak_layout* L, const void* d_pool, const int32_t* tensors, int32_t n, const void* d_x,
+                  int64_t M, void* d_y, void* d_ws, uint64_t ws_bytes, void* stream) {
+  Proj p;
+  if (int rc = linear_proj(L, tensors, n, p, "cloak_model_step")) return rc;
+  p.scatter = false;
+  p.gather = false;
+  p.x_perm = nullptr;
+  if (M == 0) return CLOAK_OK;
+  return run_proj(L, d_pool, p, d_x, p.K, M, d_y, p.rows, d_ws, ws_bytes, static_cast<hipStream_t>(stream),
+                  "cloak_model_step");
+}
+}  // namespace cloak
 
 extern "C" int cloak_linear(const cloak_layout* L, const void* d_pool, int32_t tensor, const void* d_x, int64_t M,
                             void* d_y, void* d_ws, uint64_t ws_bytes, void* stream) {

@@ -2,7 +2,9 @@
 // kernel of a step (embedding through argmax), so the host pays one call per
 // step instead of ~10 per layer.  The projections are the cloaked entry
 // points (cloak_linear_fused / cloak_linear / cloak_swiglu / cloak_down),
-// which pick the GEMV or the MFMA GEMM by token count.
+// which pick the GEMV or the MFMA GEMM by token count.  Like the FFN's hidden
+// units, attention runs on the heads in their stored (permuted) order: q/k/v
+// results are not scattered and o reads the attention output as stored.
 
 #include <hip/hip_runtime.h>
 
@@ -122,6 +124,10 @@ extern "C" int cloak_model_create(const cloak_layout* L, const void* d_pool, con
               "n_heads/n_kv_heads in 1..8)");
     return CLOAK_EINVAL;
   }
+  if (reinterpret_cast<uintptr_t>(d_pool) % 256 != 0) {
+    set_error("cloak_model_create: pool must be 256-byte aligned");
+    return CLOAK_EINVAL;
+  }
   if (!L->dev.phi) {
     set_error("cloak_model_create: layout has no device tables");
     return CLOAK_ESTATE;
@@ -150,6 +156,13 @@ extern "C" int cloak_model_create(const cloak_layout* L, const void* d_pool, con
         return CLOAK_ESHAPE;
       }
       m->t.push_back(t);
+    }
+    const AttnPerm* ap = L->attn_of_layer(l);
+    if (ap && ap->head_dim != c.head_dim) {
+      set_error("cloak_model_create: layer %d is head-permuted with head_dim %lld, the model uses %d", l,
+                (long long)ap->head_dim, c.head_dim);
+      delete m;
+      return CLOAK_ESHAPE;
     }
   }
   m->embed = L->find_tensor(-1, CLOAK_EMBED);
@@ -237,7 +250,7 @@ extern "C" int cloak_model_step(cloak_model* m, const cloak_step* s, void* d_ws,
     na.D = int32_t(D);
     na.eps = c.norm_eps;
     HIP_TRY(launch_rmsnorm(na, int(T), st), "cloak_model_step(norm)");
-    if (int rc = cloak_linear_fused(L, m->pool, t, 3, h, T, qkv, scratch, sb, stream)) return rc;
+    if (int rc = linear_stored(L, m->pool, t, 3, h, T, qkv, scratch, sb, stream)) return rc;
     uint16_t* kc = m->kv + int64_t(2 * l) * layer_kv;
     uint16_t* vc = kc + layer_kv;
     RopeArgs ra{};
@@ -280,7 +293,7 @@ extern "C" int cloak_model_step(cloak_model* m, const cloak_step* s, void* d_ws,
     aa.out = attn;
     aa.ldo = D;
     HIP_TRY(launch_attention(aa, st), "cloak_model_step(attention)");
-    if (int rc = cloak_linear(L, m->pool, t[3], attn, T, o, scratch, sb, stream)) return rc;
+    if (int rc = linear_stored(L, m->pool, t + 3, 1, attn, T, o, scratch, sb, stream)) return rc;
     NormArgs nb = na;
     nb.add = o;
     nb.r_out = r;

@@ -37,11 +37,13 @@ LLAMA8B = dict(n_layers=32, d_model=4096, n_heads=32, n_kv_heads=8, head_dim=128
                theta=500000.0, eps=1e-5)
 
 
-def model_shapes(cfg):
+def model_shapes(cfg, head_perm=True):
+    """Every tensor of the decoder; with head_perm the attention heads are permuted too."""
     shapes = []
     kvd = cfg["n_kv_heads"] * cfg["head_dim"]
+    hd = cfg["head_dim"] if head_perm else 0
     for l in range(cfg["n_layers"]):
-        shapes += synth.decoder_layer_shapes(cfg["d_model"], cfg["d_ffn"], kvd, "bf16", layer=l)
+        shapes += synth.decoder_layer_shapes(cfg["d_model"], cfg["d_ffn"], kvd, "bf16", layer=l, head_dim=hd)
     shapes += [(-1, "embed", cfg["vocab"], cfg["d_model"], "bf16"), (-1, "head", cfg["vocab"], cfg["d_model"], "bf16")]
     return shapes
 
@@ -71,11 +73,12 @@ class Engine:
 
     def __init__(self, cfg, pool_bytes, page_bytes=2 << 20, seed=None, flags=0, kv_blocks=4096, block_size=16,
                  max_tokens=2048, prefill_chunk=512, max_seqs=64, split_keys=512, remap_every=256,
-                 weights=None, gains=None, record_logits=False, max_context=None, remap_slices=1):
+                 weights=None, gains=None, record_logits=False, max_context=None, remap_slices=1,
+                 head_perm=True):
         import torch
         self.torch = torch
         self.cfg = dict(cfg)
-        self.shapes = model_shapes(cfg)
+        self.shapes = model_shapes(cfg, head_perm)
         self.bs = block_size
         self.kv_blocks = kv_blocks
         self.max_tokens = max_tokens

@@ -102,11 +102,13 @@ def ffn_block_shapes(d_model, d_ffn, dtype, layer=0):
             (layer, "down", d_model, d_ffn, dtype)]
 
 
-def decoder_layer_shapes(d_model, d_ffn, d_kv, dtype, layer=0):
-    return [(layer, "q", d_model, d_model, dtype),
-            (layer, "k", d_kv, d_model, dtype),
-            (layer, "v", d_kv, d_model, dtype),
-            (layer, "o", d_model, d_model, dtype)] + ffn_block_shapes(d_model, d_ffn, dtype, layer)
+def decoder_layer_shapes(d_model, d_ffn, d_kv, dtype, layer=0, head_dim=0):
+    """q/k/v/o carry ``head_dim`` as a sixth entry when it is given (> 0)."""
+    hd = (head_dim,) if head_dim else ()
+    return [(layer, "q", d_model, d_model, dtype) + hd,
+            (layer, "k", d_kv, d_model, dtype) + hd,
+            (layer, "v", d_kv, d_model, dtype) + hd,
+            (layer, "o", d_model, d_model, dtype) + hd] + ffn_block_shapes(d_model, d_ffn, dtype, layer)
 
 
 # FP32 FFN block, d_model 512, d_ffn 1024, 64 KiB pages over 16 MiB.

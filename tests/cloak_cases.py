@@ -54,8 +54,8 @@ def act_dtype(wdtype):
     return "f32" if wdtype == "f32" else "bf16"
 
 
-def decoder_shapes(d, ffn, dkv, dtype, layers=1, extra=()):
+def decoder_shapes(d, ffn, dkv, dtype, layers=1, extra=(), head_dim=0):
     shapes = []
     for l in range(layers):
-        shapes += synth.decoder_layer_shapes(d, ffn, dkv, dtype, layer=l)
+        shapes += synth.decoder_layer_shapes(d, ffn, dkv, dtype, layer=l, head_dim=head_dim)
     return shapes + list(extra)

@@ -21,6 +21,9 @@ pytestmark = pytest.mark.gpu
 
 TINY = dict(n_layers=2, d_model=256, n_heads=2, n_kv_heads=1, head_dim=128, d_ffn=512, vocab=1024,
             theta=500000.0, eps=1e-5)
+# two kv heads, so the kv-group permutation is not trivial
+GQA = dict(n_layers=2, d_model=512, n_heads=4, n_kv_heads=2, head_dim=128, d_ffn=512, vocab=1024,
+           theta=500000.0, eps=1e-5)
 
 
 @pytest.fixture(scope="module")
@@ -49,15 +52,18 @@ def make_engine(S, cfg, ws, **kw):
     return S.Engine(cfg, **args)
 
 
-def test_tiny_decoder_matches_fp64_oracle(S):
-    shapes, ws = tiny_weights(TINY)
+@pytest.mark.parametrize("cfg,head_perm", [(TINY, True), (TINY, False), (GQA, True)],
+                         ids=["tiny-heads", "tiny-noheads", "gqa-heads"])
+def test_tiny_decoder_matches_fp64_oracle(S, cfg, head_perm):
+    # with head_perm the attention runs on permuted heads in stored order
+    shapes, ws = tiny_weights(cfg)
     rng = np.random.Generator(np.random.PCG64(11))
-    prompt = rng.integers(0, TINY["vocab"], 40).astype(np.int32)
-    forced = rng.integers(0, TINY["vocab"], 8).astype(np.int32)
-    eng = make_engine(S, TINY, ws)
+    prompt = rng.integers(0, cfg["vocab"], 40).astype(np.int32)
+    forced = rng.integers(0, cfg["vocab"], 8).astype(np.int32)
+    eng = make_engine(S, cfg, ws, head_perm=head_perm)
     r = S.Request(0, prompt, len(forced), forced=forced)
     eng.run([r], realtime=False)
-    ref = oracle_decoder(TINY, shapes, ws).forward(np.concatenate([prompt, forced[:-1]]))
+    ref = oracle_decoder(cfg, shapes, ws).forward(np.concatenate([prompt, forced[:-1]]))
     worst = 0.0
     for i, lg in enumerate(r.logits):
         err = ON.normwise_err(lg, ref[len(prompt) - 1 + i])
