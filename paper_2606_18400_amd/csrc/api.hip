@@ -197,6 +197,22 @@ extern "C" int cloak_pool_init(const cloak_layout* L, void* d_pool, void* stream
   return CLOAK_OK;
 }
 
+extern "C" int cloak_pool_decoy(const cloak_layout* L, void* d_pool, uint64_t decoy_seed, void* stream) {
+  clear_error();
+  if (int rc = check_device_state(L, "cloak_pool_decoy")) return rc;
+  if (int rc = check_pool(L, d_pool, "cloak_pool_decoy")) return rc;
+  DecoyArgs a{};
+  a.pool = static_cast<uint8_t*>(d_pool);
+  a.phi = L->dev.phi;
+  a.V = L->V;
+  a.nfree = L->P - L->V;
+  a.decoy_seed = decoy_seed;
+  a.log2_page = L->log2_page;
+  a.dtype = decoy_dtype(L);
+  HIP_TRY(launch_decoy(a, static_cast<hipStream_t>(stream)), "cloak_pool_decoy");
+  return CLOAK_OK;
+}
+
 extern "C" int cloak_load(cloak_layout* L, void* d_pool, int32_t tensor, const void* h_src, const float* h_scales,
                           void* stream) {
   clear_error();

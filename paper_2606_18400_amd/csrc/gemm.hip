@@ -572,24 +572,6 @@ __global__ __launch_bounds__(256) void gather_cols_kernel(const uint16_t* __rest
 // multiples of 2^-9 (code = rint(|v| * 512), exact scaling); above, the 23
 // fraction bits are rounded to 3 and a carry out of the fraction moves the
 // code to the next binade by plain addition.
-__device__ inline uint32_t e4m3_code(float v) {
-  const uint32_t u = __float_as_uint(v);
-  const uint32_t sign = (u >> 24) & 0x80u;
-  const uint32_t au = u & 0x7fffffffu;
-  if (au > 0x7f800000u) return 0x7fu;
-  const float a = __uint_as_float(au);
-  if (a >= 448.0f) return sign | 0x7eu;
-  if (a < 0.015625f) return sign | uint32_t(rintf(a * 512.0f));
-  const int e = int(au >> 23) - 127;   // -6 .. 8
-  const uint32_t frac = au & 0x7fffffu;
-  uint32_t keep = frac >> 20;
-  const uint32_t rest = frac & 0xfffffu;
-  if (rest > 0x80000u || (rest == 0x80000u && (keep & 1u))) ++keep;
-  uint32_t code = uint32_t(e + 7) * 8u + keep;
-  if (code > 0x7eu) code = 0x7eu;
-  return sign | code;
-}
-
 __device__ inline float bf16_bits_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
 
 // One workgroup per token row: max |x| over the row, s = max / 448 (1 for a

@@ -191,6 +191,26 @@ hipError_t launch_rope_kv(const RopeArgs& a, int T, hipStream_t s);
 hipError_t launch_attention(const AttnArgs& a, hipStream_t s);
 hipError_t launch_argmax(const uint16_t* logits, int64_t rows, int64_t V, int32_t* out, hipStream_t s);
 
+// OCP E4M3FN code of a binary32 value: nearest, ties to the even code,
+// saturating at +-448, NaN -> 0x7F.
+__device__ inline uint32_t e4m3_code(float v) {
+  const uint32_t u = __float_as_uint(v);
+  const uint32_t sign = (u >> 24) & 0x80u;
+  const uint32_t au = u & 0x7fffffffu;
+  if (au > 0x7f800000u) return 0x7fu;
+  const float a = __uint_as_float(au);
+  if (a >= 448.0f) return sign | 0x7eu;
+  if (a < 0.015625f) return sign | uint32_t(rintf(a * 512.0f));
+  const int e = int(au >> 23) - 127;   // -6 .. 8
+  const uint32_t frac = au & 0x7fffffu;
+  uint32_t keep = frac >> 20;
+  const uint32_t rest = frac & 0xfffffu;
+  if (rest > 0x80000u || (rest == 0x80000u && (keep & 1u))) ++keep;
+  uint32_t code = uint32_t(e + 7) * 8u + keep;
+  if (code > 0x7eu) code = 0x7eu;
+  return sign | code;
+}
+
 struct SwapArgs {
   uint8_t* pool;
   const int32_t* pairs;     // [2*npairs] physical page pairs
@@ -199,5 +219,16 @@ struct SwapArgs {
   int32_t pad;
 };
 hipError_t launch_swap(const SwapArgs& a, hipStream_t s);
+
+// Decoy contents of the free virtual pages [V, V + nfree) (definition in include/cloak.h).
+struct DecoyArgs {
+  uint8_t* pool;
+  const int32_t* phi;
+  int64_t V, nfree;
+  uint64_t decoy_seed;
+  int32_t log2_page;
+  int32_t dtype;            // CLOAK_F32 / CLOAK_BF16 / CLOAK_FP8_E4M3
+};
+hipError_t launch_decoy(const DecoyArgs& a, hipStream_t s);
 
 }  // namespace cloak
