@@ -22,8 +22,18 @@ Readings taken here (listed with the other readings in the design notes):
 * Permutation: Fisher-Yates in Durstenfeld's in-place form, walking ``i`` from
   ``n-1`` down to ``1`` and swapping ``a[i]`` with ``a[bounded(i+1)]``.
 
+Cryptographic alternative (layouts built with the CSPRNG flag): the same
+sub-streams, but word ``j`` of sub-stream (seed, tag, idx) is bytes
+``8*(j % 4) .. 8*(j % 4) + 7`` (little-endian) of
+``SHA-256(seed_le64 || tag_le32 || idx_le32 || (j // 4)_le64)`` -- SHA-256
+(FIPS 180-4) in counter mode, so that no output reveals the seed or another
+output.  Bounded draws and Fisher-Yates are unchanged.
+
 Pure Python integers, no vectorisation: this is the definition written out.
 """
+
+import hashlib
+import struct
 
 MASK64 = (1 << 64) - 1
 GOLDEN_GAMMA = 0x9E3779B97F4A7C15  # 2**64 / golden ratio, odd
@@ -60,6 +70,28 @@ def substream(seed: int, tag: int, idx: int) -> SplitMix64:
     if not (0 <= idx < (1 << 32)):
         raise ValueError("sub-stream index must fit in 32 bits")
     return SplitMix64(mix64((seed & MASK64) ^ mix64((tag << 32) | idx)))
+
+
+class Sha256Ctr:
+    """Counter-mode SHA-256 word stream for (seed, tag, idx)."""
+
+    def __init__(self, seed: int, tag: int, idx: int):
+        self.prefix = struct.pack("<QII", seed & MASK64, tag, idx)
+        self.j = 0
+        self.block = b""
+
+    def next_u64(self) -> int:
+        if self.j % 4 == 0:
+            self.block = hashlib.sha256(self.prefix + struct.pack("<Q", self.j // 4)).digest()
+        w = int.from_bytes(self.block[8 * (self.j % 4):8 * (self.j % 4) + 8], "little")
+        self.j += 1
+        return w
+
+
+def substream_csprng(seed: int, tag: int, idx: int) -> Sha256Ctr:
+    if not (0 <= idx < (1 << 32)):
+        raise ValueError("sub-stream index must fit in 32 bits")
+    return Sha256Ctr(seed, tag, idx)
 
 
 def bounded(rng, n: int) -> int:

@@ -18,9 +18,11 @@ import numpy as np
 from . import prng
 
 
-def matching(remap_seed, P):
-    """tau as an array: tau[p] is the page that p swaps with (an involution)."""
-    s = prng.fisher_yates(P, prng.substream(remap_seed, prng.TAG_REMAP, 0))
+def matching(remap_seed, P, csprng=False):
+    """tau as an array: tau[p] is the page that p swaps with (an involution).
+    ``csprng`` draws the words from counter-mode SHA-256 (layouts built so)."""
+    sub = prng.substream_csprng if csprng else prng.substream
+    s = prng.fisher_yates(P, sub(remap_seed, prng.TAG_REMAP, 0))
     tau = list(range(P))
     for i in range(P // 2):
         a, b = s[2 * i], s[2 * i + 1]
@@ -28,10 +30,10 @@ def matching(remap_seed, P):
     return tau
 
 
-def remap(pool, phi, remap_seed, page_bytes):
+def remap(pool, phi, remap_seed, page_bytes, csprng=False):
     """Return (pool', phi') after one remap; the inputs are not modified."""
     P = len(phi)
-    tau = matching(remap_seed, P)
+    tau = matching(remap_seed, P, csprng)
     B = page_bytes
     out = np.empty_like(pool)
     for p in range(P):
@@ -51,13 +53,13 @@ def remap(pool, phi, remap_seed, page_bytes):
 # transpositions, so the slices commute and together equal tau).
 # ----------------------------------------------------------------------------
 
-def pairs(remap_seed, P):
+def pairs(remap_seed, P, csprng=False):
     """Pairs (p, tau[p]) with p < tau[p], ascending in p."""
-    tau = matching(remap_seed, P)
+    tau = matching(remap_seed, P, csprng)
     return [(p, tau[p]) for p in range(P) if tau[p] > p]
 
 
-def remap_in_slices(pool, phi, remap_seed, page_bytes, slice_pairs):
+def remap_in_slices(pool, phi, remap_seed, page_bytes, slice_pairs, csprng=False):
     """Yield (pool_i, phi_i) after each slice of at most slice_pairs pairs."""
     if slice_pairs < 1:
         raise ValueError("slice_pairs must be positive")
@@ -65,7 +67,7 @@ def remap_in_slices(pool, phi, remap_seed, page_bytes, slice_pairs):
     pool = pool.copy()
     phi = list(phi)
     where = {phi[v]: v for v in range(len(phi))}   # physical page -> virtual page
-    todo = pairs(remap_seed, len(phi))
+    todo = pairs(remap_seed, len(phi), csprng)
     for i0 in range(0, len(todo), slice_pairs):
         for a, b in todo[i0:i0 + slice_pairs]:
             pa = pool[a * B:(a + 1) * B].copy()

@@ -35,6 +35,7 @@ DTYPES = {"f32": 0, "bf16": 1, "fp8": 2}
 KINDS = {"q": 0, "k": 1, "v": 2, "o": 3, "gate": 4, "up": 5, "down": 6, "embed": 7, "head": 8}
 CLOAK_IDENTITY = 1
 CLOAK_NATIVE = 2
+CLOAK_CSPRNG = 4
 QUERY = dict(P=1, V=2, T=3, PAGE_BYTES=4, PHI=5, SIGMA=6, PI=7, VBASE=8, NPAGES=9, CONTIGUITY=10,
              UPLOAD_ORDER=11, REMAPS=12, TENSOR=13, DFFN=14, REMAP_PENDING=15, ROW_PERM=16, COL_PERM=17,
              SHAPE=18)

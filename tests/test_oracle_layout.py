@@ -187,3 +187,14 @@ def test_hidden_perm_uses_its_own_substream():
         assert lay.pi[l] == prng.fisher_yates(24, prng.substream(77, 2, l))
     assert lay.phi == prng.fisher_yates(512, prng.substream(77, 3, 0))
     assert lay.sigma == prng.fisher_yates(len(shapes), prng.substream(77, 1, 0))
+
+
+def test_csprng_layout_is_valid_and_differs():
+    shapes = tiny_shapes()
+    a = L.build_layout(5, shapes, 64, 64 * 256, csprng=True)
+    b = L.build_layout(5, shapes, 64, 64 * 256)
+    assert sorted(a.phi) == list(range(a.P)) and sorted(a.sigma) == list(range(a.T))
+    assert all(sorted(p) == list(range(24)) for p in a.pi.values())
+    assert a.phi != b.phi and a.pi != b.pi
+    assert a.phi == prng.fisher_yates(a.P, prng.substream_csprng(5, 3, 0))
+    assert L.upload_order(a, 0) == prng.fisher_yates(a.npages[0], prng.substream_csprng(5, 4, 0))

@@ -112,3 +112,38 @@ def test_fisher_yates_uniform_chi2():
 def test_fisher_yates_is_permutation(n):
     p = prng.fisher_yates(n, prng.substream(99, 2, 3))
     assert sorted(p) == list(range(n))
+
+
+# ---------------------------------------------------------------- counter-mode SHA-256 streams
+
+def test_sha256_primitive_known_answers():
+    # FIPS 180-4 example messages: the empty string and "abc"
+    import hashlib
+    assert hashlib.sha256(b"").hexdigest() == \
+        "e3b0c44298fc1c149afbf4c8996fb92427ae41e4649b934ca495991b7852b855"
+    assert hashlib.sha256(b"abc").hexdigest() == \
+        "ba7816bf8f01cfea414140de5dae2223b00361a396177a9cb410ff61f20015ad"
+
+
+def test_csprng_words_follow_the_counter_construction():
+    import hashlib
+    import struct
+    g = prng.substream_csprng(0x0123456789ABCDEF, 3, 7)
+    words = [g.next_u64() for _ in range(9)]
+    for j, w in enumerate(words):
+        msg = (0x0123456789ABCDEF).to_bytes(8, "little") + (3).to_bytes(4, "little") + \
+            (7).to_bytes(4, "little") + (j // 4).to_bytes(8, "little")
+        block = hashlib.sha256(msg).digest()
+        assert w == struct.unpack_from("<Q", block, 8 * (j % 4))[0]
+    # distinct (tag, idx) give unrelated streams; the seed is masked to 64 bits
+    assert words[0] != prng.substream_csprng(0x0123456789ABCDEF, 3, 8).next_u64()
+    assert prng.substream_csprng(-1, 1, 0).next_u64() == prng.substream_csprng((1 << 64) - 1, 1, 0).next_u64()
+
+
+def test_csprng_permutations_are_uniform_on_small_n():
+    # all 24 permutations of 4 items, chi-square over 4800 sub-streams
+    from collections import Counter
+    cnt = Counter(tuple(prng.fisher_yates(4, prng.substream_csprng(s, 2, 0))) for s in range(4800))
+    assert len(cnt) == 24
+    chi2 = sum((c - 200) ** 2 / 200 for c in cnt.values())
+    assert chi2 < 49.7      # 23 degrees of freedom, p = 0.001
