@@ -321,6 +321,37 @@ def virtual_to_physical(layout, t, byte_offset):
     return layout.phi[v] * B + byte_offset % B
 
 
+# ----------------------------------------------------------------------------
+# Masked device page map.  The paper's page tables are the GPU's own; here the
+# map is a table in device memory that every translating kernel reads, so a
+# hardened layout stores it masked.  Reading: the k-th upload of the map uses
+# key_k = the k-th nonzero word of the counter-mode SHA-256 stream (seed,
+# tag 8, idx 0) and stores entry v as phi[v] XOR m(key_k, v), with m the low
+# 32 bits of the SplitMix64 finaliser of (key_k XOR v); the key travels in the
+# kernels' arguments only.
+# ----------------------------------------------------------------------------
+
+TAG_MAP_KEY = 8
+
+
+def map_keys(seed):
+    """Keys of successive uploads of the device map (zero words skipped)."""
+    g = prng.substream_csprng(seed, TAG_MAP_KEY, 0)
+    while True:
+        k = g.next_u64()
+        if k:
+            yield k
+
+
+def map_mask(key, v):
+    return prng.mix64(key ^ v) & 0xFFFFFFFF
+
+
+def masked_map(phi, key):
+    """Device table entries (as uint32) for page map phi under key."""
+    return [(phi[v] ^ map_mask(key, v)) & 0xFFFFFFFF for v in range(len(phi))]
+
+
 def contiguity(layout):
     """Share of in-tensor page successions that stay physically adjacent.
 

@@ -198,3 +198,26 @@ def test_csprng_layout_is_valid_and_differs():
     assert a.phi != b.phi and a.pi != b.pi
     assert a.phi == prng.fisher_yates(a.P, prng.substream_csprng(5, 3, 0))
     assert L.upload_order(a, 0) == prng.fisher_yates(a.npages[0], prng.substream_csprng(5, 4, 0))
+
+
+def test_masked_map_hides_phi_and_unmasks_exactly():
+    import hashlib
+    import struct
+    lay = L.build_layout(31, tiny_shapes(), 64, 64 * 4096)
+    keys = L.map_keys(31)
+    k0, k1 = next(keys), next(keys)
+    # keys: words of SHA-256(seed || 8 || 0 || block), as the stream defines
+    d = hashlib.sha256(struct.pack("<QIIQ", 31, 8, 0, 0)).digest()
+    assert (k0, k1) == struct.unpack_from("<QQ", d, 0)
+    t0 = L.masked_map(lay.phi, k0)
+    # unmasking with the key restores phi; another key does not
+    assert [t0[v] ^ L.map_mask(k0, v) for v in range(lay.P)] == lay.phi
+    assert [t0[v] ^ L.map_mask(k1, v) for v in range(lay.P)] != lay.phi
+    # entries spread over all 32 bits (phi < 4096 occupies 12): no high bit is constant
+    t = np.array(t0, dtype=np.uint64)
+    for bit in range(12, 32):
+        frac = np.mean((t >> np.uint64(bit)) & np.uint64(1))
+        assert 0.45 < frac < 0.55, bit
+    # successive uploads differ entry by entry almost everywhere
+    t1 = L.masked_map(lay.phi, k1)
+    assert np.mean(np.array(t0) != np.array(t1)) > 0.99
