@@ -326,9 +326,10 @@ def virtual_to_physical(layout, t, byte_offset):
 # map is a table in device memory that every translating kernel reads, so a
 # hardened layout stores it masked.  Reading: the k-th upload of the map uses
 # key_k = the k-th nonzero word of the counter-mode SHA-256 stream (seed,
-# tag 8, idx 0) and stores entry v as phi[v] XOR m(key_k, v), with m the low
-# 32 bits of the SplitMix64 finaliser of (key_k XOR v); the key travels in the
-# kernels' arguments only.
+# tag 8, idx 0) and stores entry v as phi[v] XOR m(key_k, v); the key travels
+# in the kernels' arguments only.  m: with k0 the low and k1 the high 32 bits
+# of the key (k1 made odd), h = v XOR k0, h = (h XOR h>>16) * k1,
+# h = (h XOR h>>15) * 0x2C1B3C6D, m = (h XOR h>>16) XOR k0, all mod 2**32.
 # ----------------------------------------------------------------------------
 
 TAG_MAP_KEY = 8
@@ -344,7 +345,12 @@ def map_keys(seed):
 
 
 def map_mask(key, v):
-    return prng.mix64(key ^ v) & 0xFFFFFFFF
+    M = 0xFFFFFFFF
+    k0, k1 = key & M, ((key >> 32) & M) | 1
+    h = (v & M) ^ k0
+    h = ((h ^ (h >> 16)) * k1) & M
+    h = ((h ^ (h >> 15)) * 0x2C1B3C6D) & M
+    return (h ^ (h >> 16)) ^ k0
 
 
 def masked_map(phi, key):

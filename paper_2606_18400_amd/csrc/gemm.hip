@@ -79,13 +79,14 @@ struct RowRef {
 };
 
 template <bool TR>
-__device__ inline const uint8_t* row_addr(const int32_t* phi, int log2_page, RowRef& r, int64_t koff) {
+__device__ inline const uint8_t* row_addr(const int32_t* phi, uint64_t key, int log2_page, RowRef& r,
+                                          int64_t koff) {
   const int64_t o = r.rowoff + koff;
   const int64_t vp = o >> log2_page;
   if (vp != r.cvp) {
     r.cvp = vp;
     const int64_t v = r.vbase + vp;
-    r.cbase = (TR ? int64_t(phi[v]) : v) << log2_page;
+    r.cbase = (TR ? int64_t(uint32_t(phi[v]) ^ phi_mask(key, v)) : v) << log2_page;
   }
   return r.pool + r.cbase + (o & ((int64_t(1) << log2_page) - 1));
 }
@@ -139,11 +140,12 @@ struct WTile {
     }
   }
   template <bool TR>
-  __device__ inline void load(const int32_t* phi, int log2_page, int kb) {
+  __device__ inline void load(const int32_t* phi, uint64_t key, int log2_page, int kb) {
     const int64_t koff = int64_t(kb) * STEP_BYTES;
 #pragma unroll
     for (int i = 0; i < N; ++i)
-      g[i] = r[i].ok ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(row_addr<TR>(phi, log2_page, r[i], koff)))
+      g[i] = r[i].ok ? __builtin_nontemporal_load(
+                           reinterpret_cast<const u32x4*>(row_addr<TR>(phi, key, log2_page, r[i], koff)))
                      : u32x4{0u, 0u, 0u, 0u};
   }
   __device__ inline void store(uint8_t* tile) const {
@@ -319,7 +321,7 @@ __global__ __launch_bounds__(NTHREADS, 1) void gemm_kernel(const GemmArgs a) {
 #pragma unroll
     for (int i = 0; i < LOADS; ++i)
       gx[i] = xok[i] ? *reinterpret_cast<const u32x4*>(xrow[i] + int64_t(kb) * ROWB) : u32x4{0u, 0u, 0u, 0u};
-    wt.template load<TR>(a.phi, a.log2_page, kb);
+    wt.template load<TR>(a.phi, a.phi_key, a.log2_page, kb);
   };
   auto swrite = [&](int buf) {
 #pragma unroll
@@ -517,7 +519,7 @@ __global__ __launch_bounds__(64 * WAVES, 1) void gemm_dma_kernel(const GemmArgs 
       for (int j = 0; j < DLOADS; ++j) {
         const int r0 = DRPL * (DLOADS * wave + j);
         const uint8_t* xsrc = xptr[j] + int64_t(ks) * DROWB;
-        const uint8_t* wsrc = row_addr<TR>(a.phi, a.log2_page, wr[j], int64_t(ks) * DROWB);
+        const uint8_t* wsrc = row_addr<TR>(a.phi, a.phi_key, a.log2_page, wr[j], int64_t(ks) * DROWB);
         __builtin_amdgcn_global_load_lds(xsrc, base + r0 * DROWB, 16, 0, 0);
         __builtin_amdgcn_global_load_lds(wsrc, base + DTILE + r0 * DROWB, 16, 0, 0);
       }
@@ -698,7 +700,7 @@ __global__ __launch_bounds__(STHREADS) void skinny_kernel(const SkinnyArgs a) {
 #pragma unroll
     for (int i = 0; i < XL; ++i)
       gx[i] = xok[i] ? *reinterpret_cast<const u32x4*>(xrow[i] + kb * SBK) : u32x4{0u, 0u, 0u, 0u};
-    wt.template load<TR>(a.phi, a.log2_page, kb);
+    wt.template load<TR>(a.phi, a.phi_key, a.log2_page, kb);
   };
   auto swrite = [&](int buf) {
 #pragma unroll

@@ -49,8 +49,11 @@ __device__ inline int64_t uniform64(int64_t v) {
   return int64_t((uint64_t(hi) << 32) | lo);
 }
 
-__device__ inline int64_t page_of(const int32_t* phi, int64_t vpage) {
-  return int64_t(((scalar_i32_ptr)phi)[uniform64(vpage)]);
+template <bool MASKED>
+__device__ inline int64_t page_of(const int32_t* phi, uint64_t key, int64_t vpage) {
+  const int64_t v = uniform64(vpage);
+  const uint32_t e = uint32_t(((scalar_i32_ptr)phi)[v]);
+  return int64_t(MASKED ? e ^ phi_mask(key, v) : e);
 }
 
 constexpr int kChunkBytes = 1024;
@@ -140,7 +143,8 @@ struct ChunkLoc {
   int64_t p0, p1, inpage;
 };
 
-template <bool TR>
+// TR: 0 untranslated twin, 1 plain page map, 2 masked page map
+template <int TR>
 __device__ inline ChunkLoc locate(const GemvArgs& a, const SegView& v, int n, int c) {
   const int64_t o = int64_t(n) * a.row_bytes + int64_t(c) * kChunkBytes;
   const int64_t page_bytes = int64_t(1) << a.log2_page;
@@ -151,8 +155,8 @@ __device__ inline ChunkLoc locate(const GemvArgs& a, const SegView& v, int n, in
   // the second lookup is unconditional (index clamped to the tensor's last
   // page) so that both scalar loads of every row can be in flight together
   const int64_t vnext = vp + 1 < v.npages ? vpage + 1 : vpage;
-  L.p0 = TR ? page_of(a.phi, vpage) : vpage;
-  L.p1 = TR ? page_of(a.phi, vnext) : vnext;
+  L.p0 = TR ? page_of<TR == 2>(a.phi, a.phi_key, vpage) : vpage;
+  L.p1 = TR ? page_of<TR == 2>(a.phi, a.phi_key, vnext) : vnext;
   return L;
 }
 
@@ -227,14 +231,14 @@ __device__ inline void lane_reduce(float (&v)[V], int lane) {
 template <int N> struct Log2 { static constexpr int value = 1 + Log2<N / 2>::value; };
 template <> struct Log2<1> { static constexpr int value = 0; };
 
-template <int WT, int R, int CPW, bool TR, int EPI>
+template <int WT, int R, int CPW, int TR, int EPI>
 struct GroupLoads {
   u32x4 w[CPW][R];
 };
 
 // Issue every weight load of group `grp` for this wave (page lookups first,
 // as one batch of scalar loads, then R*CPW independent 16 B loads per lane).
-template <int WT, int R, int CPW, bool TR, int EPI>
+template <int WT, int R, int CPW, int TR, int EPI>
 __device__ inline void issue_group(const GemvArgs& a, int grp, int wave, int nwaves, int lane,
                                    GroupLoads<WT, R, CPW, TR, EPI>& L) {
   constexpr int EPL = WTraits<WT>::EPL;
@@ -263,7 +267,7 @@ __device__ inline void issue_group(const GemvArgs& a, int grp, int wave, int nwa
 }
 
 // MAXW: most waves per workgroup (8; 16 for the wide single-token variant)
-template <int WT, int MT, int R, int CPW, bool TR, int EPI, int MAXW = kMaxWaves>
+template <int WT, int MT, int R, int CPW, int TR, int EPI, int MAXW = kMaxWaves>
 __global__ __launch_bounds__(MAXW * 64) void gemv_kernel(const GemvArgs a) {
   constexpr int XW = WTraits<WT>::XW;
   constexpr int V = R * MT;
@@ -385,7 +389,7 @@ bool use_wide(int nchunks, int mtile) {
   return mtile == 1 && nchunks > 2 * kMaxWaves && nchunks <= kWideCpw * kWideWaves;
 }
 
-template <int WT, int CPW, bool TR, int EPI>
+template <int WT, int CPW, int TR, int EPI>
 KernelFn pick_mt(int mt) {
   constexpr int kMax = WT == kFP8 ? (CPW <= 1 ? 8 : CPW == 2 ? 4 : CPW == 4 ? 2 : 1)
                                   : (CPW <= 2 ? 8 : CPW == 4 ? 4 : 2);
@@ -396,7 +400,7 @@ KernelFn pick_mt(int mt) {
   return gemv_kernel<WT, (kMax < 8 ? 1 : 8), R, CPW, TR, EPI>;
 }
 
-template <int WT, bool TR, int EPI>
+template <int WT, int TR, int EPI>
 KernelFn pick_cpw(int cpw, int mt) {
   switch (cpw) {
     case 1: return pick_mt<WT, 1, TR, EPI>(mt);
@@ -407,11 +411,12 @@ KernelFn pick_cpw(int cpw, int mt) {
 }
 
 template <int WT, int EPI>
-KernelFn pick_tr(bool tr, int cpw, int mt) {
-  return tr ? pick_cpw<WT, true, EPI>(cpw, mt) : pick_cpw<WT, false, EPI>(cpw, mt);
+KernelFn pick_tr(int tr, int cpw, int mt) {
+  return tr == 2 ? pick_cpw<WT, 2, EPI>(cpw, mt) : tr == 1 ? pick_cpw<WT, 1, EPI>(cpw, mt)
+                                                 : pick_cpw<WT, 0, EPI>(cpw, mt);
 }
 
-KernelFn pick(int wt, bool tr, int cpw, int mt, int epi) {
+KernelFn pick(int wt, int tr, int cpw, int mt, int epi) {
   if (epi == kSwiGLU) {
     if (wt == kF32) return pick_tr<kF32, kSwiGLU>(tr, cpw, mt);
     if (wt == kBF16) return pick_tr<kBF16, kSwiGLU>(tr, cpw, mt);
@@ -423,12 +428,13 @@ KernelFn pick(int wt, bool tr, int cpw, int mt, int epi) {
 }
 
 template <int WT, int EPI>
-KernelFn pick_wide_tr(bool tr) {
-  return tr ? gemv_kernel<WT, 1, kWideRows, kWideCpw, true, EPI, kWideWaves>
-            : gemv_kernel<WT, 1, kWideRows, kWideCpw, false, EPI, kWideWaves>;
+KernelFn pick_wide_tr(int tr) {
+  return tr == 2   ? gemv_kernel<WT, 1, kWideRows, kWideCpw, 2, EPI, kWideWaves>
+         : tr == 1 ? gemv_kernel<WT, 1, kWideRows, kWideCpw, 1, EPI, kWideWaves>
+                   : gemv_kernel<WT, 1, kWideRows, kWideCpw, 0, EPI, kWideWaves>;
 }
 
-KernelFn pick_wide(int wt, bool tr, int epi) {
+KernelFn pick_wide(int wt, int tr, int epi) {
   if (epi == kSwiGLU) {
     if (wt == kF32) return pick_wide_tr<kF32, kSwiGLU>(tr);
     if (wt == kBF16) return pick_wide_tr<kBF16, kSwiGLU>(tr);
@@ -470,6 +476,8 @@ int gemv_max_tokens(int wtype, int nchunks) { return max_mtile(wtype, gemv_cpw(n
 int gemv_rows(int nchunks, int mtile) { return use_wide(nchunks, mtile) ? kWideRows : rows_for(gemv_cpw(nchunks)); }
 
 hipError_t launch_gemv(const GemvArgs& a, int wtype, int mtile, bool translate, hipStream_t s) {
+  // masked maps get their own instantiation, so plain maps pay nothing for them
+  const int tr = translate ? (a.phi_key ? 2 : 1) : 0;
   if (a.groups <= 0) return hipSuccess;
   const bool wide = use_wide(a.nchunks, mtile);
   int cpw = wide ? kWideCpw : gemv_cpw(a.nchunks);
@@ -483,7 +491,7 @@ hipError_t launch_gemv(const GemvArgs& a, int wtype, int mtile, bool translate, 
   if (cpw > 8 || mtile > max_mtile(wtype, cpw) || a.mcount > mtile) return hipErrorInvalidValue;
   const int waves = (a.nchunks + cpw - 1) / cpw;
   const int threads = waves * 64;
-  KernelFn fn = wide ? pick_wide(wtype, translate, a.mode) : pick(wtype, translate, cpw, mtile, a.mode);
+  KernelFn fn = wide ? pick_wide(wtype, tr, a.mode) : pick(wtype, tr, cpw, mtile, a.mode);
   int blocks = resident_blocks(fn, threads);
   if (blocks <= 0) blocks = a.groups;
   if (blocks > a.groups) blocks = a.groups;

@@ -228,6 +228,7 @@ extern "C" int cloak_model_step(cloak_model* m, const cloak_step* s, void* d_ws,
     EmbedArgs e{};
     e.pool = static_cast<const uint8_t*>(L->kernel_pool(m->pool));
     e.phi = L->dev.phi;
+    e.phi_key = L->dev.phi_key;
     e.log2_page = L->log2_page;
     e.translate = L->kernel_translate() ? 1 : 0;
     e.vbase = te.vbase;
@@ -250,7 +251,7 @@ extern "C" int cloak_model_step(cloak_model* m, const cloak_step* s, void* d_ws,
     na.D = int32_t(D);
     na.eps = c.norm_eps;
     HIP_TRY(launch_rmsnorm(na, int(T), st), "cloak_model_step(norm)");
-    if (int rc = linear_stored(L, m->pool, t, 3, h, T, qkv, scratch, sb, stream)) return rc;
+    if (int rc = cloak_linear_stored(L, m->pool, t, 3, h, T, qkv, scratch, sb, stream)) return rc;
     uint16_t* kc = m->kv + int64_t(2 * l) * layer_kv;
     uint16_t* vc = kc + layer_kv;
     RopeArgs ra{};
@@ -293,7 +294,7 @@ extern "C" int cloak_model_step(cloak_model* m, const cloak_step* s, void* d_ws,
     aa.out = attn;
     aa.ldo = D;
     HIP_TRY(launch_attention(aa, st), "cloak_model_step(attention)");
-    if (int rc = linear_stored(L, m->pool, t + 3, 1, attn, T, o, scratch, sb, stream)) return rc;
+    if (int rc = cloak_linear_stored(L, m->pool, t + 3, 1, attn, T, o, scratch, sb, stream)) return rc;
     NormArgs nb = na;
     nb.add = o;
     nb.r_out = r;

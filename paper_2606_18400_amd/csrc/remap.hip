@@ -88,7 +88,8 @@ __global__ __launch_bounds__(kThreads) void decoy_kernel(const DecoyArgs a) {
   const int64_t v = a.V + i;
   const int64_t byte0 = (int64_t(blockIdx.x) % slices_per_page) * slice;
   const uint64_t s0 = mix64(a.decoy_seed ^ mix64((uint64_t(7) << 32) | uint64_t(uint32_t(v))));
-  u32x4* dst = reinterpret_cast<u32x4*>(a.pool + (int64_t(a.phi[v]) << a.log2_page) + byte0);
+  const int64_t phys = int64_t(uint32_t(a.phi[v]) ^ phi_mask(a.phi_key, v));
+  u32x4* dst = reinterpret_cast<u32x4*>(a.pool + (phys << a.log2_page) + byte0);
   const int nvec = int(slice / 16);
   for (int u = 0; u < kVecPerThread; ++u) {
     const int q = threadIdx.x + u * kThreads;

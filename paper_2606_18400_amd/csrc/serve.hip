@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void embed_kernel(const EmbedArgs a) {
   for (int p = threadIdx.x; p < a.row_bytes / 16; p += blockDim.x) {
     const int64_t o = int64_t(id) * a.row_bytes + int64_t(p) * 16;
     const int64_t v = a.vbase + (o >> a.log2_page);
-    const int64_t phys = a.translate ? int64_t(a.phi[v]) : v;
+    const int64_t phys = a.translate ? int64_t(uint32_t(a.phi[v]) ^ phi_mask(a.phi_key, v)) : v;
     const u32x4 w = *reinterpret_cast<const u32x4*>(a.pool + (phys << a.log2_page) + (o & page_mask));
     *reinterpret_cast<u32x4*>(out + int64_t(p) * 16) = w;
   }
