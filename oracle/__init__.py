@@ -10,6 +10,7 @@ cloaked path computes (CloakLM, arXiv 2606.18400, Sections 4.2 and 5):
                   virtual->physical page map, pack / unpack, contiguity.
 * ``remap``    -- the in-place re-randomisation of page placement.
 * ``decoy``    -- weight-like contents of the pages that hold no weights.
+* ``moe``      -- the router-weighted mixture of cloaked expert FFNs.
 * ``numerics`` -- exact decoding of stored weights and the FP64 linear /
                   SwiGLU-FFN reference values.
 * ``model``    -- an FP64 decoder used to check the serving loop end to end.
@@ -27,4 +28,4 @@ than itself (published test vectors, closed forms, brute force on tiny inputs,
 invariants).  No function here is "parity unpinned".
 """
 
-from . import prng, layout, remap, numerics, decoy  # noqa: F401
+from . import prng, layout, remap, numerics, decoy, moe  # noqa: F401
