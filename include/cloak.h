@@ -305,6 +305,25 @@ int cloak_swiglu(const cloak_layout* layout, const void* d_pool, int32_t layer, 
 int cloak_down(const cloak_layout* layout, const void* d_pool, int32_t layer, const void* d_h,
                int64_t M, void* d_y, void* d_ws, uint64_t ws_bytes, void* stream);
 
+/* Mixture-of-experts layer over cloaked experts (the paper serves a Qwen 3
+ * MoE model, Section 5; experts are ordinary cloaked tensors: each expert e is
+ * the FFN group of layer first_layer + e, with its own hidden permutation and
+ * its own place in the tensor order).  For token m:
+ *   y[m] = sum_j d_weights[m][j] * FFN_{d_ids[m][j]}(x[m]),
+ * FFN_e = down_e(silu(gate_e x) * up_e x); slots whose id lies outside
+ * [0, n_experts) are skipped.  x, y: [M][d_model] bf16; d_ids int32 and
+ * d_weights f32 [M][top_k] on the device (routing is the caller's).  Experts
+ * are BF16 or FP8 (per-row scales) with one d_model and d_ffn.  The hidden
+ * activations are rounded to bf16, the weighted expert outputs kept in f32 and
+ * added per token in slot order.  M * top_k <= 4096.  Workspace:
+ * cloak_moe_ws_bytes.  Errors: EINVAL (experts missing or inconsistent, sizes,
+ * workspace). */
+uint64_t cloak_moe_ws_bytes(const cloak_layout* layout, int32_t first_layer, int32_t n_experts, int32_t top_k,
+                            int64_t M);
+int cloak_moe(const cloak_layout* layout, const void* d_pool, int32_t first_layer, int32_t n_experts,
+              int32_t top_k, const void* d_x, int64_t M, const int32_t* d_ids, const float* d_weights,
+              void* d_y, void* d_ws, uint64_t ws_bytes, void* stream);
+
 /* Per-token FP8 quantisation of activations, as the FP8 x FP8 MFMA path
  * applies it to x before a projection with FP8 weights and more than 256
  * tokens (the paper names FP8 weights with per-channel scales; this

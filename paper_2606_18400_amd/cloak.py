@@ -95,6 +95,8 @@ _SIGS = {
     "cloak_swiglu": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _u64, _vp], _i32),
     "cloak_down": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _u64, _vp], _i32),
     "cloak_quantize_fp8": ([_vp, _i64, _i64, _i64, _vp, _vp, _vp], _i32),
+    "cloak_moe_ws_bytes": ([_vp, _i32, _i32, _i32, _i64], _u64),
+    "cloak_moe": ([_vp, _vp, _i32, _i32, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _u64, _vp], _i32),
     "cloak_remap": ([_vp, _vp, _u64, _vp], _i32),
     "cloak_remap_host": ([_vp, _vp, _u64, _u64], _i32),
     "cloak_remap_begin": ([_vp, _u64], _i32),
@@ -295,6 +297,18 @@ def cloak_down(layout, pool, layer, h, M, y, ws=None, ws_bytes=0, stream=None):
 
 def cloak_remap(layout, pool, remap_seed, stream=None):
     _check(_lib.cloak_remap(layout, _ptr(pool), remap_seed & ((1 << 64) - 1), _stream(stream)), "cloak_remap")
+
+
+def cloak_moe_ws_bytes(layout, first_layer, n_experts, top_k, M):
+    v = _lib.cloak_moe_ws_bytes(layout, first_layer, n_experts, top_k, M)
+    if v == (1 << 64) - 1:
+        raise CloakError(CLOAK_EINVAL, "cloak_moe_ws_bytes", cloak_last_error() or "bad arguments")
+    return v
+
+
+def cloak_moe(layout, pool, first_layer, n_experts, top_k, x, M, ids, weights, y, ws, ws_bytes, stream=None):
+    _check(_lib.cloak_moe(layout, _ptr(pool), first_layer, n_experts, top_k, _ptr(x), M, _ptr(ids), _ptr(weights),
+                          _ptr(y), _ptr(ws), ws_bytes, _stream(stream)), "cloak_moe")
 
 
 def cloak_quantize_fp8(x, M, q, s, stream=None):

@@ -175,6 +175,23 @@ extern "C" int cloak_layout_to_device(cloak_layout* L, void* stream) {
   d.stage_event = ev;
   std::vector<int32_t> perms(size_t(L->n_perm > 0 ? L->n_perm : 1), 0);
   for (const auto& pt : L->perms) std::memcpy(perms.data() + pt.dev_off, pt.p.data(), pt.p.size() * 4);
+  // one MoE expert record per FFN group, ascending layer id
+  std::vector<MoeExpert> ex(L->ffn.size() > 0 ? L->ffn.size() : 1);
+  for (size_t i = 0; i < L->ffn_by_layer.size(); ++i) {
+    const FfnPerm& f = L->ffn[size_t(L->ffn_by_layer[i])];
+    MoeExpert r{};
+    const int32_t ts[3] = {f.gate, f.up, f.down};
+    r.ok = f.gate >= 0 && f.up >= 0 && f.down >= 0;
+    for (int k = 0; k < 3; ++k) {
+      r.vbase[k] = ts[k] >= 0 ? L->tensors[size_t(ts[k])].vbase : 0;
+      r.npages[k] = ts[k] >= 0 ? L->tensors[size_t(ts[k])].npages : 0;
+      r.scale_off[k] = ts[k] >= 0 ? int32_t(L->tensors[size_t(ts[k])].scale_off) : -1;
+    }
+    ex[i] = r;
+  }
+  HIP_TRY(hipMalloc(&d.experts, ex.size() * sizeof(MoeExpert)), "hipMalloc(expert table)");
+  HIP_TRY(hipMemcpyAsync(d.experts, ex.data(), ex.size() * sizeof(MoeExpert), hipMemcpyHostToDevice, st),
+          "upload expert table");
   std::vector<int32_t> table(P);
   d.phi_key = mask_map(L, table.data());
   HIP_TRY(hipMemcpyAsync(d.phi, table.data(), P * 4, hipMemcpyHostToDevice, st), "upload page map");
@@ -195,6 +212,7 @@ extern "C" int cloak_layout_free(cloak_layout* L) {
     (void)hipFree(L->dev.perms);
     (void)hipFree(L->dev.scales);
     (void)hipFree(L->dev.remap_pairs);
+    (void)hipFree(L->dev.experts);
     (void)hipHostFree(L->dev.h_stage);
     (void)hipEventDestroy(static_cast<hipEvent_t>(L->dev.stage_event));
   }
@@ -748,6 +766,117 @@ extern "C" int cloak_mlp(const cloak_layout* L, const void* d_pool, int32_t laye
   uint8_t* scratch = static_cast<uint8_t*>(d_ws) + hbytes;
   if (int rc = cloak_swiglu(L, d_pool, layer, d_x, M, d_ws, scratch, ws_bytes - hbytes, stream)) return rc;
   return cloak_down(L, d_pool, layer, d_ws, M, d_y, scratch, ws_bytes - hbytes, stream);
+}
+
+namespace {
+// The experts of a MoE call: FFN groups of layers first .. first+E-1, which
+// sit at consecutive positions of the ascending-layer table.  Returns the
+// position of the first, or -1 (error set).
+int64_t moe_experts(const cloak_layout* L, int32_t first, int32_t E, int32_t& dtype, int64_t& dm, int64_t& dff,
+                    const char* fn) {
+  if (E < 1 || E > 1024) {
+    set_error("%s: n_experts must be 1..1024", fn);
+    return -1;
+  }
+  int64_t pos = -1;
+  for (size_t i = 0; i < L->ffn_by_layer.size(); ++i)
+    if (L->ffn[size_t(L->ffn_by_layer[i])].layer == first) pos = int64_t(i);
+  if (pos < 0 || pos + E > int64_t(L->ffn_by_layer.size())) {
+    set_error("%s: layers %d..%d are not all FFN groups", fn, first, first + E - 1);
+    return -1;
+  }
+  for (int32_t e = 0; e < E; ++e) {
+    const FfnPerm& f = L->ffn[size_t(L->ffn_by_layer[size_t(pos + e)])];
+    if (f.layer != first + e || f.gate < 0 || f.up < 0 || f.down < 0) {
+      set_error("%s: expert %d (layer %d) lacks gate, up or down", fn, e, first + e);
+      return -1;
+    }
+    const cloak_shape& g = L->tensors[size_t(f.gate)].shape;
+    const cloak_shape& u = L->tensors[size_t(f.up)].shape;
+    const cloak_shape& d = L->tensors[size_t(f.down)].shape;
+    if (e == 0) {
+      dtype = g.dtype;
+      dm = g.k_in;
+      dff = f.d_ffn;
+    }
+    if (g.dtype != dtype || u.dtype != dtype || d.dtype != dtype || g.k_in != dm || u.k_in != dm ||
+        d.n_out != dm || f.d_ffn != dff) {
+      set_error("%s: experts must share dtype, d_model and d_ffn", fn);
+      return -1;
+    }
+  }
+  if (dtype != CLOAK_BF16 && dtype != CLOAK_FP8_E4M3) {
+    set_error("%s: experts must be BF16 or FP8 E4M3", fn);
+    return -1;
+  }
+  const int elt = elt_bytes(dtype);
+  if ((dm * elt) % 16 != 0 || (dff * elt) % 16 != 0 || dm % 8 != 0 || dff % 8 != 0 || dm > INT32_MAX ||
+      dff > INT32_MAX) {
+    set_error("%s: d_model and d_ffn rows must be multiples of 16 bytes", fn);
+    return -1;
+  }
+  return pos;
+}
+
+constexpr int64_t kMoeMaxPairs = 4096;
+}  // namespace
+
+extern "C" uint64_t cloak_moe_ws_bytes(const cloak_layout* L, int32_t first_layer, int32_t n_experts, int32_t top_k,
+                                       int64_t M) {
+  if (!L || M < 0 || top_k < 1) return UINT64_MAX;
+  int32_t dt = 0;
+  int64_t dm = 0, dff = 0;
+  if (moe_experts(L, first_layer, n_experts, dt, dm, dff, "cloak_moe_ws_bytes") < 0) return UINT64_MAX;
+  const uint64_t n = uint64_t(M) * uint64_t(top_k);
+  return a256((1 + 3 * uint64_t(n_experts) + n) * 4) + a256(n * uint64_t(dff) * 2) + a256(n * uint64_t(dm) * 4);
+}
+
+extern "C" int cloak_moe(const cloak_layout* L, const void* d_pool, int32_t first_layer, int32_t n_experts,
+                         int32_t top_k, const void* d_x, int64_t M, const int32_t* d_ids, const float* d_weights,
+                         void* d_y, void* d_ws, uint64_t ws_bytes, void* stream) {
+  clear_error();
+  if (int rc = check_device_state(L, "cloak_moe")) return rc;
+  if (int rc = check_pool(L, d_pool, "cloak_moe")) return rc;
+  int32_t dt = 0;
+  int64_t dm = 0, dff = 0;
+  const int64_t pos = moe_experts(L, first_layer, n_experts, dt, dm, dff, "cloak_moe");
+  if (pos < 0) return CLOAK_EINVAL;
+  if (top_k < 1 || M < 0 || M * top_k > kMoeMaxPairs) {
+    set_error("cloak_moe: need top_k >= 1 and M * top_k <= %lld", (long long)kMoeMaxPairs);
+    return CLOAK_EINVAL;
+  }
+  if (M == 0) return CLOAK_OK;
+  const uint64_t need = cloak_moe_ws_bytes(L, first_layer, n_experts, top_k, M);
+  if (!d_x || !d_ids || !d_weights || !d_y || !d_ws || ws_bytes < need) {
+    set_error("cloak_moe: null buffer or workspace below %llu bytes", (unsigned long long)need);
+    return CLOAK_EINVAL;
+  }
+  const uint64_t n = uint64_t(M) * uint64_t(top_k);
+  uint8_t* w = static_cast<uint8_t*>(d_ws);
+  MoeArgs a{};
+  a.pool = static_cast<const uint8_t*>(L->kernel_pool(d_pool));
+  a.phi = L->dev.phi;
+  a.phi_key = L->dev.phi_key;
+  a.log2_page = L->log2_page;
+  a.wtype = dt == CLOAK_FP8_E4M3 ? kFP8 : kBF16;
+  a.experts = static_cast<const MoeExpert*>(L->dev.experts) + pos;
+  a.scales = L->dev.scales;
+  a.E = n_experts;
+  a.topk = top_k;
+  a.M = int32_t(M);
+  a.d_model = int32_t(dm);
+  a.d_ffn = int32_t(dff);
+  a.x = static_cast<const uint16_t*>(d_x);
+  a.ids = d_ids;
+  a.wts = d_weights;
+  a.route = reinterpret_cast<int32_t*>(w);
+  w += a256((1 + 3 * uint64_t(n_experts) + n) * 4);
+  a.h = reinterpret_cast<uint16_t*>(w);
+  w += a256(n * uint64_t(dff) * 2);
+  a.yp = reinterpret_cast<float*>(w);
+  a.y = static_cast<uint16_t*>(d_y);
+  HIP_TRY(launch_moe(a, L->kernel_translate(), static_cast<hipStream_t>(stream)), "cloak_moe");
+  return CLOAK_OK;
 }
 
 extern "C" int cloak_quantize_fp8(const void* d_x, int64_t M, int64_t K, int64_t ldx, void* d_q, void* d_s,

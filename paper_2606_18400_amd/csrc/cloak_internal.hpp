@@ -117,6 +117,7 @@ struct DeviceTables {
   int32_t* perms = nullptr;      // concatenated row/column permutations
   float* scales = nullptr;       // concatenated permuted FP8 scales
   int32_t* remap_pairs = nullptr;// [P] device copy of the pair list
+  void* experts = nullptr;       // MoeExpert per FFN group, in ascending layer order
   int32_t* h_stage = nullptr;    // pinned [2P]: pair list + new phi
   void* stage_event = nullptr;   // hipEvent_t guarding h_stage reuse
 };
@@ -133,6 +134,7 @@ struct cloak_layout {
   std::vector<cloak::TensorInfo> tensors;
   std::vector<int32_t> sigma;
   std::vector<cloak::FfnPerm> ffn;
+  std::vector<int32_t> ffn_by_layer;     // indices into ffn, ascending layer id (device expert table order)
   std::vector<cloak::AttnPerm> attn;
   std::vector<cloak::PermTable> perms;   // every row/column permutation, concatenated on the device
   std::vector<int32_t> phi;

@@ -463,6 +463,228 @@ int resident_blocks(KernelFn fn, int threads) {
   return n;
 }
 
+// ------------------------------------------------------------------ MoE experts
+// A mixture-of-experts layer over cloaked expert tensors.  The route kernel
+// groups the call's (token, slot) pairs by expert in slot order; the SwiGLU
+// and down kernels give every active expert a column of workgroups whose
+// waves each stream kMoeRows rows of that expert once for all of its tokens
+// (kMoeTok at a time), translating pages per 1 KiB chunk like the GEMV; the
+// combine kernel adds each token's weighted slot results in slot order.
+
+constexpr int kMoeWaves = 4;
+constexpr int kMoeRows = 4;
+constexpr int kMoeTok = 4;
+
+__global__ __launch_bounds__(256) void moe_route_kernel(const MoeArgs a) {
+  extern __shared__ int32_t sh[];
+  const int n = a.M * a.topk;
+  int32_t* ids = sh;
+  int32_t* cnt = sh + n;
+  int32_t* start = cnt + a.E;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int e = a.ids[i];
+    ids[i] = (e >= 0 && e < a.E) ? e : -1;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < a.E; e += blockDim.x) {
+    int c = 0;
+    for (int i = 0; i < n; ++i) c += ids[i] == e;
+    cnt[e] = c;
+  }
+  __syncthreads();
+  int32_t* act_expert = a.route + 1;
+  int32_t* act_start = act_expert + a.E;
+  int32_t* act_count = act_start + a.E;
+  int32_t* ent = act_count + a.E;
+  if (threadIdx.x == 0) {
+    int na = 0, off = 0;
+    for (int e = 0; e < a.E; ++e) {
+      start[e] = off;
+      if (cnt[e] > 0) {
+        act_expert[na] = e;
+        act_start[na] = off;
+        act_count[na] = cnt[e];
+        ++na;
+        off += cnt[e];
+      }
+    }
+    a.route[0] = na;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < a.E; e += blockDim.x) {
+    if (cnt[e] == 0) continue;
+    int pos = start[e];
+    for (int i = 0; i < n; ++i)
+      if (ids[i] == e) ent[pos++] = i;
+  }
+}
+
+// This lane's 16 B of chunk c of row `row` of a tensor (zero past the row).
+template <int TR>
+__device__ inline u32x4 moe_load(const MoeArgs& a, int64_t vbase, int64_t npages, int64_t row, int64_t row_bytes,
+                                 int c, int lane, bool ok) {
+  const int64_t o = row * row_bytes + int64_t(c) * kChunkBytes;
+  const int64_t page_bytes = int64_t(1) << a.log2_page;
+  const int64_t vp = o >> a.log2_page;
+  const int64_t inpage = o & (page_bytes - 1);
+  const int64_t vpage = vbase + vp;
+  const int64_t vnext = vp + 1 < npages ? vpage + 1 : vpage;
+  const int64_t p0 = TR ? page_of<TR == 2>(a.phi, a.phi_key, vpage) : vpage;
+  const int64_t p1 = TR ? page_of<TR == 2>(a.phi, a.phi_key, vnext) : vnext;
+  const int64_t lo = inpage + int64_t(lane) * 16;
+  const bool second = lo >= page_bytes;
+  const uint8_t* addr = a.pool + ((second ? p1 : p0) << a.log2_page) + (second ? lo - page_bytes : lo);
+  u32x4 w = {0u, 0u, 0u, 0u};
+  if (ok) w = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(addr));
+  return w;
+}
+
+// bf16 activations matching this lane's weight elements of chunk c.
+template <int WT>
+__device__ inline void moe_x(const uint16_t* row, int K, int c, int lane, bool ok, uint32_t (&xr)[WTraits<WT>::XW]) {
+  constexpr int EPL = WTraits<WT>::EPL;
+  const int k0 = c * 64 * EPL + lane * EPL;
+#pragma unroll
+  for (int q = 0; q < WTraits<WT>::XW / 4; ++q) {
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if (ok && k0 < K) v = *reinterpret_cast<const u32x4*>(row + k0 + q * 8);
+    xr[4 * q] = v.x;
+    xr[4 * q + 1] = v.y;
+    xr[4 * q + 2] = v.z;
+    xr[4 * q + 3] = v.w;
+  }
+}
+
+template <int WT, int TR>
+__global__ __launch_bounds__(kMoeWaves * 64) void moe_swiglu_kernel(const MoeArgs a) {
+  constexpr int XW = WTraits<WT>::XW;
+  constexpr int V = 2 * kMoeRows * kMoeTok;
+  static_assert(V == 32, "value j of the reduction sits in lane 2j");
+  const int s = blockIdx.x;
+  if (s >= a.route[0]) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int unit0 = (int(blockIdx.y) * kMoeWaves + wave) * kMoeRows;
+  if (unit0 >= a.d_ffn) return;
+  const int e = a.route[1 + s], st = a.route[1 + a.E + s], cnt = a.route[1 + 2 * a.E + s];
+  const int32_t* ent = a.route + 1 + 3 * a.E;
+  const MoeExpert ex = a.experts[e];
+  const int64_t row_bytes = int64_t(a.d_model) * (WT == kFP8 ? 1 : 2);
+  const int nch = int((row_bytes + kChunkBytes - 1) / kChunkBytes);
+  for (int t0 = 0; t0 < cnt; t0 += kMoeTok) {
+    int pair[kMoeTok];
+#pragma unroll
+    for (int m = 0; m < kMoeTok; ++m) pair[m] = t0 + m < cnt ? ent[st + t0 + m] : -1;
+    float v[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) v[j] = 0.f;
+    for (int c = 0; c < nch; ++c) {
+      const bool lane_ok = int64_t(c) * kChunkBytes + int64_t(lane) * 16 < row_bytes;
+      uint32_t xr[kMoeTok][XW];
+#pragma unroll
+      for (int m = 0; m < kMoeTok; ++m)
+        moe_x<WT>(a.x + int64_t(pair[m] < 0 ? 0 : pair[m] / a.topk) * a.d_model, a.d_model, c, lane,
+                  pair[m] >= 0 && lane_ok, xr[m]);
+#pragma unroll
+      for (int r = 0; r < 2 * kMoeRows; ++r) {
+        const int which = r / kMoeRows;
+        const int u = unit0 + r % kMoeRows;
+        const bool rok = u < a.d_ffn;
+        const u32x4 w = moe_load<TR>(a, ex.vbase[which], ex.npages[which], rok ? u : 0, row_bytes, c, lane,
+                                     rok && lane_ok);
+#pragma unroll
+        for (int m = 0; m < kMoeTok; ++m) v[r * kMoeTok + m] = dot_chunk<WT>(w, xr[m], v[r * kMoeTok + m]);
+      }
+    }
+    lane_reduce<V>(v, lane);
+    const float mine = v[0];
+    const float upv = __shfl(mine, (lane + 32) & 63);
+    if (lane < 32 && (lane & 1) == 0) {
+      const int j = lane >> 1;
+      const int u = unit0 + j / kMoeTok, m = j % kMoeTok;
+      if (u < a.d_ffn && pair[m] >= 0) {
+        float gs = mine, us = upv;
+        if (ex.scale_off[0] >= 0) gs *= a.scales[ex.scale_off[0] + u];
+        if (ex.scale_off[1] >= 0) us *= a.scales[ex.scale_off[1] + u];
+        a.h[int64_t(pair[m]) * a.d_ffn + u] = f32_to_bf16_rne(gs / (1.0f + expf(-gs)) * us);
+      }
+    }
+  }
+}
+
+template <int WT, int TR>
+__global__ __launch_bounds__(kMoeWaves * 64) void moe_down_kernel(const MoeArgs a) {
+  constexpr int XW = WTraits<WT>::XW;
+  constexpr int V = kMoeRows * kMoeTok;
+  static_assert(V == 16, "value j of the reduction sits in lane 4j");
+  const int s = blockIdx.x;
+  if (s >= a.route[0]) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int row0 = (int(blockIdx.y) * kMoeWaves + wave) * kMoeRows;
+  if (row0 >= a.d_model) return;
+  const int e = a.route[1 + s], st = a.route[1 + a.E + s], cnt = a.route[1 + 2 * a.E + s];
+  const int32_t* ent = a.route + 1 + 3 * a.E;
+  const MoeExpert ex = a.experts[e];
+  const int64_t row_bytes = int64_t(a.d_ffn) * (WT == kFP8 ? 1 : 2);
+  const int nch = int((row_bytes + kChunkBytes - 1) / kChunkBytes);
+  for (int t0 = 0; t0 < cnt; t0 += kMoeTok) {
+    int pair[kMoeTok];
+#pragma unroll
+    for (int m = 0; m < kMoeTok; ++m) pair[m] = t0 + m < cnt ? ent[st + t0 + m] : -1;
+    float v[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) v[j] = 0.f;
+    for (int c = 0; c < nch; ++c) {
+      const bool lane_ok = int64_t(c) * kChunkBytes + int64_t(lane) * 16 < row_bytes;
+      uint32_t xr[kMoeTok][XW];
+#pragma unroll
+      for (int m = 0; m < kMoeTok; ++m)
+        moe_x<WT>(a.h + int64_t(pair[m] < 0 ? 0 : pair[m]) * a.d_ffn, a.d_ffn, c, lane, pair[m] >= 0 && lane_ok,
+                  xr[m]);
+#pragma unroll
+      for (int r = 0; r < kMoeRows; ++r) {
+        const int n = row0 + r;
+        const bool rok = n < a.d_model;
+        const u32x4 w = moe_load<TR>(a, ex.vbase[2], ex.npages[2], rok ? n : 0, row_bytes, c, lane, rok && lane_ok);
+#pragma unroll
+        for (int m = 0; m < kMoeTok; ++m) v[r * kMoeTok + m] = dot_chunk<WT>(w, xr[m], v[r * kMoeTok + m]);
+      }
+    }
+    lane_reduce<V>(v, lane);
+    if ((lane & 3) == 0) {
+      const int j = lane >> 2;
+      const int n = row0 + j / kMoeTok, m = j % kMoeTok;
+      if (n < a.d_model && pair[m] >= 0) {
+        float acc = v[0];
+        if (ex.scale_off[2] >= 0) acc *= a.scales[ex.scale_off[2] + n];
+        a.yp[int64_t(pair[m]) * a.d_model + n] = acc * a.wts[pair[m]];
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void moe_combine_kernel(const MoeArgs a) {
+  const int m = blockIdx.x;
+  for (int n = threadIdx.x; n < a.d_model; n += blockDim.x) {
+    float sum = 0.f;
+    for (int j = 0; j < a.topk; ++j) {
+      const int pi = m * a.topk + j;
+      const int e = a.ids[pi];
+      if (e >= 0 && e < a.E) sum += a.yp[int64_t(pi) * a.d_model + n];
+    }
+    a.y[int64_t(m) * a.d_model + n] = f32_to_bf16_rne(sum);
+  }
+}
+
+using MoeFn = void (*)(const MoeArgs);
+
+template <int WT>
+void pick_moe(int tr, MoeFn& sw, MoeFn& dn) {
+  sw = tr == 2 ? moe_swiglu_kernel<WT, 2> : tr == 1 ? moe_swiglu_kernel<WT, 1> : moe_swiglu_kernel<WT, 0>;
+  dn = tr == 2 ? moe_down_kernel<WT, 2> : tr == 1 ? moe_down_kernel<WT, 1> : moe_down_kernel<WT, 0>;
+}
+
 }  // namespace
 
 int gemv_cpw(int nchunks) {
@@ -496,6 +718,24 @@ hipError_t launch_gemv(const GemvArgs& a, int wtype, int mtile, bool translate, 
   if (blocks <= 0) blocks = a.groups;
   if (blocks > a.groups) blocks = a.groups;
   hipLaunchKernelGGL(fn, dim3(blocks), dim3(threads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_moe(const MoeArgs& a, bool translate, hipStream_t s) {
+  const int n = a.M * a.topk;
+  if (n <= 0) return hipSuccess;
+  const int tr = translate ? (a.phi_key ? 2 : 1) : 0;
+  MoeFn sw, dn;
+  if (a.wtype == kFP8)
+    pick_moe<kFP8>(tr, sw, dn);
+  else
+    pick_moe<kBF16>(tr, sw, dn);
+  const unsigned slots = unsigned(n < a.E ? n : a.E);
+  const unsigned per = kMoeWaves * kMoeRows;
+  hipLaunchKernelGGL(moe_route_kernel, dim3(1), dim3(256), size_t(n + 2 * a.E) * 4, s, a);
+  hipLaunchKernelGGL(sw, dim3(slots, unsigned((a.d_ffn + per - 1) / per)), dim3(kMoeWaves * 64), 0, s, a);
+  hipLaunchKernelGGL(dn, dim3(slots, unsigned((a.d_model + per - 1) / per)), dim3(kMoeWaves * 64), 0, s, a);
+  hipLaunchKernelGGL(moe_combine_kernel, dim3(unsigned(a.M)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

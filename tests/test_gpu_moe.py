@@ -1,0 +1,154 @@
+"""MoE layer over cloaked experts on the GPU (cloak_moe) against the FP64 oracle.
+
+Experts are ordinary cloaked FFN groups (own hidden permutation, own place in
+the tensor order); ids and router weights are seeded inputs.  Tolerance as for
+the other projections: normwise 1e-2 for BF16 experts, 5e-2 for FP8.
+"""
+
+import numpy as np
+import pytest
+
+from cloak_cases import TOL, from_device, make_weights, oracle_layout, to_device_x, values_f64, w64
+from oracle import moe as OMOE
+from paper_2606_18400_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def C():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2606_18400_amd import cloak
+    return cloak
+
+
+def expert_shapes(E, d, F, dtype, first=0, extra=()):
+    shapes = list(extra)
+    for e in range(E):
+        shapes += synth.ffn_block_shapes(d, F, dtype, layer=first + e)
+    return shapes
+
+
+def routing(M, k, E, seed, invalid=True):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ids = rng.integers(0, E, (M, k)).astype(np.int32)
+    if invalid and M > 2:
+        ids[1, 0] = -1            # skipped slots
+        ids[2, k - 1] = E + 3
+        ids[0, :] = ids[0, 0]     # one token naming one expert in every slot
+    w = rng.random((M, k)).astype(np.float32)
+    return ids, w
+
+
+def run_moe(C, cw, first, E, k, x_np, ids, w):
+    import torch
+    M = x_np.shape[0]
+    L = cw.layout
+    need = C.cloak_moe_ws_bytes(L, first, E, k, M)
+    ws = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+    y = torch.empty((M, x_np.shape[1]), dtype=torch.bfloat16, device="cuda")
+    d_ids = torch.from_numpy(ids).cuda()
+    d_w = torch.from_numpy(w).cuda()
+    C.cloak_moe(L, cw.pool, first, E, k, to_device_x(x_np), M, d_ids, d_w, y, ws, need)
+    return from_device(y)
+
+
+def expected(shapes, ws, scs, first, E, x_np, ids, w, extra_n=0):
+    ex = []
+    for e in range(E):
+        t = extra_n + 3 * e
+        ex.append((w64(shapes, ws, scs, t), w64(shapes, ws, scs, t + 1), w64(shapes, ws, scs, t + 2)))
+    return OMOE.moe_ffn(values_f64(x_np), ids, w.astype(np.float64), ex)
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+@pytest.mark.parametrize("M,k", [(1, 2), (5, 3), (37, 2), (64, 8)])
+def test_moe_vs_fp64(C, dtype, M, k):
+    # d_model 272 and d_ffn 208: rows of 544 / 416 B (bf16) straddle the 1 KiB pages
+    E, d, F = 8, 272, 208
+    extra = [(-1, "head", 40, d, dtype)]
+    shapes = expert_shapes(E, d, F, dtype, first=3, extra=extra)
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, 1024, 1024 * 4096, seed=61)
+    cw.load(ws, scs)
+    x = synth.activations(M, d, "bf16", seed=M)
+    ids, w = routing(M, k, E, seed=M + k)
+    y = run_moe(C, cw, 3, E, k, x, ids, w)
+    ref = expected(shapes, ws, scs, 3, E, x, ids, w, extra_n=1)
+    err = ON_err(y, ref)
+    assert err <= TOL[dtype], err
+    if M > 2:
+        assert np.count_nonzero(values_f64(y)[1]) > d // 2   # a skipped slot leaves the other slots
+    cw.close()
+
+
+def ON_err(y, ref):
+    from oracle import numerics as ON
+    return ON.normwise_err(values_f64(y), ref)
+
+
+def test_moe_masked_map_and_remap_bit_identical(C):
+    E, d, F, k, M = 6, 256, 512, 2, 9
+    shapes = expert_shapes(E, d, F, "bf16", first=0)
+    ws, scs = make_weights(shapes)
+    plain = C.CloakedWeights(shapes, 4096, 4096 * 2048, seed=63)
+    mask = C.CloakedWeights(shapes, 4096, 4096 * 2048, seed=63, flags=C.CLOAK_MASKED_MAP)
+    for cw in (plain, mask):
+        cw.load(ws, scs)
+    x = synth.activations(M, d, "bf16", seed=1)
+    ids, w = routing(M, k, E, seed=2)
+    a = run_moe(C, plain, 0, E, k, x, ids, w)
+    b = run_moe(C, mask, 0, E, k, x, ids, w)
+    assert np.array_equal(a, b)
+    mask.remap(7)
+    assert np.array_equal(run_moe(C, mask, 0, E, k, x, ids, w), a)
+    for cw in (plain, mask):
+        cw.close()
+
+
+def test_moe_argument_errors(C):
+    import torch
+    shapes = expert_shapes(4, 64, 64, "bf16", first=0) + [(9, "gate", 64, 64, "bf16")]
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, 1024, 1024 * 256, seed=1)
+    cw.load(ws, scs)
+    L = cw.layout
+    for first, E in [(0, 5), (1, 4), (9, 1), (0, 0)]:
+        with pytest.raises(C.CloakError):
+            C.cloak_moe_ws_bytes(L, first, E, 2, 4)
+    need = C.cloak_moe_ws_bytes(L, 0, 4, 2, 4)
+    buf = torch.empty(need, dtype=torch.uint8, device="cuda")
+    x = torch.zeros((4, 64), dtype=torch.bfloat16, device="cuda")
+    ids = torch.zeros((4, 2), dtype=torch.int32, device="cuda")
+    w = torch.zeros((4, 2), dtype=torch.float32, device="cuda")
+    y = torch.empty((4, 64), dtype=torch.bfloat16, device="cuda")
+    with pytest.raises(C.CloakError):
+        C.cloak_moe(L, cw.pool, 0, 4, 2, x, 4, ids, w, y, buf, need - 1)
+    with pytest.raises(C.CloakError):
+        C.cloak_moe(L, cw.pool, 0, 4, 1025, x, 4, ids, w, y, buf, need)
+    C.cloak_moe(L, cw.pool, 0, 4, 2, x, 0, ids, w, y, buf, need)   # M = 0: no-op
+    cw.close()
+
+
+def test_moe_qwen3_expert_shapes_sampled(C):
+    # 128 experts of 2048 -> 768 -> 2048 (a Qwen-3-30B-A3B-like MoE layer), top-8,
+    # 2 MiB pages; decode batches of 1 and 64 tokens, 6 tokens checked in FP64
+    E, d, F, k = 128, 2048, 768, 8
+    shapes = expert_shapes(E, d, F, "bf16", first=0)
+    one = [synth.weight(t, s[2], s[3], "bf16")[0] for t, s in enumerate(shapes[:3 * 8])]
+    ws = [one[t % len(one)] for t in range(len(shapes))]     # 8 distinct experts reused
+    cw = C.CloakedWeights(shapes, 2 << 20, 2 << 30, seed=65)
+    cw.load(ws)
+    for M in (1, 64):
+        x = synth.activations(M, d, "bf16", seed=M)
+        ids, w = routing(M, k, E, seed=M, invalid=False)
+        y = run_moe(C, cw, 0, E, k, x, ids, w)
+        nos = [None] * len(ws)
+        for m in sorted({0, M - 1, M // 2}):
+            # only the experts token m names are decoded (the others are never read)
+            sub = [tuple(w64(shapes, ws, nos, 3 * e + i) for i in range(3)) if e in set(ids[m].tolist()) else None
+                   for e in range(E)]
+            ref = OMOE.moe_ffn(values_f64(x[m:m + 1]), ids[m:m + 1], w[m:m + 1].astype(np.float64), sub)
+            assert ON_err(y[m:m + 1], ref) <= 1e-2, (M, m)
+    cw.close()
