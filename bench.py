@@ -432,6 +432,76 @@ def bench_stack(args):
     print(json.dumps(out), flush=True)
 
 
+MOE = dict(slots=8, experts=128, top_k=8, d_model=2048, d_ffn=768, page_bytes=2 << 20, pool_bytes=12 << 30)
+
+
+def bench_moe(args):
+    """Decode through MoE layers of 128 cloaked BF16 experts (2048 -> 768 -> 2048,
+    a Qwen-3-30B-A3B-like expert shape), top-8 routing, 8 layer slots cycled."""
+    import torch
+    from paper_2606_18400_amd import cloak as C
+    from paper_2606_18400_amd import synth
+    cfg = MOE
+    E, k, d, F = cfg["experts"], cfg["top_k"], cfg["d_model"], cfg["d_ffn"]
+    shapes = []
+    for l in range(cfg["slots"]):
+        for e in range(E):
+            shapes += synth.ffn_block_shapes(d, F, "bf16", layer=l * E + e)
+    log("generating 8 distinct experts (reused by every expert slot, distinct placement)")
+    base = [synth.weight(t, s[2], s[3], "bf16")[0] for t, s in enumerate(shapes[:24])]
+    weights = [base[t % 24] for t in range(len(shapes))]
+    expert_bytes = 3 * d * F * 2
+    res = {}
+    batches = [int(m) for m in args.moe_batches.split(",") if m]
+    for name, flags in [("cloaked", 0), ("native", C.CLOAK_IDENTITY | C.CLOAK_NATIVE)]:
+        log(f"{name}: loading {cfg['slots']} x {E} experts into a {cfg['pool_bytes'] >> 30} GiB pool")
+        cw = C.CloakedWeights(shapes, cfg["page_bytes"], cfg["pool_bytes"], seed=1, flags=flags)
+        cw.load(weights)
+        res[name] = {}
+        for M in batches:
+            rng = np.random.Generator(np.random.PCG64(17 + M))   # the same routing for both layouts
+            ids = np.stack([rng.choice(E, k, replace=False) for _ in range(M)]).astype(np.int32)
+            w = rng.random((M, k)).astype(np.float32)
+            w /= w.sum(axis=1, keepdims=True)
+            active = len(set(ids.ravel().tolist()))
+            nbytes = active * expert_bytes + 2 * M * d * 2 + M * k * 8
+            x = torch.from_numpy(synth.activations(M, d, "bf16").view(np.int16)).cuda().view(torch.bfloat16)
+            y = torch.empty((M, d), dtype=torch.bfloat16, device="cuda")
+            d_ids, d_w = torch.from_numpy(ids).cuda(), torch.from_numpy(w).cuda()
+            need = C.cloak_moe_ws_bytes(cw.layout, 0, E, k, M)
+            ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+
+            def call(i):
+                C.cloak_moe(cw.layout, cw.pool, (i % cfg["slots"]) * E, E, k, x, M, d_ids, d_w, y, ws, need)
+
+            for i in range(args.warmup):
+                call(i)
+            torch.cuda.synchronize()
+            reps = max(args.steps, 16)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for i in range(reps):
+                call(i)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            res[name][str(M)] = dict(ms=ms, gbs=nbytes / ms / 1e6, active_experts=active, bytes=nbytes)
+            log(f"{name} M={M}: {ms * 1e3:.1f} us per MoE layer, {active} experts, {nbytes / ms / 1e6:.0f} GB/s")
+        cw.close()
+        torch.cuda.empty_cache()
+    for M in res["cloaked"]:
+        res["cloaked"][M]["ratio"] = res["native"][M]["ms"] / res["cloaked"][M]["ms"]
+    m0 = str(batches[0])
+    out = {"metric": METRIC, "value": res["cloaked"][m0]["gbs"], "unit": "GB/s", "n_gpus": 1,
+           "ms_per_step": res["cloaked"][m0]["ms"], "higher_is_better": True, "vs_baseline": None, "dtype": "bf16",
+           "data": "synthetic",
+           "config": {"workload": f"decode through one MoE layer of {E} BF16 experts {d}/{F}, top-{k} routing, "
+                                  f"{cfg['slots']} layer slots cycled, 2 MiB pages over a 12 GiB pool",
+                      "expert_bytes": expert_bytes},
+           "moe": res}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -446,7 +516,8 @@ def main():
                          "draws, masked device page map, decoy free pages)")
     ap.add_argument("--remap-reps", type=int, default=5)
     ap.add_argument("--prefill-tokens", type=int, default=8192, help="prefill batch (0 skips the prefill pass)")
-    ap.add_argument("--workload", default="layer", choices=["layer", "serve", "stack"],
+    ap.add_argument("--moe-batches", default="1,8,32,64,256", help="moe: decode batch sizes")
+    ap.add_argument("--workload", default="layer", choices=["layer", "serve", "stack", "moe"],
                     help="layer: the headline decode layer (default); serve: serving trace; stack: 64-layer FP8")
     ap.add_argument("--rates", default="2,8", help="serve: Poisson arrival rates (req/s)")
     ap.add_argument("--requests", type=int, default=32, help="serve: requests per rate")
@@ -469,6 +540,8 @@ def main():
         return bench_serve(args)
     if args.workload == "stack":
         return bench_stack(args)
+    if args.workload == "moe":
+        return bench_moe(args)
     cfg = synth.LAYER4096
     d, f, kv = cfg["d_model"], cfg["d_ffn"], cfg["d_kv"]
     one = synth.decoder_layer_shapes(d, f, kv, "bf16", layer=0)

@@ -315,8 +315,8 @@ int cloak_down(const cloak_layout* layout, const void* d_pool, int32_t layer, co
  * d_weights f32 [M][top_k] on the device (routing is the caller's).  Experts
  * are BF16 or FP8 (per-row scales) with one d_model and d_ffn.  The hidden
  * activations are rounded to bf16, the weighted expert outputs kept in f32 and
- * added per token in slot order.  M * top_k <= 4096.  Workspace:
- * cloak_moe_ws_bytes.  Errors: EINVAL (experts missing or inconsistent, sizes,
+ * added per token in slot order.  M * top_k <= 4096; x 16-byte, y 8-byte and
+ * the workspace 256-byte aligned.  Workspace: cloak_moe_ws_bytes.  Errors: EINVAL (experts missing or inconsistent, sizes,
  * workspace). */
 uint64_t cloak_moe_ws_bytes(const cloak_layout* layout, int32_t first_layer, int32_t n_experts, int32_t top_k,
                             int64_t M);

@@ -851,6 +851,11 @@ extern "C" int cloak_moe(const cloak_layout* L, const void* d_pool, int32_t firs
     set_error("cloak_moe: null buffer or workspace below %llu bytes", (unsigned long long)need);
     return CLOAK_EINVAL;
   }
+  if (reinterpret_cast<uintptr_t>(d_x) % 16 != 0 || reinterpret_cast<uintptr_t>(d_y) % 8 != 0 ||
+      reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) {
+    set_error("cloak_moe: x must be 16-byte, y 8-byte and the workspace 256-byte aligned");
+    return CLOAK_EINVAL;
+  }
   const uint64_t n = uint64_t(M) * uint64_t(top_k);
   uint8_t* w = static_cast<uint8_t*>(d_ws);
   MoeArgs a{};

@@ -465,58 +465,137 @@ int resident_blocks(KernelFn fn, int threads) {
 
 // ------------------------------------------------------------------ MoE experts
 // A mixture-of-experts layer over cloaked expert tensors.  The route kernel
-// groups the call's (token, slot) pairs by expert in slot order; the SwiGLU
-// and down kernels give every active expert a column of workgroups whose
-// waves each stream kMoeRows rows of that expert once for all of its tokens
-// (kMoeTok at a time), translating pages per 1 KiB chunk like the GEMV; the
-// combine kernel adds each token's weighted slot results in slot order.
+// sorts the call's (token, slot) pairs by (expert, pair) and cuts the sorted
+// list into one run per active expert; the SwiGLU and down kernels give every
+// active expert a column of workgroups whose waves each stream a few rows of
+// that expert once per MT of its tokens, translating pages per 1 KiB chunk
+// like the GEMV; the combine kernel adds each token's weighted slot results
+// in slot order.  Every result bit is independent of scheduling.
 
 constexpr int kMoeWaves = 4;
-constexpr int kMoeRows = 4;
-constexpr int kMoeTok = 4;
+constexpr int kMoeUnits = 2;      // hidden units (gate + up rows) per wave of the SwiGLU kernel
+constexpr int kMoeDownRows = 8;   // down rows per wave (down rows are d_ffn long, usually short)
+constexpr int kMoeLoads = 16;     // 16 B loads per lane issued together (rows x 1 KiB chunks)
+constexpr int kMoeRouteThreads = 1024;
+constexpr int kMoePairBits = 12;  // pair index < 4096 in the sort key
 
-__global__ __launch_bounds__(256) void moe_route_kernel(const MoeArgs a) {
-  extern __shared__ int32_t sh[];
+// Calls of at most 64 pairs: one wave sorts the keys in registers (bitonic
+// network over lanes), finds the runs with a ballot and writes the same
+// tables as the workgroup version below.
+__global__ __launch_bounds__(64) void moe_route_wave_kernel(const MoeArgs a) {
   const int n = a.M * a.topk;
-  int32_t* ids = sh;
-  int32_t* cnt = sh + n;
-  int32_t* start = cnt + a.E;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int e = a.ids[i];
-    ids[i] = (e >= 0 && e < a.E) ? e : -1;
+  const int l = threadIdx.x;
+  int32_t key = INT32_MAX;
+  if (l < n) {
+    int e = a.ids[l];
+    if (e < 0 || e >= a.E) e = a.E;
+    key = (e << kMoePairBits) | l;
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < a.E; e += blockDim.x) {
-    int c = 0;
-    for (int i = 0; i < n; ++i) c += ids[i] == e;
-    cnt[e] = c;
+  for (int k = 2; k <= 64; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int32_t p = __shfl_xor(key, j);
+      const bool lower = (l & j) == 0, asc = (l & k) == 0;
+      key = (lower == asc) ? min(key, p) : max(key, p);
+    }
   }
-  __syncthreads();
+  const int e = key >> kMoePairBits;
+  const bool valid = e < a.E;
+  const int32_t prev = __shfl_up(key, 1);
+  const bool opens = valid && (l == 0 || (prev >> kMoePairBits) != e);
+  const unsigned long long runs = __ballot(opens);
+  const int n_valid = __popcll(__ballot(valid));
   int32_t* act_expert = a.route + 1;
   int32_t* act_start = act_expert + a.E;
   int32_t* act_count = act_start + a.E;
   int32_t* ent = act_count + a.E;
-  if (threadIdx.x == 0) {
-    int na = 0, off = 0;
-    for (int e = 0; e < a.E; ++e) {
-      start[e] = off;
-      if (cnt[e] > 0) {
-        act_expert[na] = e;
-        act_start[na] = off;
-        act_count[na] = cnt[e];
-        ++na;
-        off += cnt[e];
-      }
+  if (valid) ent[l] = key & ((1 << kMoePairBits) - 1);
+  if (opens) {
+    const int slot = __popcll(runs & ((1ull << l) - 1));
+    const unsigned long long later = l < 63 ? runs & ~((2ull << l) - 1) : 0ull;
+    const int end = later ? __ffsll((long long)later) - 1 : n_valid;
+    act_expert[slot] = e;
+    act_start[slot] = l;
+    act_count[slot] = end - l;
+  }
+  if (l == 0) a.route[0] = __popcll(runs);
+}
+
+__global__ __launch_bounds__(kMoeRouteThreads) void moe_route_kernel(const MoeArgs a) {
+  extern __shared__ int32_t sh[];
+  const int n = a.M * a.topk;
+  int N2 = 1;
+  while (N2 < n) N2 <<= 1;
+  int32_t* keys = sh;                       // [N2] (expert << 12) | pair, invalid experts sort last
+  int32_t* part = sh + N2;                  // [threads] run counts, then their inclusive scan
+  int32_t* sstart = part + kMoeRouteThreads;  // [min(E, n)] start of each active expert's run
+  __shared__ int32_t n_valid;
+  const int T = blockDim.x, t = threadIdx.x;
+  if (t == 0) n_valid = 0;
+  for (int i = t; i < N2; i += T) {
+    int32_t key = INT32_MAX;
+    if (i < n) {
+      int e = a.ids[i];
+      if (e < 0 || e >= a.E) e = a.E;
+      key = (e << kMoePairBits) | i;
     }
-    a.route[0] = na;
+    keys[i] = key;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < a.E; e += blockDim.x) {
-    if (cnt[e] == 0) continue;
-    int pos = start[e];
-    for (int i = 0; i < n; ++i)
-      if (ids[i] == e) ent[pos++] = i;
+  for (int k = 2; k <= N2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = t; i < N2; i += T) {
+        const int l = i ^ j;
+        if (l > i) {
+          const int32_t x = keys[i], y = keys[l];
+          if ((x > y) == ((i & k) == 0)) {
+            keys[i] = y;
+            keys[l] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
   }
+  // runs: position p opens one when its expert differs from position p-1's
+  const int per = (n + T - 1) / T;
+  const int lo = t * per, hi = min(n, lo + per);
+  int runs = 0, valid = 0;
+  for (int p = lo; p < hi; ++p) {
+    const int e = keys[p] >> kMoePairBits;
+    if (e < a.E) {
+      ++valid;
+      if (p == 0 || (keys[p - 1] >> kMoePairBits) != e) ++runs;
+    }
+  }
+  part[t] = runs;
+  atomicAdd(&n_valid, valid);   // an integer sum: any order gives the same value
+  __syncthreads();
+  for (int off = 1; off < T; off <<= 1) {
+    const int v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int32_t* act_expert = a.route + 1;
+  int32_t* act_start = act_expert + a.E;
+  int32_t* act_count = act_start + a.E;
+  int32_t* ent = act_count + a.E;
+  int s = part[t] - runs;
+  for (int p = lo; p < hi; ++p) {
+    const int e = keys[p] >> kMoePairBits;
+    if (e >= a.E) break;
+    ent[p] = keys[p] & ((1 << kMoePairBits) - 1);
+    if (p == 0 || (keys[p - 1] >> kMoePairBits) != e) {
+      act_expert[s] = e;
+      act_start[s] = p;
+      sstart[s] = p;
+      ++s;
+    }
+  }
+  __syncthreads();
+  const int na = part[T - 1];
+  for (int r = t; r < na; r += T) act_count[r] = (r + 1 < na ? sstart[r + 1] : n_valid) - sstart[r];
+  if (t == 0) a.route[0] = na;
 }
 
 // This lane's 16 B of chunk c of row `row` of a tensor (zero past the row).
@@ -555,53 +634,82 @@ __device__ inline void moe_x(const uint16_t* row, int K, int c, int lane, bool o
   }
 }
 
-template <int WT, int TR>
-__global__ __launch_bounds__(kMoeWaves * 64) void moe_swiglu_kernel(const MoeArgs a) {
+// NR rows of one expert tensor set (gate and up, or down) times MT tokens:
+// per-lane partial sums in v[r * MT + m].  Rows are (tensor ti[r], row rr[r]).
+template <int WT, int TR, int NR, int MT>
+__device__ inline void moe_rows(const MoeArgs& a, const MoeExpert& ex, const int (&ti)[NR], const int (&rr)[NR],
+                                const bool (&rok)[NR], int64_t row_bytes, const uint16_t* xbase, int K,
+                                const int (&xrow)[MT], int lane, float (&v)[NR * MT]) {
   constexpr int XW = WTraits<WT>::XW;
-  constexpr int V = 2 * kMoeRows * kMoeTok;
-  static_assert(V == 32, "value j of the reduction sits in lane 2j");
+  constexpr int CH = kMoeLoads / NR > 0 ? kMoeLoads / NR : 1;   // chunks per pass
+  const int nch = int((row_bytes + kChunkBytes - 1) / kChunkBytes);
+  for (int c0 = 0; c0 < nch; c0 += CH) {
+    u32x4 w[CH][NR];
+#pragma unroll
+    for (int cc = 0; cc < CH; ++cc) {
+      const int c = c0 + cc;
+      const bool ok = c < nch && int64_t(c) * kChunkBytes + int64_t(lane) * 16 < row_bytes;
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        w[cc][r] = moe_load<TR>(a, ex.vbase[ti[r]], ex.npages[ti[r]], rok[r] ? rr[r] : 0, row_bytes,
+                                c < nch ? c : 0, lane, ok && rok[r]);
+    }
+#pragma unroll
+    for (int cc = 0; cc < CH; ++cc) {
+      const int c = c0 + cc;
+      if (c >= nch) break;
+      const bool ok = int64_t(c) * kChunkBytes + int64_t(lane) * 16 < row_bytes;
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        uint32_t xr[XW];
+        moe_x<WT>(xbase + int64_t(xrow[m] < 0 ? 0 : xrow[m]) * K, K, c, lane, ok && xrow[m] >= 0, xr);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r * MT + m] = dot_chunk<WT>(w[cc][r], xr, v[r * MT + m]);
+      }
+    }
+  }
+}
+
+template <int WT, int TR, int MT>
+__global__ __launch_bounds__(kMoeWaves * 64) void moe_swiglu_kernel(const MoeArgs a) {
+  constexpr int NR = 2 * kMoeUnits;
+  constexpr int V = NR * MT;
+  constexpr int STRIDE = 64 / V;   // value j of the reduction sits in lane j * STRIDE; up values 32 lanes on
   const int s = blockIdx.x;
   if (s >= a.route[0]) return;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int unit0 = (int(blockIdx.y) * kMoeWaves + wave) * kMoeRows;
+  const int unit0 = (int(blockIdx.y) * kMoeWaves + wave) * kMoeUnits;
   if (unit0 >= a.d_ffn) return;
   const int e = a.route[1 + s], st = a.route[1 + a.E + s], cnt = a.route[1 + 2 * a.E + s];
   const int32_t* ent = a.route + 1 + 3 * a.E;
   const MoeExpert ex = a.experts[e];
   const int64_t row_bytes = int64_t(a.d_model) * (WT == kFP8 ? 1 : 2);
-  const int nch = int((row_bytes + kChunkBytes - 1) / kChunkBytes);
-  for (int t0 = 0; t0 < cnt; t0 += kMoeTok) {
-    int pair[kMoeTok];
+  int ti[NR], rr[NR];
+  bool rok[NR];
 #pragma unroll
-    for (int m = 0; m < kMoeTok; ++m) pair[m] = t0 + m < cnt ? ent[st + t0 + m] : -1;
+  for (int r = 0; r < NR; ++r) {
+    ti[r] = r / kMoeUnits;
+    rr[r] = unit0 + r % kMoeUnits;
+    rok[r] = rr[r] < a.d_ffn;
+  }
+  for (int t0 = 0; t0 < cnt; t0 += MT) {
+    int pair[MT], xrow[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      pair[m] = t0 + m < cnt ? ent[st + t0 + m] : -1;
+      xrow[m] = pair[m] < 0 ? -1 : pair[m] / a.topk;
+    }
     float v[V];
 #pragma unroll
     for (int j = 0; j < V; ++j) v[j] = 0.f;
-    for (int c = 0; c < nch; ++c) {
-      const bool lane_ok = int64_t(c) * kChunkBytes + int64_t(lane) * 16 < row_bytes;
-      uint32_t xr[kMoeTok][XW];
-#pragma unroll
-      for (int m = 0; m < kMoeTok; ++m)
-        moe_x<WT>(a.x + int64_t(pair[m] < 0 ? 0 : pair[m] / a.topk) * a.d_model, a.d_model, c, lane,
-                  pair[m] >= 0 && lane_ok, xr[m]);
-#pragma unroll
-      for (int r = 0; r < 2 * kMoeRows; ++r) {
-        const int which = r / kMoeRows;
-        const int u = unit0 + r % kMoeRows;
-        const bool rok = u < a.d_ffn;
-        const u32x4 w = moe_load<TR>(a, ex.vbase[which], ex.npages[which], rok ? u : 0, row_bytes, c, lane,
-                                     rok && lane_ok);
-#pragma unroll
-        for (int m = 0; m < kMoeTok; ++m) v[r * kMoeTok + m] = dot_chunk<WT>(w, xr[m], v[r * kMoeTok + m]);
-      }
-    }
+    moe_rows<WT, TR, NR, MT>(a, ex, ti, rr, rok, row_bytes, a.x, a.d_model, xrow, lane, v);
     lane_reduce<V>(v, lane);
     const float mine = v[0];
     const float upv = __shfl(mine, (lane + 32) & 63);
-    if (lane < 32 && (lane & 1) == 0) {
-      const int j = lane >> 1;
-      const int u = unit0 + j / kMoeTok, m = j % kMoeTok;
+    if (lane < 32 && lane % STRIDE == 0) {
+      const int j = lane / STRIDE;
+      const int u = unit0 + j / MT, m = j % MT;
       if (u < a.d_ffn && pair[m] >= 0) {
         float gs = mine, us = upv;
         if (ex.scale_off[0] >= 0) gs *= a.scales[ex.scale_off[0] + u];
@@ -612,49 +720,41 @@ __global__ __launch_bounds__(kMoeWaves * 64) void moe_swiglu_kernel(const MoeArg
   }
 }
 
-template <int WT, int TR>
+template <int WT, int TR, int MT>
 __global__ __launch_bounds__(kMoeWaves * 64) void moe_down_kernel(const MoeArgs a) {
-  constexpr int XW = WTraits<WT>::XW;
-  constexpr int V = kMoeRows * kMoeTok;
-  static_assert(V == 16, "value j of the reduction sits in lane 4j");
+  constexpr int NR = kMoeDownRows;
+  constexpr int V = NR * MT;
+  constexpr int STRIDE = 64 / V;
   const int s = blockIdx.x;
   if (s >= a.route[0]) return;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int row0 = (int(blockIdx.y) * kMoeWaves + wave) * kMoeRows;
+  const int row0 = (int(blockIdx.y) * kMoeWaves + wave) * kMoeDownRows;
   if (row0 >= a.d_model) return;
   const int e = a.route[1 + s], st = a.route[1 + a.E + s], cnt = a.route[1 + 2 * a.E + s];
   const int32_t* ent = a.route + 1 + 3 * a.E;
   const MoeExpert ex = a.experts[e];
   const int64_t row_bytes = int64_t(a.d_ffn) * (WT == kFP8 ? 1 : 2);
-  const int nch = int((row_bytes + kChunkBytes - 1) / kChunkBytes);
-  for (int t0 = 0; t0 < cnt; t0 += kMoeTok) {
-    int pair[kMoeTok];
+  int ti[NR], rr[NR];
+  bool rok[NR];
 #pragma unroll
-    for (int m = 0; m < kMoeTok; ++m) pair[m] = t0 + m < cnt ? ent[st + t0 + m] : -1;
+  for (int r = 0; r < NR; ++r) {
+    ti[r] = 2;
+    rr[r] = row0 + r;
+    rok[r] = rr[r] < a.d_model;
+  }
+  for (int t0 = 0; t0 < cnt; t0 += MT) {
+    int pair[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) pair[m] = t0 + m < cnt ? ent[st + t0 + m] : -1;
     float v[V];
 #pragma unroll
     for (int j = 0; j < V; ++j) v[j] = 0.f;
-    for (int c = 0; c < nch; ++c) {
-      const bool lane_ok = int64_t(c) * kChunkBytes + int64_t(lane) * 16 < row_bytes;
-      uint32_t xr[kMoeTok][XW];
-#pragma unroll
-      for (int m = 0; m < kMoeTok; ++m)
-        moe_x<WT>(a.h + int64_t(pair[m] < 0 ? 0 : pair[m]) * a.d_ffn, a.d_ffn, c, lane, pair[m] >= 0 && lane_ok,
-                  xr[m]);
-#pragma unroll
-      for (int r = 0; r < kMoeRows; ++r) {
-        const int n = row0 + r;
-        const bool rok = n < a.d_model;
-        const u32x4 w = moe_load<TR>(a, ex.vbase[2], ex.npages[2], rok ? n : 0, row_bytes, c, lane, rok && lane_ok);
-#pragma unroll
-        for (int m = 0; m < kMoeTok; ++m) v[r * kMoeTok + m] = dot_chunk<WT>(w, xr[m], v[r * kMoeTok + m]);
-      }
-    }
+    moe_rows<WT, TR, NR, MT>(a, ex, ti, rr, rok, row_bytes, a.h, a.d_ffn, pair, lane, v);
     lane_reduce<V>(v, lane);
-    if ((lane & 3) == 0) {
-      const int j = lane >> 2;
-      const int n = row0 + j / kMoeTok, m = j % kMoeTok;
+    if (lane % STRIDE == 0) {
+      const int j = lane / STRIDE;
+      const int n = row0 + j / MT, m = j % MT;
       if (n < a.d_model && pair[m] >= 0) {
         float acc = v[0];
         if (ex.scale_off[2] >= 0) acc *= a.scales[ex.scale_off[2] + n];
@@ -664,25 +764,56 @@ __global__ __launch_bounds__(kMoeWaves * 64) void moe_down_kernel(const MoeArgs 
   }
 }
 
+// One thread per 4 outputs of a token: the weighted slot results in slot order.
 __global__ __launch_bounds__(256) void moe_combine_kernel(const MoeArgs a) {
   const int m = blockIdx.x;
-  for (int n = threadIdx.x; n < a.d_model; n += blockDim.x) {
-    float sum = 0.f;
-    for (int j = 0; j < a.topk; ++j) {
-      const int pi = m * a.topk + j;
-      const int e = a.ids[pi];
-      if (e >= 0 && e < a.E) sum += a.yp[int64_t(pi) * a.d_model + n];
+  const int n0 = (int(blockIdx.y) * 256 + int(threadIdx.x)) * 4;
+  if (n0 >= a.d_model) return;
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 8
+  for (int j = 0; j < a.topk; ++j) {
+    const int pi = m * a.topk + j;
+    const int e = a.ids[pi];
+    if (e >= 0 && e < a.E) {
+      const float4 p = *reinterpret_cast<const float4*>(a.yp + int64_t(pi) * a.d_model + n0);
+      acc.x += p.x;
+      acc.y += p.y;
+      acc.z += p.z;
+      acc.w += p.w;
     }
-    a.y[int64_t(m) * a.d_model + n] = f32_to_bf16_rne(sum);
   }
+  const uint32_t lo = uint32_t(f32_to_bf16_rne(acc.x)) | (uint32_t(f32_to_bf16_rne(acc.y)) << 16);
+  const uint32_t hi = uint32_t(f32_to_bf16_rne(acc.z)) | (uint32_t(f32_to_bf16_rne(acc.w)) << 16);
+  *reinterpret_cast<uint2*>(a.y + int64_t(m) * a.d_model + n0) = make_uint2(lo, hi);
 }
 
 using MoeFn = void (*)(const MoeArgs);
 
+template <int WT, int TR>
+void pick_moe_mt(int mt, MoeFn& sw, MoeFn& dn) {
+  if (mt <= 1) {
+    sw = moe_swiglu_kernel<WT, TR, 1>;
+    dn = moe_down_kernel<WT, TR, 1>;
+  } else if (mt <= 2) {
+    sw = moe_swiglu_kernel<WT, TR, 2>;
+    dn = moe_down_kernel<WT, TR, 2>;
+  } else if (mt <= 4) {
+    sw = moe_swiglu_kernel<WT, TR, 4>;
+    dn = moe_down_kernel<WT, TR, 4>;
+  } else {
+    sw = moe_swiglu_kernel<WT, TR, 8>;
+    dn = moe_down_kernel<WT, TR, 8>;
+  }
+}
+
 template <int WT>
-void pick_moe(int tr, MoeFn& sw, MoeFn& dn) {
-  sw = tr == 2 ? moe_swiglu_kernel<WT, 2> : tr == 1 ? moe_swiglu_kernel<WT, 1> : moe_swiglu_kernel<WT, 0>;
-  dn = tr == 2 ? moe_down_kernel<WT, 2> : tr == 1 ? moe_down_kernel<WT, 1> : moe_down_kernel<WT, 0>;
+void pick_moe(int tr, int mt, MoeFn& sw, MoeFn& dn) {
+  if (tr == 2)
+    pick_moe_mt<WT, 2>(mt, sw, dn);
+  else if (tr == 1)
+    pick_moe_mt<WT, 1>(mt, sw, dn);
+  else
+    pick_moe_mt<WT, 0>(mt, sw, dn);
 }
 
 }  // namespace
@@ -724,18 +855,33 @@ hipError_t launch_gemv(const GemvArgs& a, int wtype, int mtile, bool translate, 
 hipError_t launch_moe(const MoeArgs& a, bool translate, hipStream_t s) {
   const int n = a.M * a.topk;
   if (n <= 0) return hipSuccess;
+  if (n > (1 << kMoePairBits) || a.E >= (1 << (31 - kMoePairBits)) || a.d_model % 4 != 0)
+    return hipErrorInvalidValue;
   const int tr = translate ? (a.phi_key ? 2 : 1) : 0;
+  // token tile from the pairs an active expert averages: every extra pass
+  // re-streams the expert's rows (measured on 128 experts of 2048/768: 4-token
+  // tiles beat 2-token tiles from 2 pairs per expert, 8-token tiles beat two
+  // 4-token passes at 16)
+  const int per_expert = (n + a.E - 1) / a.E;
+  const int mt = a.M == 1 ? 1 : per_expert <= 1 ? 2 : per_expert <= 4 ? 4 : 8;
   MoeFn sw, dn;
   if (a.wtype == kFP8)
-    pick_moe<kFP8>(tr, sw, dn);
+    pick_moe<kFP8>(tr, mt, sw, dn);
   else
-    pick_moe<kBF16>(tr, sw, dn);
+    pick_moe<kBF16>(tr, mt, sw, dn);
+  int n2 = 1;
+  while (n2 < n) n2 <<= 1;
   const unsigned slots = unsigned(n < a.E ? n : a.E);
-  const unsigned per = kMoeWaves * kMoeRows;
-  hipLaunchKernelGGL(moe_route_kernel, dim3(1), dim3(256), size_t(n + 2 * a.E) * 4, s, a);
-  hipLaunchKernelGGL(sw, dim3(slots, unsigned((a.d_ffn + per - 1) / per)), dim3(kMoeWaves * 64), 0, s, a);
-  hipLaunchKernelGGL(dn, dim3(slots, unsigned((a.d_model + per - 1) / per)), dim3(kMoeWaves * 64), 0, s, a);
-  hipLaunchKernelGGL(moe_combine_kernel, dim3(unsigned(a.M)), dim3(256), 0, s, a);
+  const size_t route_lds = size_t(n2 + kMoeRouteThreads + slots) * 4;
+  const unsigned per_sw = kMoeWaves * kMoeUnits, per_dn = kMoeWaves * kMoeDownRows;
+  if (n <= 64)
+    hipLaunchKernelGGL(moe_route_wave_kernel, dim3(1), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL(moe_route_kernel, dim3(1), dim3(kMoeRouteThreads), route_lds, s, a);
+  hipLaunchKernelGGL(sw, dim3(slots, unsigned((a.d_ffn + per_sw - 1) / per_sw)), dim3(kMoeWaves * 64), 0, s, a);
+  hipLaunchKernelGGL(dn, dim3(slots, unsigned((a.d_model + per_dn - 1) / per_dn)), dim3(kMoeWaves * 64), 0, s, a);
+  hipLaunchKernelGGL(moe_combine_kernel, dim3(unsigned(a.M), unsigned((a.d_model + 1023) / 1024)), dim3(256), 0, s,
+                     a);
   return hipGetLastError();
 }
 

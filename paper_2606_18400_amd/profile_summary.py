@@ -2,12 +2,17 @@
 
 Usage:
   python -m paper_2606_18400_amd.profile_summary stats <kernel_stats.csv | results.db> [--top N]
+  python -m paper_2606_18400_amd.profile_summary trace <kernel_trace.csv> [--match moe]
   python -m paper_2606_18400_amd.profile_summary pmc <fetch counter_collection.csv> <write counter_collection.csv>
           [--copy-match MulFunctor] [--copy-bytes 1073741824]
 
 `stats` prints, per kernel: dispatch count, average / min / max duration in
 microseconds and total milliseconds, sorted by total time (CSV from
 `--kernel-trace --stats --output-format csv`, or the rocpd SQLite database).
+
+`trace` prints, per (kernel, grid), dispatch count and average duration from
+the per-dispatch CSV of `--kernel-trace` (grid sizes separate the batch sizes
+of one run).
 
 `pmc` reads one `--pmc FETCH_SIZE` and one `--pmc WRITE_SIZE` pass (KiB per
 dispatch) and scales each counter by what it reads for a plain elementwise
@@ -47,6 +52,19 @@ def print_stats(path, top):
         print(f"{n:6d} {avg:10.2f} {mn:10.2f} {mx:10.2f} {tot:10.2f}  {short_name(name)[:120]}")
 
 
+def print_trace(path, match):
+    d = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if match and match not in r["Kernel_Name"]:
+            continue
+        key = (short_name(r["Kernel_Name"]).split("(")[0], int(r["Grid_Size_X"]), int(r["Grid_Size_Y"]))
+        d[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    print(f"{'calls':>6} {'avg_us':>10}  {'grid (threads)':>16}  kernel")
+    for k in sorted(d, key=lambda k: (k[1], k[2], k[0])):
+        v = d[k]
+        print(f"{len(v):6d} {sum(v) / len(v):10.2f}  {k[1]:>9}x{k[2]:<6}  {k[0][:90]}")
+
+
 def counter_means(path):
     d = collections.defaultdict(list)
     for r in csv.DictReader(open(path)):
@@ -81,6 +99,9 @@ def main(argv=None):
     s = sub.add_parser("stats")
     s.add_argument("path")
     s.add_argument("--top", type=int, default=30)
+    t = sub.add_parser("trace")
+    t.add_argument("path")
+    t.add_argument("--match", default="")
     p = sub.add_parser("pmc")
     p.add_argument("fetch_csv")
     p.add_argument("write_csv")
@@ -89,6 +110,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print_stats(a.path, a.top)
+    elif a.cmd == "trace":
+        print_trace(a.path, a.match)
     else:
         print_pmc(a.fetch_csv, a.write_csv, a.copy_match, a.copy_bytes)
 
