@@ -242,6 +242,28 @@ def copy_calibration(nbytes=1 << 30):
     return dict(bytes_read=nbytes, bytes_written=nbytes, ms=ms, gbs=2 * nbytes / ms / 1e6)
 
 
+def vendor_gemv(rows, cols, copies=16, reps=64):
+    """The library GEMV (torch.mv on contiguous BF16 matrices of the SwiGLU
+    kernel's shape) for comparison: `copies` distinct matrices cycled so that no
+    call finds its matrix in the last-level cache; events on the stream."""
+    import torch
+    w = torch.empty((copies, rows, cols), dtype=torch.bfloat16, device="cuda").normal_()
+    x = torch.empty(cols, dtype=torch.bfloat16, device="cuda").normal_()
+    for i in range(copies):
+        torch.mv(w[i], x)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for i in range(reps):
+        torch.mv(w[i % copies], x)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / reps
+    del w
+    torch.cuda.empty_cache()
+    return dict(rows=rows, cols=cols, ms=ms, gbs=(rows * cols + cols + rows) * 2 / ms / 1e6)
+
+
 def cpu_oracle_baseline(cfg, weights, budget_s=12.0):
     """The oracle's FP64 decode step (decode stored weights, then the products)."""
     from oracle import numerics as ON
@@ -592,6 +614,8 @@ def main():
                                      avg_launch_ms=p_kms, native_avg_launch_ms=n_kms))
         log(f"prefill cloaked {fl / p_ms / 1e9:.0f} TFLOP/s native {fl / n_ms / 1e9:.0f} TFLOP/s")
     calib = copy_calibration()
+    vendor = vendor_gemv(2 * f, d)
+    log(f"library GEMV (torch.mv, {2 * f}x{d} bf16): {vendor['gbs']:.0f} GB/s")
     log("timing remap of the whole pool")
     remap = time_remap(cl, args.remap_reps)
     log(f"remap {remap['gbs']:.0f} GB/s vs device copy {remap['memcpy_gbs']:.0f} GB/s")
@@ -671,6 +695,7 @@ def main():
         "vmm_twin": vmm,
         "hardened": hard,
         "copy_calibration": calib,
+        "vendor_gemv": vendor,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "contiguity": C.cloak_query(cl.cw.layout, "CONTIGUITY"),

@@ -405,8 +405,8 @@ uint64_t proj_ws_bytes(const cloak_layout* L, const Proj& p, int64_t M) {
   else if (p.gather && path != kPathGemv)
     b += a256(uint64_t(M) * uint64_t(p.K) * 2);
   if (path == kPathSkinny) {
-    const int64_t lr = launch_rows(L, p, skinny_tile_rows());
-    const SplitPlan sp = plan_split(lr / skinny_tile_rows(), p.K, M);
+    const int64_t lr = launch_rows(L, p, skinny_tile_rows(M));
+    const SplitPlan sp = plan_split(lr / skinny_tile_rows(M), p.K, M);
     b += a256(uint64_t(sp.ksplit) * uint64_t(M) * uint64_t(lr) * 4);
   }
   return b;
@@ -475,7 +475,7 @@ int run_proj(const cloak_layout* L, const void* pool, const Proj& p, const void*
     ldx = p.K;
     wsb += a256(uint64_t(M) * uint64_t(p.K) * 2);
   }
-  const int64_t tile = path == kPathSkinny ? skinny_tile_rows() : gemm_tile_rows();
+  const int64_t tile = path == kPathSkinny ? skinny_tile_rows(M) : gemm_tile_rows();
   SkinnyArgs g{};
   g.pool = static_cast<const uint8_t*>(L->kernel_pool(pool));
   g.phi = L->dev.phi;
@@ -524,6 +524,7 @@ int run_proj(const cloak_layout* L, const void* pool, const Proj& p, const void*
     g.ldp = lr;
     g.ksplit = sp.ksplit;
     g.kblocks_per_split = sp.kb_per;
+    g.tile_rows = int32_t(tile);
     HIP_TRY(launch_skinny(g, L->kernel_translate(), st), fn);
   } else {
     GemmArgs ga{};

@@ -638,10 +638,15 @@ __global__ __launch_bounds__(256) void quant_rows_kernel(const uint16_t* __restr
 // part[slice][token][launch-row]; skinny_reduce_kernel adds the slices in a
 // fixed order (deterministic) and applies the epilogue.  SwiGLU tiles hold
 // 32 gate rows and the same 32 up rows.
-constexpr int SBN = 64, SBK = 64, STHREADS = 256;
-constexpr int S_WTILE = SBN * ROWB;                    // 8 KiB weight tile
+constexpr int SBK = 64, STHREADS = 256;
+// weight rows per tile: 128 for 128-token tiles, which halves the activation
+// bytes staged per weight byte (every row tile stages the whole token tile;
+// measured +5% on the 4096/14336 layer at M=128), else 64 (at 256 tokens
+// 128-row tiles need one wave per SIMD and measured 15% slower)
+template <int SBM>
+constexpr int sbn_for() { return SBM == 128 ? 128 : 64; }
 
-template <int EPI>
+template <int EPI, int SBN>
 __device__ inline bool skinny_row(const SkinnyArgs& a, int tile_n, int tr, int& seg, int& n) {
   if (EPI == kSwiGLU) {
     seg = tr < SBN / 2 ? 0 : 1;
@@ -659,10 +664,12 @@ __device__ inline bool skinny_row(const SkinnyArgs& a, int tile_n, int tr, int& 
 
 // SBM = token tile (16 .. 256): the batch is padded only to SBM.
 template <int SBM>
-constexpr int skinny_lds_bytes() { return 2 * (SBM * ROWB + S_WTILE); }
+constexpr int skinny_lds_bytes() { return 2 * (SBM + sbn_for<SBM>()) * ROWB; }
 
 template <int SBM, bool TR, int EPI, bool F8>
 __global__ __launch_bounds__(STHREADS) void skinny_kernel(const SkinnyArgs a) {
+  constexpr int SBN = sbn_for<SBM>();
+  constexpr int S_WTILE = SBN * ROWB;
   constexpr int XTILE = SBM * ROWB;
   constexpr int XCH = SBM * (ROWB / 16);   // 16-byte chunks of the token tile
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];   // skinny_lds_bytes<SBM>()
@@ -694,7 +701,7 @@ __global__ __launch_bounds__(STHREADS) void skinny_kernel(const SkinnyArgs a) {
   }
   WTile<SBN, STHREADS, F8> wt;
   wt.init(tid, a.pool, a.seg, a.row_bytes,
-          [&](int tr, int& seg, int& n) { return skinny_row<EPI>(a, tile_n, tr, seg, n); });
+          [&](int tr, int& seg, int& n) { return skinny_row<EPI, SBN>(a, tile_n, tr, seg, n); });
   u32x4 gx[XL];
   auto gload = [&](int kb) {
 #pragma unroll
@@ -708,9 +715,9 @@ __global__ __launch_bounds__(STHREADS) void skinny_kernel(const SkinnyArgs a) {
       if (xslot[i]) *reinterpret_cast<u32x4*>(lds_x(buf) + swz(xr[i], ch)) = gx[i];
     wt.store(lds_w(buf));
   };
-  // wave grid: WR waves along the 64 rows x WT along the tokens.  Tiles of
-  // 128+ tokens use 2 x 2 (each wave 32 rows x SBM/2 tokens), which reads
-  // about 40% fewer fragment bytes from LDS per MFMA than 4 x 1.
+  // wave grid: WR waves along the SBN rows x WT along the tokens.  Tiles of
+  // 128+ tokens use 2 x 2 (each wave SBN/2 rows x SBM/2 tokens), which reads
+  // fewer fragment bytes from LDS per MFMA than 4 x 1.
   constexpr int WR = SBM >= 128 ? 2 : 4, WT = 4 / WR;
   constexpr int RB = SBN / WR / 16, TB = SBM / WT / 16;   // 16-blocks per wave
   const int gr = wave % WR, gt = wave / WR;   // this wave's place in the grid
@@ -771,8 +778,9 @@ __global__ __launch_bounds__(256) void skinny_reduce_kernel(const SkinnyArgs a) 
     const int m = int(i / per_tok);
     const int c = int(i % per_tok);
     if constexpr (EPI == kSwiGLU) {
-      const int tile = c / (SBN / 2), j = c % (SBN / 2);
-      const int rg = tile * SBN + j, ru = rg + SBN / 2;
+      const int half = a.tile_rows / 2;
+      const int tile = c / half, j = c % half;
+      const int rg = tile * a.tile_rows + j, ru = rg + half;
       float g = 0.f, u = 0.f;
       for (int ks = 0; ks < a.ksplit; ++ks) {
         const float* p = a.part + (int64_t(ks) * a.M + m) * a.ldp;
@@ -850,7 +858,7 @@ hipError_t launch_gemm(const GemmArgs& a, bool translate, hipStream_t s) {
   return hipGetLastError();
 }
 
-int skinny_tile_rows() { return SBN; }
+int skinny_tile_rows(int64_t M) { return M > 64 && M <= 128 ? sbn_for<128>() : sbn_for<64>(); }
 
 template <int SBM, bool F8>
 void (*skinny_fn2(bool translate, int mode))(const SkinnyArgs) {
@@ -866,7 +874,7 @@ void (*skinny_fn(bool translate, int mode, bool f8))(const SkinnyArgs) {
 hipError_t launch_skinny(const SkinnyArgs& a, bool translate, hipStream_t s) {
   const int64_t blocks = int64_t(a.tiles_n) * a.ksplit;
   if (blocks <= 0 || a.M <= 0) return hipSuccess;
-  if (a.M > kSkinnyMaxTokens || a.K % SBK != 0) return hipErrorInvalidValue;
+  if (a.M > kSkinnyMaxTokens || a.K % SBK != 0 || a.tile_rows != skinny_tile_rows(a.M)) return hipErrorInvalidValue;
   const bool f8 = a.f8 != 0;
   void (*fn)(const SkinnyArgs);
   int lds;

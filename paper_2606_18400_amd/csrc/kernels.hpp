@@ -121,12 +121,15 @@ struct SkinnyArgs {
   const float* sx;
   // split-K
   float* part;              // [ksplit][M][ldp] FP32 partial sums (workspace)
-  int64_t ldp;              // launch-rows (tiles_n * skinny_tile_rows())
+  int64_t ldp;              // launch-rows (tiles_n * tile_rows)
   int32_t ksplit;
   int32_t kblocks_per_split;
+  int32_t tile_rows;        // weight rows per tile: skinny_tile_rows(M)
+  int32_t pad2;
 };
 hipError_t launch_skinny(const SkinnyArgs& a, bool translate, hipStream_t s);
-int skinny_tile_rows();
+// weight rows per skinny tile at M tokens (every tensor starts on a tile)
+int skinny_tile_rows(int64_t M);
 constexpr int64_t kSkinnyMaxTokens = 256;
 hipError_t launch_gather_cols(const uint16_t* x, int64_t ldx, const int32_t* perm, uint16_t* out, int64_t M,
                               int64_t K, hipStream_t s);
