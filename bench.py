@@ -439,6 +439,42 @@ def bench_stack(args):
             ms = a.elapsed_time(b) / reps
             res[name][str(M)] = dict(ms=ms, gbs=step_bytes(M) / ms / 1e6)
             log(f"{name} M={M}: {ms:.2f} ms/step, {step_bytes(M) / ms / 1e6:.0f} GB/s")
+        pm = args.prefill_tokens
+        if pm > 0:
+            # prefill of one FP8 layer (FP8 x FP8 MFMA on per-token E4M3 activations), cycling layers
+            x = torch.from_numpy(synth.activations(pm, d, "bf16").view(np.int16)).cuda().view(torch.bfloat16)
+            qkv = torch.empty((pm, d + 2 * kv), dtype=torch.bfloat16, device="cuda")
+            o = torch.empty((pm, d), dtype=torch.bfloat16, device="cuda")
+            h = torch.empty((pm, f), dtype=torch.bfloat16, device="cuda")
+            y = torch.empty((pm, d), dtype=torch.bfloat16, device="cuda")
+            need = max(C.cloak_linear_fused_ws_bytes(cw.layout, [0, 1, 2], pm),
+                       C.cloak_ws_bytes(cw.layout, C.CLOAK_OP_LINEAR, 3, pm),
+                       C.cloak_ws_bytes(cw.layout, C.CLOAK_OP_SWIGLU, 0, pm),
+                       C.cloak_ws_bytes(cw.layout, C.CLOAK_OP_DOWN, 0, pm))
+            ws = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+
+            def prefill_layer(l):
+                t0 = TENSORS_PER_LAYER * l
+                C.cloak_linear_fused(cw.layout, cw.pool, [t0, t0 + 1, t0 + 2], x, pm, qkv, ws, ws.numel())
+                C.cloak_linear(cw.layout, cw.pool, t0 + 3, x, pm, o, ws, ws.numel())
+                C.cloak_swiglu(cw.layout, cw.pool, l, x, pm, h, ws, ws.numel())
+                C.cloak_down(cw.layout, cw.pool, l, h, pm, y, ws, ws.numel())
+
+            prefill_layer(0)
+            torch.cuda.synchronize()
+            reps = 8
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for i in range(reps):
+                prefill_layer(1 + i)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            fl = 2 * pm * (d * d * 2 + 2 * kv * d + 3 * f * d)
+            res[name]["prefill"] = dict(tokens=pm, ms=ms, tflops=fl / ms / 1e9, peak_fp8_tflops=5000.0,
+                                        frac=fl / ms / 1e9 / 5000.0)
+            log(f"{name} FP8 prefill {pm} tokens: {ms:.2f} ms per layer, {fl / ms / 1e9:.0f} TFLOP/s")
+            del x, qkv, o, h, y, ws
         cw.close()
         torch.cuda.empty_cache()
     for M in res["cloaked"]:
