@@ -42,7 +42,7 @@ HERE = ROOT
 # (FETCH_SIZE and WRITE_SIZE, one rocprofv3 --pmc pass each, scaled by what the
 # same counters read for an elementwise copy of known size), valid for the
 # kernel sources with this digest; None until counters are taken.
-SWIGLU_COUNTERS = dict(sources="31cc860053579513", fetch_bytes=235087634, write_bytes=114731)
+SWIGLU_COUNTERS = dict(sources="bcd8a915472fdc31", fetch_bytes=235094491, write_bytes=114727)
 
 
 def log(msg):
@@ -240,6 +240,30 @@ def copy_calibration(nbytes=1 << 30):
     ms = start.elapsed_time(stop)
     del src, dst
     return dict(bytes_read=nbytes, bytes_written=nbytes, ms=ms, gbs=2 * nbytes / ms / 1e6)
+
+
+def read_ceiling(nbytes, copies=16, reps=64):
+    """Plain streaming-read rate (cloak_stream_read) over `copies` distinct
+    regions of nbytes, cycled so that no launch finds its bytes in the
+    last-level cache: the practical ceiling of a kernel that reads nbytes."""
+    import torch
+    from paper_2606_18400_amd import cloak as C
+    nbytes = nbytes // 256 * 256
+    buf = torch.ones(copies * nbytes, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for i in range(copies):
+        C.cloak_stream_read(buf[i * nbytes:], nbytes, out)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for i in range(reps):
+        C.cloak_stream_read(buf[(i % copies) * nbytes:], nbytes, out)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / reps
+    del buf
+    torch.cuda.empty_cache()
+    return dict(bytes=nbytes, ms=ms, gbs=nbytes / ms / 1e6)
 
 
 def vendor_gemv(rows, cols, copies=16, reps=64):
@@ -652,6 +676,8 @@ def main():
     calib = copy_calibration()
     vendor = vendor_gemv(2 * f, d)
     log(f"library GEMV (torch.mv, {2 * f}x{d} bf16): {vendor['gbs']:.0f} GB/s")
+    ceiling = read_ceiling(swiglu_bytes)
+    log(f"streaming read of {swiglu_bytes} B regions: {ceiling['gbs']:.0f} GB/s")
     log("timing remap of the whole pool")
     remap = time_remap(cl, args.remap_reps)
     log(f"remap {remap['gbs']:.0f} GB/s vs device copy {remap['memcpy_gbs']:.0f} GB/s")
@@ -710,7 +736,8 @@ def main():
     roofline = dict(kernel="gemv_kernel SwiGLU (gate+up, bf16, M=1)", bound="hbm", achieved=achieved,
                     peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=traffic,
                     bytes_per_launch=swiglu_bytes, avg_launch_ms=k_ms, native_avg_launch_ms=k_ms_nat,
-                    kernel_sources=digest)
+                    kernel_sources=digest, read_ceiling_gbs=ceiling["gbs"],
+                    frac_of_read_ceiling=achieved / ceiling["gbs"])
 
     cpu = None
     if not args.no_cpu:

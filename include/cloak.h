@@ -305,6 +305,14 @@ int cloak_swiglu(const cloak_layout* layout, const void* d_pool, int32_t layer, 
 int cloak_down(const cloak_layout* layout, const void* d_pool, int32_t layer, const void* d_h,
                int64_t M, void* d_y, void* d_ws, uint64_t ws_bytes, void* stream);
 
+/* Bandwidth calibration (not part of the cloaked path): stream every byte of
+ * d_src once with non-temporal 16-byte loads, as the weight-reading kernels
+ * do, and fold them into one word that is written to *d_out only when it
+ * equals a constant.  Gives the device's plain streaming-read rate, the
+ * practical ceiling the decode kernels are compared with.  bytes: multiple of
+ * 16; d_src 16-byte aligned.  Asynchronous on `stream`. */
+int cloak_stream_read(const void* d_src, uint64_t bytes, uint32_t* d_out, void* stream);
+
 /* Mixture-of-experts layer over cloaked experts (the paper serves a Qwen 3
  * MoE model, Section 5; experts are ordinary cloaked tensors: each expert e is
  * the FFN group of layer first_layer + e, with its own hidden permutation and

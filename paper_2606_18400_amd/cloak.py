@@ -96,6 +96,7 @@ _SIGS = {
     "cloak_down": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _u64, _vp], _i32),
     "cloak_quantize_fp8": ([_vp, _i64, _i64, _i64, _vp, _vp, _vp], _i32),
     "cloak_moe_ws_bytes": ([_vp, _i32, _i32, _i32, _i64], _u64),
+    "cloak_stream_read": ([_vp, _u64, _vp, _vp], _i32),
     "cloak_moe": ([_vp, _vp, _i32, _i32, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _u64, _vp], _i32),
     "cloak_remap": ([_vp, _vp, _u64, _vp], _i32),
     "cloak_remap_host": ([_vp, _vp, _u64, _u64], _i32),
@@ -297,6 +298,10 @@ def cloak_down(layout, pool, layer, h, M, y, ws=None, ws_bytes=0, stream=None):
 
 def cloak_remap(layout, pool, remap_seed, stream=None):
     _check(_lib.cloak_remap(layout, _ptr(pool), remap_seed & ((1 << 64) - 1), _stream(stream)), "cloak_remap")
+
+
+def cloak_stream_read(src, nbytes, out, stream=None):
+    _check(_lib.cloak_stream_read(_ptr(src), nbytes, _ptr(out), _stream(stream)), "cloak_stream_read")
 
 
 def cloak_moe_ws_bytes(layout, first_layer, n_experts, top_k, M):

@@ -885,6 +885,16 @@ extern "C" int cloak_moe(const cloak_layout* L, const void* d_pool, int32_t firs
   return CLOAK_OK;
 }
 
+extern "C" int cloak_stream_read(const void* d_src, uint64_t bytes, uint32_t* d_out, void* stream) {
+  clear_error();
+  if (!d_src || !d_out || bytes % 16 != 0 || reinterpret_cast<uintptr_t>(d_src) % 16 != 0 || bytes > uint64_t(INT64_MAX)) {
+    set_error("cloak_stream_read: need a 16-byte aligned buffer of a multiple of 16 bytes and an output word");
+    return CLOAK_EINVAL;
+  }
+  HIP_TRY(launch_stream_read(d_src, int64_t(bytes), d_out, static_cast<hipStream_t>(stream)), "cloak_stream_read");
+  return CLOAK_OK;
+}
+
 extern "C" int cloak_quantize_fp8(const void* d_x, int64_t M, int64_t K, int64_t ldx, void* d_q, void* d_s,
                                   void* stream) {
   using namespace cloak;

@@ -281,5 +281,6 @@ struct DecoyArgs {
   int32_t dtype;            // CLOAK_F32 / CLOAK_BF16 / CLOAK_FP8_E4M3
 };
 hipError_t launch_decoy(const DecoyArgs& a, hipStream_t s);
+hipError_t launch_stream_read(const void* src, int64_t bytes, uint32_t* out, hipStream_t s);
 
 }  // namespace cloak

@@ -865,3 +865,15 @@ def test_prefill_full_layer4096_sampled_tokens(C):
     assert err <= 1e-2, err
     cw.close()
     torch.cuda.empty_cache()
+
+
+def test_stream_read_calibration_runs_and_checks_arguments(C):
+    import torch
+    buf = torch.ones(1 << 20, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(1, dtype=torch.int32, device="cuda")
+    C.cloak_stream_read(buf, buf.numel(), out)
+    torch.cuda.synchronize()
+    assert int(out.item()) == 0          # the fold of all-ones words is not the sentinel
+    for nbytes, off in [(1000, 0), ((1 << 20) - 16, 8)]:   # not a multiple of 16; misaligned
+        with pytest.raises(C.CloakError):
+            C.cloak_stream_read(buf[off:], nbytes, out)
