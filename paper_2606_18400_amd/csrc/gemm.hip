@@ -826,6 +826,20 @@ hipError_t launch_quant_rows(const uint16_t* x, int64_t ldx, const int32_t* perm
   return hipGetLastError();
 }
 
+// Dynamic LDS above the default limit is allowed per kernel and device:
+// raised once for each (device, kernel) pair, thread-safely.
+static hipError_t raise_lds_limit(const void* fn, int lds) {
+  static std::mutex mu;
+  static std::set<std::pair<int, const void*>> raised;
+  int dev = 0;
+  if (hipError_t e = hipGetDevice(&dev)) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  if (raised.count({dev, fn})) return hipSuccess;
+  if (hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds)) return e;
+  raised.insert({dev, fn});
+  return hipSuccess;
+}
+
 hipError_t launch_gemm(const GemmArgs& a, bool translate, hipStream_t s) {
   const int ntiles = a.tiles_m * a.tiles_n;
   if (ntiles <= 0) return hipSuccess;
@@ -846,14 +860,7 @@ hipError_t launch_gemm(const GemmArgs& a, bool translate, hipStream_t s) {
                    : (sw ? gemm_dma_kernel<false, kSwiGLU, DWAVES> : gemm_dma_kernel<false, kStore, DWAVES>);
   const int threads = f8 ? NTHREADS : 64 * DWAVES;
 
-  static bool attr_set[16] = {};
-  const int key = (translate ? 2 : 0) + (sw ? 1 : 0) + (f8 ? 4 : 0) + (a8 ? 8 : 0);
-  if (!attr_set[key]) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       int(lds));
-    if (e != hipSuccess) return e;
-    attr_set[key] = true;
-  }
+  if (hipError_t e = raise_lds_limit(reinterpret_cast<const void*>(fn), int(lds))) return e;
   hipLaunchKernelGGL(fn, dim3(blocks), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
@@ -883,18 +890,8 @@ hipError_t launch_skinny(const SkinnyArgs& a, bool translate, hipStream_t s) {
   else if (a.M <= 64) fn = skinny_fn<64>(translate, a.mode, f8), lds = skinny_lds_bytes<64>();
   else if (a.M <= 128) fn = skinny_fn<128>(translate, a.mode, f8), lds = skinny_lds_bytes<128>();
   else fn = skinny_fn<256>(translate, a.mode, f8), lds = skinny_lds_bytes<256>();
-  if (lds > 64 * 1024) {
-    // above the default dynamic LDS limit: raise it once per kernel
-    static std::mutex mu;
-    static std::set<void*> raised;
-    std::lock_guard<std::mutex> lock(mu);
-    if (!raised.count(reinterpret_cast<void*>(fn))) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-      if (e != hipSuccess) return e;
-      raised.insert(reinterpret_cast<void*>(fn));
-    }
-  }
+  if (lds > 64 * 1024)
+    if (hipError_t e = raise_lds_limit(reinterpret_cast<const void*>(fn), lds)) return e;
   hipLaunchKernelGGL(fn, dim3(unsigned(blocks)), dim3(STHREADS), size_t(lds), s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

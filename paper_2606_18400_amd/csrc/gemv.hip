@@ -27,6 +27,7 @@
 
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <utility>
 
 #include "kernels.hpp"
@@ -447,13 +448,13 @@ KernelFn pick_wide(int wt, int tr, int epi) {
 
 int resident_blocks(KernelFn fn, int threads) {
   static std::mutex mu;
-  static std::map<std::pair<void*, int>, int> cache;
-  std::lock_guard<std::mutex> lock(mu);
-  auto key = std::make_pair(reinterpret_cast<void*>(fn), threads);
-  auto it = cache.find(key);
-  if (it != cache.end()) return it->second;
+  static std::map<std::tuple<int, void*, int>, int> cache;   // (device, kernel, threads)
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> lock(mu);
+  const auto key = std::make_tuple(dev, reinterpret_cast<void*>(fn), threads);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), threads, 0) !=
       hipSuccess)
