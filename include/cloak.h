@@ -323,8 +323,10 @@ int cloak_stream_read(const void* d_src, uint64_t bytes, uint32_t* d_out, void* 
  * d_weights f32 [M][top_k] on the device (routing is the caller's).  Experts
  * are BF16 or FP8 (per-row scales) with one d_model and d_ffn.  The hidden
  * activations are rounded to bf16, the weighted expert outputs kept in f32 and
- * added per token in slot order.  M * top_k <= 4096; x 16-byte, y 8-byte and
- * the workspace 256-byte aligned.  Workspace: cloak_moe_ws_bytes.  Errors: EINVAL (experts missing or inconsistent, sizes,
+ * added per token in slot order.  Calls of more than 4096 (token, slot) pairs
+ * run in consecutive chunks of floor(4096 / top_k) tokens on one workspace;
+ * top_k <= 4096.  x 16-byte, y 8-byte and the workspace 256-byte aligned.
+ * Workspace: cloak_moe_ws_bytes.  Errors: EINVAL (experts missing or inconsistent, sizes,
  * workspace). */
 uint64_t cloak_moe_ws_bytes(const cloak_layout* layout, int32_t first_layer, int32_t n_experts, int32_t top_k,
                             int64_t M);

@@ -828,7 +828,10 @@ extern "C" uint64_t cloak_moe_ws_bytes(const cloak_layout* L, int32_t first_laye
   int32_t dt = 0;
   int64_t dm = 0, dff = 0;
   if (moe_experts(L, first_layer, n_experts, dt, dm, dff, "cloak_moe_ws_bytes") < 0) return UINT64_MAX;
-  const uint64_t n = uint64_t(M) * uint64_t(top_k);
+  if (top_k > kMoeMaxPairs) return UINT64_MAX;
+  // calls above kMoeMaxPairs pairs run in token chunks that reuse one chunk's workspace
+  const int64_t chunk = kMoeMaxPairs / top_k;
+  const uint64_t n = uint64_t(M < chunk ? M : chunk) * uint64_t(top_k);
   return a256((1 + 3 * uint64_t(n_experts) + n) * 4) + a256(n * uint64_t(dff) * 2) + a256(n * uint64_t(dm) * 4);
 }
 
@@ -842,8 +845,8 @@ extern "C" int cloak_moe(const cloak_layout* L, const void* d_pool, int32_t firs
   int64_t dm = 0, dff = 0;
   const int64_t pos = moe_experts(L, first_layer, n_experts, dt, dm, dff, "cloak_moe");
   if (pos < 0) return CLOAK_EINVAL;
-  if (top_k < 1 || M < 0 || M * top_k > kMoeMaxPairs) {
-    set_error("cloak_moe: need top_k >= 1 and M * top_k <= %lld", (long long)kMoeMaxPairs);
+  if (top_k < 1 || top_k > kMoeMaxPairs || M < 0 || M > INT32_MAX) {
+    set_error("cloak_moe: need 1 <= top_k <= %lld and 0 <= M", (long long)kMoeMaxPairs);
     return CLOAK_EINVAL;
   }
   if (M == 0) return CLOAK_OK;
@@ -869,19 +872,24 @@ extern "C" int cloak_moe(const cloak_layout* L, const void* d_pool, int32_t firs
   a.scales = L->dev.scales;
   a.E = n_experts;
   a.topk = top_k;
-  a.M = int32_t(M);
+  const int64_t chunk = kMoeMaxPairs / top_k;
   a.d_model = int32_t(dm);
   a.d_ffn = int32_t(dff);
-  a.x = static_cast<const uint16_t*>(d_x);
-  a.ids = d_ids;
-  a.wts = d_weights;
   a.route = reinterpret_cast<int32_t*>(w);
   w += a256((1 + 3 * uint64_t(n_experts) + n) * 4);
   a.h = reinterpret_cast<uint16_t*>(w);
   w += a256(n * uint64_t(dff) * 2);
   a.yp = reinterpret_cast<float*>(w);
-  a.y = static_cast<uint16_t*>(d_y);
-  HIP_TRY(launch_moe(a, L->kernel_translate(), static_cast<hipStream_t>(stream)), "cloak_moe");
+  // token chunks of at most kMoeMaxPairs pairs, in order, on one workspace
+  for (int64_t m0 = 0; m0 < M; m0 += chunk) {
+    const int64_t mc = M - m0 < chunk ? M - m0 : chunk;
+    a.M = int32_t(mc);
+    a.x = static_cast<const uint16_t*>(d_x) + m0 * dm;
+    a.ids = d_ids + m0 * top_k;
+    a.wts = d_weights + m0 * top_k;
+    a.y = static_cast<uint16_t*>(d_y) + m0 * dm;
+    HIP_TRY(launch_moe(a, L->kernel_translate(), static_cast<hipStream_t>(stream)), "cloak_moe");
+  }
   return CLOAK_OK;
 }
 

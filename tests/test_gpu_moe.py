@@ -88,6 +88,22 @@ def ON_err(y, ref):
     return ON.normwise_err(values_f64(y), ref)
 
 
+def test_moe_large_call_runs_in_chunks(C):
+    # 600 tokens x top-8 = 4800 pairs: two chunks of 512 and 88 tokens on one workspace
+    E, d, F, k, M = 8, 272, 208, 8, 600
+    shapes = expert_shapes(E, d, F, "bf16", first=0)
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, 1024, 1024 * 4096, seed=67)
+    cw.load(ws, scs)
+    assert C.cloak_moe_ws_bytes(cw.layout, 0, E, k, M) == C.cloak_moe_ws_bytes(cw.layout, 0, E, k, 512)
+    x = synth.activations(M, d, "bf16", seed=3)
+    ids, w = routing(M, k, E, seed=4)
+    y = run_moe(C, cw, 0, E, k, x, ids, w)
+    ref = expected(shapes, ws, scs, 0, E, x, ids, w)
+    assert ON_err(y, ref) <= TOL["bf16"]
+    cw.close()
+
+
 def test_moe_masked_map_and_remap_bit_identical(C):
     E, d, F, k, M = 6, 256, 512, 2, 9
     shapes = expert_shapes(E, d, F, "bf16", first=0)
@@ -126,7 +142,7 @@ def test_moe_argument_errors(C):
     with pytest.raises(C.CloakError):
         C.cloak_moe(L, cw.pool, 0, 4, 2, x, 4, ids, w, y, buf, need - 1)
     with pytest.raises(C.CloakError):
-        C.cloak_moe(L, cw.pool, 0, 4, 1025, x, 4, ids, w, y, buf, need)
+        C.cloak_moe(L, cw.pool, 0, 4, 4097, x, 4, ids, w, y, buf, need)
     C.cloak_moe(L, cw.pool, 0, 4, 2, x, 0, ids, w, y, buf, need)   # M = 0: no-op
     cw.close()
 
