@@ -820,6 +820,10 @@ int64_t moe_experts(const cloak_layout* L, int32_t first, int32_t E, int32_t& dt
 }
 
 constexpr int64_t kMoeMaxPairs = 4096;
+
+// ints of the routing workspace for n pairs over E experts: counts and runs,
+// the sorted pairs, and the MFMA path's token-tile list
+uint64_t moe_route_ints(uint64_t n, uint64_t E) { return 1 + 3 * E + n + 1 + 2 * uint64_t(moe_max_tiles(int64_t(n), int64_t(E))); }
 }  // namespace
 
 extern "C" uint64_t cloak_moe_ws_bytes(const cloak_layout* L, int32_t first_layer, int32_t n_experts, int32_t top_k,
@@ -832,7 +836,7 @@ extern "C" uint64_t cloak_moe_ws_bytes(const cloak_layout* L, int32_t first_laye
   // calls above kMoeMaxPairs pairs run in token chunks that reuse one chunk's workspace
   const int64_t chunk = kMoeMaxPairs / top_k;
   const uint64_t n = uint64_t(M < chunk ? M : chunk) * uint64_t(top_k);
-  return a256((1 + 3 * uint64_t(n_experts) + n) * 4) + a256(n * uint64_t(dff) * 2) + a256(n * uint64_t(dm) * 4);
+  return a256(moe_route_ints(n, uint64_t(n_experts)) * 4) + a256(n * uint64_t(dff) * 2) + a256(n * uint64_t(dm) * 4);
 }
 
 extern "C" int cloak_moe(const cloak_layout* L, const void* d_pool, int32_t first_layer, int32_t n_experts,
@@ -860,7 +864,9 @@ extern "C" int cloak_moe(const cloak_layout* L, const void* d_pool, int32_t firs
     set_error("cloak_moe: x must be 16-byte, y 8-byte and the workspace 256-byte aligned");
     return CLOAK_EINVAL;
   }
-  const uint64_t n = uint64_t(M) * uint64_t(top_k);
+  // the workspace holds one chunk: its regions are sized for the largest chunk's pairs
+  const int64_t chunk = kMoeMaxPairs / top_k;
+  const uint64_t n = uint64_t(M < chunk ? M : chunk) * uint64_t(top_k);
   uint8_t* w = static_cast<uint8_t*>(d_ws);
   MoeArgs a{};
   a.pool = static_cast<const uint8_t*>(L->kernel_pool(d_pool));
@@ -872,11 +878,10 @@ extern "C" int cloak_moe(const cloak_layout* L, const void* d_pool, int32_t firs
   a.scales = L->dev.scales;
   a.E = n_experts;
   a.topk = top_k;
-  const int64_t chunk = kMoeMaxPairs / top_k;
   a.d_model = int32_t(dm);
   a.d_ffn = int32_t(dff);
   a.route = reinterpret_cast<int32_t*>(w);
-  w += a256((1 + 3 * uint64_t(n_experts) + n) * 4);
+  w += a256(moe_route_ints(n, uint64_t(n_experts)) * 4);
   a.h = reinterpret_cast<uint16_t*>(w);
   w += a256(n * uint64_t(dff) * 2);
   a.yp = reinterpret_cast<float*>(w);

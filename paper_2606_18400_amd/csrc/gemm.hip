@@ -807,9 +807,194 @@ __global__ __launch_bounds__(256) void skinny_reduce_kernel(const SkinnyArgs a) 
   }
 }
 
+// ---------------------------------------------------------------------------
+// MoE experts on MFMA, for calls whose active experts average 2+ tokens.  The
+// tile list (moe_tiles_kernel) names, per token tile, the active-expert slot
+// and the tile's first token; a workgroup takes one token tile (up to
+// MOE_TM of that expert's (token, slot) pairs, gathered row by row) by one
+// 64-row weight tile over the whole K, with the skinny kernel's double-
+// buffered loaders (page-translated weight rows cached per lane, FP8 rows
+// widened exactly), and writes the results directly: SwiGLU tiles hold 32
+// gate and the same 32 up rows, paired through LDS after the K loop; down
+// tiles scale each result by the slot's router weight.
+constexpr int MOE_TM = 32;     // tokens per tile
+constexpr int MOE_TN = 64;     // weight rows per tile
+
+__global__ __launch_bounds__(1024) void moe_tiles_kernel(const MoeArgs a) {
+  __shared__ int32_t scan[1024];
+  const int n = a.M * a.topk;
+  const int na = a.route[0];
+  const int32_t* act_count = a.route + 1 + 2 * a.E;
+  int32_t* tiles = a.route + 1 + 3 * a.E + n;   // [0] count, then (slot, first token) pairs
+  const int t = threadIdx.x;
+  int own = 0;
+  for (int s = t; s < na; s += blockDim.x) own += (act_count[s] + MOE_TM - 1) / MOE_TM;
+  scan[t] = own;
+  __syncthreads();
+  for (int off = 1; off < int(blockDim.x); off <<= 1) {
+    const int v = t >= off ? scan[t - off] : 0;
+    __syncthreads();
+    scan[t] += v;
+    __syncthreads();
+  }
+  int pos = scan[t] - own;
+  for (int s = t; s < na; s += blockDim.x)
+    for (int tok0 = 0; tok0 < act_count[s]; tok0 += MOE_TM) {
+      tiles[1 + 2 * pos] = s;
+      tiles[2 + 2 * pos] = tok0;
+      ++pos;
+    }
+  if (t == int(blockDim.x) - 1) tiles[0] = scan[t];
+}
+
+template <int EPI, bool TR, bool F8>
+__global__ __launch_bounds__(STHREADS) void moe_mfma_kernel(const MoeArgs a) {
+  constexpr int XTILE = MOE_TM * ROWB, WTILE = MOE_TN * ROWB;
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];   // 2 * (XTILE + WTILE)
+  auto lds_x = [&](int buf) { return smem + buf * (XTILE + WTILE); };
+  auto lds_w = [&](int buf) { return smem + buf * (XTILE + WTILE) + XTILE; };
+  const int n = a.M * a.topk;
+  const int32_t* tiles = a.route + 1 + 3 * a.E + n;
+  const int tile = blockIdx.x;
+  if (tile >= tiles[0]) return;
+  const int s = tiles[1 + 2 * tile], tok0 = tiles[2 + 2 * tile];
+  const int e = a.route[1 + s], st = a.route[1 + a.E + s], cnt = a.route[1 + 2 * a.E + s];
+  const int ntok = cnt - tok0 < MOE_TM ? cnt - tok0 : MOE_TM;
+  const int32_t* ent = a.route + 1 + 3 * a.E + st + tok0;
+  const MoeExpert& ex = a.experts[e];
+  const int tile_n = blockIdx.y;
+  const int K = EPI == kSwiGLU ? a.d_model : a.d_ffn;
+  const int64_t row_bytes = int64_t(K) * (F8 ? 1 : 2);
+  const int rows = EPI == kSwiGLU ? a.d_ffn : a.d_model;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int ch = tid & 7;
+  // token rows: MOE_TM rows x 8 chunks of 16 B = one chunk per thread
+  static_assert(MOE_TM * 8 == STHREADS, "one activation chunk per thread");
+  const int xr = tid >> 3;
+  const bool xok = xr < ntok;
+  const int pair = xok ? ent[xr] : 0;
+  const uint16_t* xrow = (EPI == kSwiGLU ? a.x + int64_t(pair / a.topk) * a.d_model
+                                         : a.h + int64_t(pair) * a.d_ffn) + ch * 8;
+  WSeg segs[2] = {};
+  segs[0].vbase = EPI == kSwiGLU ? ex.vbase[0] : ex.vbase[2];
+  segs[1].vbase = ex.vbase[1];
+  WTile<MOE_TN, STHREADS, F8> wt;
+  wt.init(tid, a.pool, segs, row_bytes, [&](int tr, int& seg, int& nn) {
+    if (EPI == kSwiGLU) {
+      seg = tr < MOE_TN / 2 ? 0 : 1;
+      nn = tile_n * (MOE_TN / 2) + tr % (MOE_TN / 2);
+    } else {
+      seg = 0;
+      nn = tile_n * MOE_TN + tr;
+    }
+    return nn < rows;
+  });
+  u32x4 gx;
+  auto gload = [&](int kb) {
+    gx = xok ? *reinterpret_cast<const u32x4*>(xrow + kb * SBK) : u32x4{0u, 0u, 0u, 0u};
+    wt.template load<TR>(a.phi, a.phi_key, a.log2_page, kb);
+  };
+  auto swrite = [&](int buf) {
+    *reinterpret_cast<u32x4*>(lds_x(buf) + swz(xr, ch)) = gx;
+    wt.store(lds_w(buf));
+  };
+  // 4 waves along the 64 rows, each 16 rows x all MOE_TM tokens
+  constexpr int TB = MOE_TM / 16;
+  f32x4 acc[TB];
+#pragma unroll
+  for (int j = 0; j < TB; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int wrow = wave * 16;
+  const int nk = K / SBK;
+  gload(0);
+  swrite(0);
+  __syncthreads();
+  for (int kb = 0; kb < nk; ++kb) {
+    const int buf = kb & 1;
+    if (kb + 1 < nk) gload(kb + 1);
+#pragma unroll
+    for (int q = 0; q < SBK / 32; ++q) {
+      const int chunk = q * 4 + (lane >> 4);
+      const bf16x8_t fa = *reinterpret_cast<const bf16x8_t*>(lds_w(buf) + swz(wrow + (lane & 15), chunk));
+#pragma unroll
+      for (int j = 0; j < TB; ++j) {
+        const bf16x8_t fb = *reinterpret_cast<const bf16x8_t*>(lds_x(buf) + swz(j * 16 + (lane & 15), chunk));
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[j], 0, 0, 0);
+      }
+    }
+    if (kb + 1 < nk) swrite(buf ^ 1);
+    __syncthreads();
+  }
+  // lane holds tile rows wrow + 4*(lane/16) + r of token j*16 + lane%16
+  const int r4 = wrow + 4 * (lane >> 4);
+  if constexpr (EPI == kSwiGLU) {
+    float* red = reinterpret_cast<float*>(smem);   // [MOE_TN][MOE_TM]; every buffer is free after the loop
+#pragma unroll
+    for (int j = 0; j < TB; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[(r4 + r) * MOE_TM + j * 16 + (lane & 15)] = acc[j][r];
+    __syncthreads();
+    for (int i = tid; i < (MOE_TN / 2) * MOE_TM; i += STHREADS) {
+      const int u = i / MOE_TM, m = i % MOE_TM;
+      const int unit = tile_n * (MOE_TN / 2) + u;
+      if (m >= ntok || unit >= a.d_ffn) continue;
+      float g = red[u * MOE_TM + m], v = red[(u + MOE_TN / 2) * MOE_TM + m];
+      if (ex.scale_off[0] >= 0) g *= a.scales[ex.scale_off[0] + unit];
+      if (ex.scale_off[1] >= 0) v *= a.scales[ex.scale_off[1] + unit];
+      a.h[int64_t(ent[m]) * a.d_ffn + unit] = f32_to_bf16_rne(g / (1.0f + expf(-g)) * v);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < TB; ++j) {
+      const int m = j * 16 + (lane & 15);
+      if (m >= ntok) continue;
+      const int p = ent[m];
+      const float wgt = a.wts[p];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int nrow = tile_n * MOE_TN + r4 + r;
+        if (nrow >= a.d_model) continue;
+        float v = acc[j][r];
+        if (ex.scale_off[2] >= 0) v *= a.scales[ex.scale_off[2] + nrow];
+        a.yp[int64_t(p) * a.d_model + nrow] = v * wgt;
+      }
+    }
+  }
+}
+
 }  // namespace
 
 int gemm_lds_bytes() { return 4 * TILE_BYTES; }
+
+hipError_t launch_moe_mfma(const MoeArgs& a, bool translate, hipStream_t s) {
+  const int n = a.M * a.topk;
+  if (n <= 0) return hipSuccess;
+  if (a.d_model % SBK != 0 || a.d_ffn % SBK != 0) return hipErrorInvalidValue;
+  const bool f8 = a.wtype == kFP8;
+  using Fn = void (*)(const MoeArgs);
+  Fn sw, dn;
+  if (f8) {
+    sw = translate ? moe_mfma_kernel<kSwiGLU, true, true> : moe_mfma_kernel<kSwiGLU, false, true>;
+    dn = translate ? moe_mfma_kernel<kStore, true, true> : moe_mfma_kernel<kStore, false, true>;
+  } else {
+    sw = translate ? moe_mfma_kernel<kSwiGLU, true, false> : moe_mfma_kernel<kSwiGLU, false, false>;
+    dn = translate ? moe_mfma_kernel<kStore, true, false> : moe_mfma_kernel<kStore, false, false>;
+  }
+  const unsigned max_tiles = unsigned(moe_max_tiles(n, a.E));
+  const size_t lds = size_t(2) * (MOE_TM + MOE_TN) * ROWB;
+  hipLaunchKernelGGL(moe_tiles_kernel, dim3(1), dim3(1024), 0, s, a);
+  hipLaunchKernelGGL(sw, dim3(max_tiles, unsigned((a.d_ffn + MOE_TN / 2 - 1) / (MOE_TN / 2))), dim3(STHREADS), lds, s,
+                     a);
+  hipLaunchKernelGGL(dn, dim3(max_tiles, unsigned((a.d_model + MOE_TN - 1) / MOE_TN)), dim3(STHREADS), lds, s, a);
+  return hipGetLastError();
+}
+
+int64_t moe_max_tiles(int64_t pairs, int64_t experts) {
+  const int64_t slots = pairs < experts ? pairs : experts;
+  return (pairs + MOE_TM - 1) / MOE_TM + slots;
+}
 int gemm_tile_rows() { return BN; }
 int gemm_k_step() { return BK; }
 int gemm_k_step_a8() { return 2 * BK; }

@@ -269,6 +269,11 @@ struct MoeArgs {
   uint16_t* y;               // [M][d_model] bf16
 };
 hipError_t launch_moe(const MoeArgs& a, bool translate, hipStream_t s);
+// The expert SwiGLU and down products on MFMA (gemm.hip), after the route kernel:
+// for calls whose active experts average 2+ tokens; d_model and d_ffn multiples of 64.
+hipError_t launch_moe_mfma(const MoeArgs& a, bool translate, hipStream_t s);
+// token tiles the MFMA path may need for `pairs` (token, slot) pairs over `experts`
+int64_t moe_max_tiles(int64_t pairs, int64_t experts);
 
 // Decoy contents of the free virtual pages [V, V + nfree) (definition in include/cloak.h).
 struct DecoyArgs {

@@ -46,11 +46,14 @@ def run_moe(C, cw, first, E, k, x_np, ids, w):
     M = x_np.shape[0]
     L = cw.layout
     need = C.cloak_moe_ws_bytes(L, first, E, k, M)
-    ws = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+    # a canary past the workspace the library asked for: it must stay untouched
+    ws = torch.empty(need + 4096, dtype=torch.uint8, device="cuda")
+    ws[need:] = 0xA5
     y = torch.empty((M, x_np.shape[1]), dtype=torch.bfloat16, device="cuda")
     d_ids = torch.from_numpy(ids).cuda()
     d_w = torch.from_numpy(w).cuda()
     C.cloak_moe(L, cw.pool, first, E, k, to_device_x(x_np), M, d_ids, d_w, y, ws, need)
+    assert bool((ws[need:] == 0xA5).all()), "cloak_moe wrote past its workspace"
     return from_device(y)
 
 
@@ -86,6 +89,25 @@ def test_moe_vs_fp64(C, dtype, M, k):
 def ON_err(y, ref):
     from oracle import numerics as ON
     return ON.normwise_err(values_f64(y), ref)
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+@pytest.mark.parametrize("geom", [(8, 256, 320, 64, 2), (4, 512, 192, 100, 3), (16, 128, 128, 300, 4)])
+def test_moe_mfma_tiles_vs_fp64(C, dtype, geom):
+    # experts averaging 8+ tokens run on the MFMA token tiles (d_model, d_ffn
+    # multiples of 64); 1 KiB pages; ragged last tiles; skipped slots
+    E, d, F, M, k = geom
+    shapes = expert_shapes(E, d, F, dtype, first=2)
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, 1024, 1024 * 4096, seed=69)
+    cw.load(ws, scs)
+    x = synth.activations(M, d, "bf16", seed=M + 1)
+    ids, w = routing(M, k, E, seed=M + 2)
+    assert (M * k + E - 1) // E >= 2
+    y = run_moe(C, cw, 2, E, k, x, ids, w)
+    ref = expected(shapes, ws, scs, 2, E, x, ids, w)
+    assert ON_err(y, ref) <= TOL[dtype]
+    cw.close()
 
 
 def test_moe_large_call_runs_in_chunks(C):
@@ -149,14 +171,15 @@ def test_moe_argument_errors(C):
 
 def test_moe_qwen3_expert_shapes_sampled(C):
     # 128 experts of 2048 -> 768 -> 2048 (a Qwen-3-30B-A3B-like MoE layer), top-8,
-    # 2 MiB pages; decode batches of 1 and 64 tokens, 6 tokens checked in FP64
+    # 2 MiB pages; batches of 1, 64 and 256 tokens (the last on the MFMA tiles),
+    # 3 tokens each checked in FP64
     E, d, F, k = 128, 2048, 768, 8
     shapes = expert_shapes(E, d, F, "bf16", first=0)
     one = [synth.weight(t, s[2], s[3], "bf16")[0] for t, s in enumerate(shapes[:3 * 8])]
     ws = [one[t % len(one)] for t in range(len(shapes))]     # 8 distinct experts reused
     cw = C.CloakedWeights(shapes, 2 << 20, 2 << 30, seed=65)
     cw.load(ws)
-    for M in (1, 64):
+    for M in (1, 64, 256):
         x = synth.activations(M, d, "bf16", seed=M)
         ids, w = routing(M, k, E, seed=M, invalid=False)
         y = run_moe(C, cw, 0, E, k, x, ids, w)
