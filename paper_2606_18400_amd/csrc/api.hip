@@ -154,15 +154,20 @@ void fill_common(const cloak_layout* L, const void* pool, GemvArgs& a, int64_t K
 
 }  // namespace
 
-extern "C" int cloak_layout_to_device(cloak_layout* L, void* stream) {
-  clear_error();
-  if (!L) {
-    set_error("cloak_layout_to_device: null layout");
-    return CLOAK_EINVAL;
-  }
-  if (L->dev.phi) return CLOAK_OK;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  DeviceTables d;
+namespace {
+// Every device table of a layout; on failure whatever was allocated is freed.
+void free_tables(DeviceTables& d) {
+  if (d.phi) (void)hipFree(d.phi);
+  if (d.perms) (void)hipFree(d.perms);
+  if (d.scales) (void)hipFree(d.scales);
+  if (d.remap_pairs) (void)hipFree(d.remap_pairs);
+  if (d.experts) (void)hipFree(d.experts);
+  if (d.h_stage) (void)hipHostFree(d.h_stage);
+  if (d.stage_event) (void)hipEventDestroy(static_cast<hipEvent_t>(d.stage_event));
+  d = DeviceTables{};
+}
+
+int build_tables(cloak_layout* L, DeviceTables& d, hipStream_t st) {
   HIP_TRY(hipGetDevice(&d.device), "hipGetDevice");
   const size_t P = size_t(L->P);
   HIP_TRY(hipMalloc(&d.phi, P * 4), "hipMalloc(page map)");
@@ -198,6 +203,22 @@ extern "C" int cloak_layout_to_device(cloak_layout* L, void* stream) {
   HIP_TRY(hipMemcpyAsync(d.perms, perms.data(), perms.size() * 4, hipMemcpyHostToDevice, st), "upload permutations");
   HIP_TRY(hipMemsetAsync(d.scales, 0, size_t(L->n_scales > 0 ? L->n_scales : 1) * 4, st), "clear scales");
   HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+  return CLOAK_OK;
+}
+}  // namespace
+
+extern "C" int cloak_layout_to_device(cloak_layout* L, void* stream) {
+  clear_error();
+  if (!L) {
+    set_error("cloak_layout_to_device: null layout");
+    return CLOAK_EINVAL;
+  }
+  if (L->dev.phi) return CLOAK_OK;
+  DeviceTables d;
+  if (int rc = build_tables(L, d, static_cast<hipStream_t>(stream))) {
+    free_tables(d);
+    return rc;
+  }
   L->dev = d;
   return CLOAK_OK;
 }
@@ -207,15 +228,7 @@ extern "C" int cloak_layout_free(cloak_layout* L) {
   if (!L) return CLOAK_OK;
   if (L->vmm.active) (void)cloak_vmm_pool_free(L);
   drop_ring(L);
-  if (L->dev.phi) {
-    (void)hipFree(L->dev.phi);
-    (void)hipFree(L->dev.perms);
-    (void)hipFree(L->dev.scales);
-    (void)hipFree(L->dev.remap_pairs);
-    (void)hipFree(L->dev.experts);
-    (void)hipHostFree(L->dev.h_stage);
-    (void)hipEventDestroy(static_cast<hipEvent_t>(L->dev.stage_event));
-  }
+  free_tables(L->dev);
   delete L;
   return CLOAK_OK;
 }
