@@ -599,6 +599,27 @@ __global__ __launch_bounds__(kMoeRouteThreads) void moe_route_kernel(const MoeAr
   if (t == 0) a.route[0] = na;
 }
 
+// Active slot s of a call: its expert, first sorted entry and pair count.
+// Single-token calls skip routing: slot j is pair j of expert ids[j] (a slot
+// naming no expert returns false and is skipped).
+__device__ inline bool moe_slot(const MoeArgs& a, int s, int& e, int& st, int& cnt) {
+  if (a.direct) {
+    if (s >= a.topk) return false;
+    e = a.ids[s];
+    st = s;
+    cnt = 1;
+    return e >= 0 && e < a.E;
+  }
+  if (s >= a.route[0]) return false;
+  e = a.route[1 + s];
+  st = a.route[1 + a.E + s];
+  cnt = a.route[1 + 2 * a.E + s];
+  return true;
+}
+
+// Pair of sorted entry i (the identity in single-token calls).
+__device__ inline int moe_entry(const MoeArgs& a, int i) { return a.direct ? i : a.route[1 + 3 * a.E + i]; }
+
 // This lane's 16 B of chunk c of row `row` of a tensor (zero past the row).
 template <int TR>
 __device__ inline u32x4 moe_load(const MoeArgs& a, int64_t vbase, int64_t npages, int64_t row, int64_t row_bytes,
@@ -676,14 +697,12 @@ __global__ __launch_bounds__(kMoeWaves * 64) void moe_swiglu_kernel(const MoeArg
   constexpr int NR = 2 * kMoeUnits;
   constexpr int V = NR * MT;
   constexpr int STRIDE = 64 / V;   // value j of the reduction sits in lane j * STRIDE; up values 32 lanes on
-  const int s = blockIdx.x;
-  if (s >= a.route[0]) return;
+  int e, st, cnt;
+  if (!moe_slot(a, blockIdx.x, e, st, cnt)) return;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int unit0 = (int(blockIdx.y) * kMoeWaves + wave) * kMoeUnits;
   if (unit0 >= a.d_ffn) return;
-  const int e = a.route[1 + s], st = a.route[1 + a.E + s], cnt = a.route[1 + 2 * a.E + s];
-  const int32_t* ent = a.route + 1 + 3 * a.E;
   const MoeExpert ex = a.experts[e];
   const int64_t row_bytes = int64_t(a.d_model) * (WT == kFP8 ? 1 : 2);
   int ti[NR], rr[NR];
@@ -698,7 +717,7 @@ __global__ __launch_bounds__(kMoeWaves * 64) void moe_swiglu_kernel(const MoeArg
     int pair[MT], xrow[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
-      pair[m] = t0 + m < cnt ? ent[st + t0 + m] : -1;
+      pair[m] = t0 + m < cnt ? moe_entry(a, st + t0 + m) : -1;
       xrow[m] = pair[m] < 0 ? -1 : pair[m] / a.topk;
     }
     float v[V];
@@ -726,14 +745,12 @@ __global__ __launch_bounds__(kMoeWaves * 64) void moe_down_kernel(const MoeArgs 
   constexpr int NR = kMoeDownRows;
   constexpr int V = NR * MT;
   constexpr int STRIDE = 64 / V;
-  const int s = blockIdx.x;
-  if (s >= a.route[0]) return;
+  int e, st, cnt;
+  if (!moe_slot(a, blockIdx.x, e, st, cnt)) return;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int row0 = (int(blockIdx.y) * kMoeWaves + wave) * kMoeDownRows;
   if (row0 >= a.d_model) return;
-  const int e = a.route[1 + s], st = a.route[1 + a.E + s], cnt = a.route[1 + 2 * a.E + s];
-  const int32_t* ent = a.route + 1 + 3 * a.E;
   const MoeExpert ex = a.experts[e];
   const int64_t row_bytes = int64_t(a.d_ffn) * (WT == kFP8 ? 1 : 2);
   int ti[NR], rr[NR];
@@ -747,7 +764,7 @@ __global__ __launch_bounds__(kMoeWaves * 64) void moe_down_kernel(const MoeArgs 
   for (int t0 = 0; t0 < cnt; t0 += MT) {
     int pair[MT];
 #pragma unroll
-    for (int m = 0; m < MT; ++m) pair[m] = t0 + m < cnt ? ent[st + t0 + m] : -1;
+    for (int m = 0; m < MT; ++m) pair[m] = t0 + m < cnt ? moe_entry(a, st + t0 + m) : -1;
     float v[V];
 #pragma unroll
     for (int j = 0; j < V; ++j) v[j] = 0.f;
@@ -874,6 +891,19 @@ hipError_t launch_moe(const MoeArgs& a, bool translate, hipStream_t s) {
   while (n2 < n) n2 <<= 1;
   const unsigned slots = unsigned(n < a.E ? n : a.E);
   const size_t route_lds = size_t(n2 + kMoeRouteThreads + slots) * 4;
+  if (a.M == 1 && a.topk <= 64) {
+    // one token: each slot is its own expert pass, no routing kernel (results are the same:
+    // a one-token pass does not depend on where its pair sits in a sorted list)
+    MoeArgs d = a;
+    d.direct = 1;
+    const unsigned per_sw = kMoeWaves * kMoeUnits, per_dn = kMoeWaves * kMoeDownRows;
+    hipLaunchKernelGGL(sw, dim3(unsigned(a.topk), unsigned((a.d_ffn + per_sw - 1) / per_sw)), dim3(kMoeWaves * 64),
+                       0, s, d);
+    hipLaunchKernelGGL(dn, dim3(unsigned(a.topk), unsigned((a.d_model + per_dn - 1) / per_dn)),
+                       dim3(kMoeWaves * 64), 0, s, d);
+    hipLaunchKernelGGL(moe_combine_kernel, dim3(1u, unsigned((a.d_model + 1023) / 1024)), dim3(256), 0, s, d);
+    return hipGetLastError();
+  }
   if (n <= 64)
     hipLaunchKernelGGL(moe_route_wave_kernel, dim3(1), dim3(64), 0, s, a);
   else

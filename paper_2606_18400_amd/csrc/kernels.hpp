@@ -259,7 +259,7 @@ struct MoeArgs {
   const float* scales;       // device scale table
   int32_t E, topk, M;
   int32_t d_model, d_ffn;
-  int32_t pad;
+  int32_t direct;            // one token: slot j is pair j of expert ids[j], no routing pass
   const uint16_t* x;         // [M][d_model] bf16
   const int32_t* ids;        // [M][topk] expert of each slot (outside [0, E): slot skipped)
   const float* wts;          // [M][topk] router weights

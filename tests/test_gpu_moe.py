@@ -86,6 +86,35 @@ def test_moe_vs_fp64(C, dtype, M, k):
     cw.close()
 
 
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_moe_single_token_slots(C, dtype):
+    # One token skips the routing pass (each slot is its own expert pass).  Slots
+    # repeat experts and name none; 64 slots is the largest such call, and the
+    # same call with a 65th, empty slot goes through routing: bit-identical.
+    E, d, F = 8, 272, 208
+    shapes = expert_shapes(E, d, F, dtype)
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, 1024, 1024 * 4096, seed=67)
+    cw.load(ws, scs)
+    x = synth.activations(1, d, "bf16", seed=5)
+    rng = np.random.Generator(np.random.PCG64(9))
+    for k in (1, 3, 64):
+        ids = rng.integers(0, E, (1, k)).astype(np.int32)
+        if k > 1:
+            ids[0, 1] = ids[0, 0]
+        if k > 2:
+            ids[0, 2] = -1 if k == 3 else E
+        w = rng.random((1, k)).astype(np.float32)
+        y = run_moe(C, cw, 0, E, k, x, ids, w)
+        err = ON_err(y, expected(shapes, ws, scs, 0, E, x, ids, w))
+        assert err <= TOL[dtype], (k, err)
+    ids65 = np.concatenate([ids, np.full((1, 1), -1, np.int32)], axis=1)
+    w65 = np.concatenate([w, np.ones((1, 1), np.float32)], axis=1)
+    y65 = run_moe(C, cw, 0, E, 65, x, ids65, w65)
+    assert np.array_equal(y65.view(np.uint16), y.view(np.uint16))
+    cw.close()
+
+
 def ON_err(y, ref):
     from oracle import numerics as ON
     return ON.normwise_err(values_f64(y), ref)
