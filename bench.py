@@ -612,8 +612,8 @@ def main():
     ap.add_argument("--stack-batches", default="1,8,32,64,256", help="stack: decode batch sizes")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the cloaked layer needs no "
-              "cross-GPU exchange, see the sharding notes in DESIGN.md", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the multi-GPU (tensor-parallel) "
+              "path is not built; each GPU would hold its own cloaked shard with its own seed", file=sys.stderr)
         sys.exit(2)
 
     import torch

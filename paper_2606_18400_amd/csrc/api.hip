@@ -369,11 +369,14 @@ struct SplitPlan {
 
 // K slices per skinny row tile: about 1024 workgroups in total (512 above
 // 64 tokens, where each slice's FP32 partial sums cost more traffic), but no
-// slice shorter than 8 K steps.
+// slice shorter than 8 K steps.  Above 128 tokens a workgroup holds 96 KiB of
+// LDS, one per CU: as many slices as keep the launch within one pass over
+// MI355X's 256 CUs (one slice when the row tiles alone exceed them).
+constexpr int64_t kSkinnyWideSlots = 256;
 SplitPlan plan_split(int64_t tiles_n, int64_t K, int64_t M) {
   const int64_t nk = K / gemm_k_step();
   const int64_t target = M > 64 ? 512 : 1024;
-  int64_t ks = (target + tiles_n - 1) / tiles_n;
+  int64_t ks = M > 128 ? kSkinnyWideSlots / tiles_n : (target + tiles_n - 1) / tiles_n;
   const int64_t cap = nk / 8 > 1 ? nk / 8 : 1;
   if (ks > cap) ks = cap;
   if (ks < 1) ks = 1;

@@ -639,12 +639,14 @@ __global__ __launch_bounds__(256) void quant_rows_kernel(const uint16_t* __restr
 // fixed order (deterministic) and applies the epilogue.  SwiGLU tiles hold
 // 32 gate rows and the same 32 up rows.
 constexpr int SBK = 64, STHREADS = 256;
-// weight rows per tile: 128 for 128-token tiles, which halves the activation
+// weight rows per tile: 128 from 128-token tiles, which halves the activation
 // bytes staged per weight byte (every row tile stages the whole token tile;
-// measured +5% on the 4096/14336 layer at M=128), else 64 (at 256 tokens
-// 128-row tiles need one wave per SIMD and measured 15% slower)
+// measured +5% on the 4096/14336 layer at M=128), else 64.  256-token tiles
+// run 8 waves (two per SIMD) so that each wave still owns a 64 x 64 block.
 template <int SBM>
-constexpr int sbn_for() { return SBM == 128 ? 128 : 64; }
+constexpr int sbn_for() { return SBM >= 128 ? 128 : 64; }
+template <int SBM>
+constexpr int snt_for() { return SBM == 256 ? 512 : STHREADS; }
 
 template <int EPI, int SBN>
 __device__ inline bool skinny_row(const SkinnyArgs& a, int tile_n, int tr, int& seg, int& n) {
@@ -667,8 +669,9 @@ template <int SBM>
 constexpr int skinny_lds_bytes() { return 2 * (SBM + sbn_for<SBM>()) * ROWB; }
 
 template <int SBM, bool TR, int EPI, bool F8>
-__global__ __launch_bounds__(STHREADS) void skinny_kernel(const SkinnyArgs a) {
+__global__ __launch_bounds__(snt_for<SBM>()) void skinny_kernel(const SkinnyArgs a) {
   constexpr int SBN = sbn_for<SBM>();
+  constexpr int NT = snt_for<SBM>();
   constexpr int S_WTILE = SBN * ROWB;
   constexpr int XTILE = SBM * ROWB;
   constexpr int XCH = SBM * (ROWB / 16);   // 16-byte chunks of the token tile
@@ -686,20 +689,20 @@ __global__ __launch_bounds__(STHREADS) void skinny_kernel(const SkinnyArgs a) {
   const int wave = tid >> 6;
   const int ch = tid & 7;
 
-  // token tile: XCH 16-byte chunks, chunk idx = tid + STHREADS*i -> row idx/8, chunk idx%8
-  constexpr int XL = (XCH + STHREADS - 1) / STHREADS;
+  // token tile: XCH 16-byte chunks, chunk idx = tid + NT*i -> row idx/8, chunk idx%8
+  constexpr int XL = (XCH + NT - 1) / NT;
   bool xslot[XL], xok[XL];
   int xr[XL];
   const uint16_t* xrow[XL];
 #pragma unroll
   for (int i = 0; i < XL; ++i) {
-    const int idx = tid + STHREADS * i;
+    const int idx = tid + NT * i;
     xslot[i] = idx < XCH;
     xr[i] = idx >> 3;
     xok[i] = xslot[i] && xr[i] < a.M;
     xrow[i] = a.x + int64_t(xok[i] ? xr[i] : 0) * a.ldx + ch * 8;
   }
-  WTile<SBN, STHREADS, F8> wt;
+  WTile<SBN, NT, F8> wt;
   wt.init(tid, a.pool, a.seg, a.row_bytes,
           [&](int tr, int& seg, int& n) { return skinny_row<EPI, SBN>(a, tile_n, tr, seg, n); });
   u32x4 gx[XL];
@@ -716,9 +719,10 @@ __global__ __launch_bounds__(STHREADS) void skinny_kernel(const SkinnyArgs a) {
     wt.store(lds_w(buf));
   };
   // wave grid: WR waves along the SBN rows x WT along the tokens.  Tiles of
-  // 128+ tokens use 2 x 2 (each wave SBN/2 rows x SBM/2 tokens), which reads
-  // fewer fragment bytes from LDS per MFMA than 4 x 1.
-  constexpr int WR = SBM >= 128 ? 2 : 4, WT = 4 / WR;
+  // 128+ tokens use 2 x (waves / 2) (each wave 64 rows x 64 tokens), which
+  // reads fewer fragment bytes from LDS per MFMA than 4 x 1.
+  constexpr int NW = NT / 64;
+  constexpr int WR = SBM >= 128 ? 2 : 4, WT = NW / WR;
   constexpr int RB = SBN / WR / 16, TB = SBM / WT / 16;   // 16-blocks per wave
   const int gr = wave % WR, gt = wave / WR;   // this wave's place in the grid
   f32x4 acc[RB][TB];
@@ -1050,7 +1054,7 @@ hipError_t launch_gemm(const GemmArgs& a, bool translate, hipStream_t s) {
   return hipGetLastError();
 }
 
-int skinny_tile_rows(int64_t M) { return M > 64 && M <= 128 ? sbn_for<128>() : sbn_for<64>(); }
+int skinny_tile_rows(int64_t M) { return M > 64 ? sbn_for<128>() : sbn_for<64>(); }
 
 template <int SBM, bool F8>
 void (*skinny_fn2(bool translate, int mode))(const SkinnyArgs) {
@@ -1077,7 +1081,8 @@ hipError_t launch_skinny(const SkinnyArgs& a, bool translate, hipStream_t s) {
   else fn = skinny_fn<256>(translate, a.mode, f8), lds = skinny_lds_bytes<256>();
   if (lds > 64 * 1024)
     if (hipError_t e = raise_lds_limit(reinterpret_cast<const void*>(fn), lds)) return e;
-  hipLaunchKernelGGL(fn, dim3(unsigned(blocks)), dim3(STHREADS), size_t(lds), s, a);
+  hipLaunchKernelGGL(fn, dim3(unsigned(blocks)), dim3(unsigned(a.M > 128 ? snt_for<256>() : STHREADS)), size_t(lds),
+                     s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t per_tok = a.mode == kSwiGLU ? int64_t(a.seg[0].rows) : int64_t(a.ldp);
