@@ -691,6 +691,21 @@ def test_fp8_mfma_paths_vs_fp64(C, M):
     cw.close()
 
 
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+@pytest.mark.parametrize("M", [129, 256])
+def test_skinny_256_token_tile_ragged(C, dtype, M):
+    # 129..256 tokens: the 8-wave tile over 128 weight rows (64 hidden units
+    # of SwiGLU per tile).  d_ffn 2848 leaves the last SwiGLU tile half full
+    # (and sends the down projection, K = 2848, to the GEMV); 129 tokens pad
+    # 127 of the 256 token rows.
+    shapes = decoder_shapes(1024, 2848, 256, dtype, layers=1, extra=[(-1, "head", 1000, 1024, dtype)])
+    ws, scs = make_weights(shapes)
+    cw = C.CloakedWeights(shapes, 65536, 65536 * 512, seed=31)
+    cw.load(ws, scs)
+    check_linear_all(C, cw, shapes, ws, scs, M)
+    cw.close()
+
+
 def one_hot_expected_a8(shapes, ws, scs, t, ks):
     """x = e_k through FP8 x FP8: the row quantises to code 448 with scale
     fl(1/448); the kernel forms ((448 q_w) * s_x) * s_w in binary32."""
