@@ -772,6 +772,127 @@ __global__ __launch_bounds__(snt_for<SBM>()) void skinny_kernel(const SkinnyArgs
   }
 }
 
+// BF16 weights at 129..256 tokens: the 8-wave 256 x 128 tile with direct
+// global -> LDS loads.  One such workgroup fills a CU, so with register
+// staging every K step waits out a full memory round trip; here
+// global_load_lds_dwordx4 writes each lane's 16 bytes straight into a ring of
+// SDS_STAGES LDS stages (48 KiB each: 256 token rows and 128 weight rows of
+// one K step), issued SDS_STAGES - 1 steps ahead.  A wave load fills 8 tile
+// rows in lane order, so the XOR swizzle of the fragment reads is applied on
+// the global side: the lane filling slot s of tile row r fetches chunk
+// s ^ (r & 7).  Padding tokens read token 0 and padding rows read row 0
+// (valid memory; their results are never stored).
+constexpr int SDS_STAGES = 3;
+constexpr int SDS_STAGE_BYTES = (256 + 128) * ROWB;
+
+template <bool TR, int EPI>
+__global__ __launch_bounds__(512) void skinny_dma_kernel(const SkinnyArgs a) {
+  constexpr int SBM = 256, SBN = 128, NW = 8;
+  constexpr int XT = SBM * ROWB;
+  constexpr int XLD = SBM / 8 / NW, WLD = SBN / 8 / NW;   // wave loads per stage: 4 token, 2 weight
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];   // SDS_STAGES * SDS_STAGE_BYTES
+  const int ks = blockIdx.x % a.ksplit;
+  const int tile_n = blockIdx.x / a.ksplit;
+  const int kb_begin = ks * a.kblocks_per_split;
+  int kb_end = kb_begin + a.kblocks_per_split;
+  if (kb_end > a.K / SBK) kb_end = a.K / SBK;
+  const int nloc = kb_end - kb_begin;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+  const uint8_t* xptr[XLD];
+#pragma unroll
+  for (int j = 0; j < XLD; ++j) {
+    const int r = 8 * (XLD * wave + j) + (lane >> 3);
+    const int c = (lane & 7) ^ (r & 7);
+    xptr[j] = reinterpret_cast<const uint8_t*>(a.x) + int64_t(r < a.M ? r : 0) * a.ldx * 2 + c * 16;
+  }
+  RowRef wr[WLD];
+#pragma unroll
+  for (int j = 0; j < WLD; ++j) {
+    const int tr = 8 * (WLD * wave + j) + (lane >> 3);
+    const int c = (lane & 7) ^ (tr & 7);
+    int seg = 0, n = 0;
+    const bool ok = skinny_row<EPI, SBN>(a, tile_n, tr, seg, n);
+    wr[j].pool = a.pool;
+    wr[j].vbase = a.seg[seg].vbase;
+    wr[j].rowoff = int64_t(ok ? n : 0) * a.row_bytes + c * 16;
+    wr[j].cvp = -1;
+    wr[j].cbase = 0;
+    wr[j].ok = true;
+  }
+  // 2 x 4 wave grid, each wave 64 weight rows x 64 tokens
+  constexpr int WR = 2, RB = SBN / WR / 16, TB = SBM / (NW / WR) / 16;
+  const int gr = wave % WR, gt = wave / WR;
+  const int wrow = gr * (SBN / WR);
+  f32x4 acc[RB][TB];
+#pragma unroll
+  for (int b = 0; b < RB; ++b)
+#pragma unroll
+    for (int j = 0; j < TB; ++j) acc[b][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // iterations i < 0 only issue the first SDS_STAGES - 1 steps
+  for (int i = 1 - SDS_STAGES; i < nloc; ++i) {
+    if (i >= 0) {
+      // this lane's loads of step i are done once only step i + 1's remain;
+      // the barrier then publishes every lane's step i and frees the buffer
+      // that step i + SDS_STAGES - 1 is loaded into
+      if (i + 1 < nloc)
+        wait_vm_lgkm0<XLD + WLD>();
+      else
+        wait_vm_lgkm0<0>();
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+    }
+    const int in = i + SDS_STAGES - 1;
+    if (in < nloc) {
+      uint8_t* base = smem + (in % SDS_STAGES) * SDS_STAGE_BYTES;
+      const int64_t koff = int64_t(kb_begin + in) * ROWB;
+#pragma unroll
+      for (int j = 0; j < XLD; ++j) {
+        const uint8_t* xsrc = xptr[j] + koff;
+        __builtin_amdgcn_global_load_lds(xsrc, base + 8 * (XLD * wave + j) * ROWB, 16, 0, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < WLD; ++j) {
+        const uint8_t* wsrc = row_addr<TR>(a.phi, a.phi_key, a.log2_page, wr[j], koff);
+        __builtin_amdgcn_global_load_lds(wsrc, base + XT + 8 * (WLD * wave + j) * ROWB, 16, 0, 0);
+      }
+    }
+    if (i < 0) continue;
+    const uint8_t* xs = smem + (i % SDS_STAGES) * SDS_STAGE_BYTES;
+    const uint8_t* wsm = xs + XT;
+#pragma unroll
+    for (int s = 0; s < SBK / 32; ++s) {
+      const int chunk = s * 4 + (lane >> 4);
+      bf16x8_t fa[RB];
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+        fa[b] = *reinterpret_cast<const bf16x8_t*>(wsm + swz(wrow + b * 16 + (lane & 15), chunk));
+#pragma unroll
+      for (int j = 0; j < TB; ++j) {
+        const int mb = gt * TB + j;
+        const bf16x8_t fb = *reinterpret_cast<const bf16x8_t*>(xs + swz(mb * 16 + (lane & 15), chunk));
+#pragma unroll
+        for (int b = 0; b < RB; ++b) acc[b][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[b], fb, acc[b][j], 0, 0, 0);
+      }
+    }
+    asm volatile("" ::: "memory");
+  }
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    const int row0 = tile_n * SBN + wrow + b * 16 + 4 * (lane >> 4);
+#pragma unroll
+    for (int j = 0; j < TB; ++j) {
+      const int m = (gt * TB + j) * 16 + (lane & 15);
+      if (m >= a.M) continue;
+      float* dst = a.part + (int64_t(ks) * a.M + m) * a.ldp + row0;
+      *reinterpret_cast<f32x4*>(dst) = acc[b][j];
+    }
+  }
+}
+
 // Sum of the K slices in slice order, then the epilogue.  STORE: one thread
 // per (token, launch-row); SwiGLU: one thread per (token, hidden unit).
 template <int EPI>
@@ -1062,6 +1183,12 @@ void (*skinny_fn2(bool translate, int mode))(const SkinnyArgs) {
   return translate ? skinny_kernel<SBM, true, kStore, F8> : skinny_kernel<SBM, false, kStore, F8>;
 }
 
+template <int UNUSED = 0>
+void (*skinny_dma_fn(bool translate, int mode))(const SkinnyArgs) {
+  if (mode == kSwiGLU) return translate ? skinny_dma_kernel<true, kSwiGLU> : skinny_dma_kernel<false, kSwiGLU>;
+  return translate ? skinny_dma_kernel<true, kStore> : skinny_dma_kernel<false, kStore>;
+}
+
 template <int SBM>
 void (*skinny_fn(bool translate, int mode, bool f8))(const SkinnyArgs) {
   return f8 ? skinny_fn2<SBM, true>(translate, mode) : skinny_fn2<SBM, false>(translate, mode);
@@ -1078,7 +1205,8 @@ hipError_t launch_skinny(const SkinnyArgs& a, bool translate, hipStream_t s) {
   else if (a.M <= 32) fn = skinny_fn<32>(translate, a.mode, f8), lds = skinny_lds_bytes<32>();
   else if (a.M <= 64) fn = skinny_fn<64>(translate, a.mode, f8), lds = skinny_lds_bytes<64>();
   else if (a.M <= 128) fn = skinny_fn<128>(translate, a.mode, f8), lds = skinny_lds_bytes<128>();
-  else fn = skinny_fn<256>(translate, a.mode, f8), lds = skinny_lds_bytes<256>();
+  else if (f8) fn = skinny_fn<256>(translate, a.mode, f8), lds = skinny_lds_bytes<256>();
+  else fn = skinny_dma_fn(translate, a.mode), lds = SDS_STAGES * SDS_STAGE_BYTES;
   if (lds > 64 * 1024)
     if (hipError_t e = raise_lds_limit(reinterpret_cast<const void*>(fn), lds)) return e;
   hipLaunchKernelGGL(fn, dim3(unsigned(blocks)), dim3(unsigned(a.M > 128 ? snt_for<256>() : STHREADS)), size_t(lds),
