@@ -772,25 +772,29 @@ __global__ __launch_bounds__(snt_for<SBM>()) void skinny_kernel(const SkinnyArgs
   }
 }
 
-// BF16 weights at 129..256 tokens: the 8-wave 256 x 128 tile with direct
-// global -> LDS loads.  One such workgroup fills a CU, so with register
-// staging every K step waits out a full memory round trip; here
-// global_load_lds_dwordx4 writes each lane's 16 bytes straight into a ring of
-// SDS_STAGES LDS stages (48 KiB each: 256 token rows and 128 weight rows of
-// one K step), issued SDS_STAGES - 1 steps ahead.  A wave load fills 8 tile
+// BF16 weights at 65..256 tokens: 8-wave tiles of 128 or 256 tokens x 128
+// weight rows with direct global -> LDS loads.  One such workgroup fills a
+// CU, so with register staging every K step would wait out a full memory
+// round trip; here global_load_lds_dwordx4 writes each lane's 16 bytes
+// straight into a ring of LDS stages (one K step of the token and weight
+// tiles each: 4 x 32 KiB for 128 tokens, 3 x 48 KiB for 256), issued
+// stages - 1 steps ahead.  A wave load fills 8 tile
 // rows in lane order, so the XOR swizzle of the fragment reads is applied on
 // the global side: the lane filling slot s of tile row r fetches chunk
 // s ^ (r & 7).  Padding tokens read token 0 and padding rows read row 0
 // (valid memory; their results are never stored).
-constexpr int SDS_STAGES = 3;
-constexpr int SDS_STAGE_BYTES = (256 + 128) * ROWB;
+template <int SBM>
+constexpr int sds_stages() { return SBM == 256 ? 3 : 4; }
+template <int SBM>
+constexpr int sds_stage_bytes() { return (SBM + 128) * ROWB; }
 
-template <bool TR, int EPI>
+template <int SBM, bool TR, int EPI>
 __global__ __launch_bounds__(512) void skinny_dma_kernel(const SkinnyArgs a) {
-  constexpr int SBM = 256, SBN = 128, NW = 8;
+  constexpr int SBN = 128, NW = 8;
+  constexpr int SDS_STAGES = sds_stages<SBM>(), SDS_STAGE_BYTES = sds_stage_bytes<SBM>();
   constexpr int XT = SBM * ROWB;
   constexpr int XLD = SBM / 8 / NW, WLD = SBN / 8 / NW;   // wave loads per stage: 4 token, 2 weight
-  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];   // SDS_STAGES * SDS_STAGE_BYTES
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];   // sds_stages * sds_stage_bytes
   const int ks = blockIdx.x % a.ksplit;
   const int tile_n = blockIdx.x / a.ksplit;
   const int kb_begin = ks * a.kblocks_per_split;
@@ -835,10 +839,13 @@ __global__ __launch_bounds__(512) void skinny_dma_kernel(const SkinnyArgs a) {
   // iterations i < 0 only issue the first SDS_STAGES - 1 steps
   for (int i = 1 - SDS_STAGES; i < nloc; ++i) {
     if (i >= 0) {
-      // this lane's loads of step i are done once only step i + 1's remain;
-      // the barrier then publishes every lane's step i and frees the buffer
-      // that step i + SDS_STAGES - 1 is loaded into
-      if (i + 1 < nloc)
+      // this lane's loads of step i are done once only the younger steps'
+      // remain (up to stages - 2 of them); the barrier then publishes every
+      // lane's step i and frees the buffer step i + stages - 1 is loaded into
+      static_assert(SDS_STAGES <= 4, "wait chain covers two younger steps");
+      if (SDS_STAGES == 4 && i + 2 < nloc)
+        wait_vm_lgkm0<2 * (XLD + WLD)>();
+      else if (i + 1 < nloc)
         wait_vm_lgkm0<XLD + WLD>();
       else
         wait_vm_lgkm0<0>();
@@ -1183,10 +1190,11 @@ void (*skinny_fn2(bool translate, int mode))(const SkinnyArgs) {
   return translate ? skinny_kernel<SBM, true, kStore, F8> : skinny_kernel<SBM, false, kStore, F8>;
 }
 
-template <int UNUSED = 0>
+template <int SBM>
 void (*skinny_dma_fn(bool translate, int mode))(const SkinnyArgs) {
-  if (mode == kSwiGLU) return translate ? skinny_dma_kernel<true, kSwiGLU> : skinny_dma_kernel<false, kSwiGLU>;
-  return translate ? skinny_dma_kernel<true, kStore> : skinny_dma_kernel<false, kStore>;
+  if (mode == kSwiGLU)
+    return translate ? skinny_dma_kernel<SBM, true, kSwiGLU> : skinny_dma_kernel<SBM, false, kSwiGLU>;
+  return translate ? skinny_dma_kernel<SBM, true, kStore> : skinny_dma_kernel<SBM, false, kStore>;
 }
 
 template <int SBM>
@@ -1204,13 +1212,14 @@ hipError_t launch_skinny(const SkinnyArgs& a, bool translate, hipStream_t s) {
   if (a.M <= 16) fn = skinny_fn<16>(translate, a.mode, f8), lds = skinny_lds_bytes<16>();
   else if (a.M <= 32) fn = skinny_fn<32>(translate, a.mode, f8), lds = skinny_lds_bytes<32>();
   else if (a.M <= 64) fn = skinny_fn<64>(translate, a.mode, f8), lds = skinny_lds_bytes<64>();
-  else if (a.M <= 128) fn = skinny_fn<128>(translate, a.mode, f8), lds = skinny_lds_bytes<128>();
+  else if (f8 && a.M <= 128) fn = skinny_fn<128>(translate, a.mode, f8), lds = skinny_lds_bytes<128>();
   else if (f8) fn = skinny_fn<256>(translate, a.mode, f8), lds = skinny_lds_bytes<256>();
-  else fn = skinny_dma_fn(translate, a.mode), lds = SDS_STAGES * SDS_STAGE_BYTES;
+  else if (a.M <= 128) fn = skinny_dma_fn<128>(translate, a.mode), lds = sds_stages<128>() * sds_stage_bytes<128>();
+  else fn = skinny_dma_fn<256>(translate, a.mode), lds = sds_stages<256>() * sds_stage_bytes<256>();
+  const bool wide = a.M > 128 || (a.M > 64 && !f8);   // 8-wave tiles
   if (lds > 64 * 1024)
     if (hipError_t e = raise_lds_limit(reinterpret_cast<const void*>(fn), lds)) return e;
-  hipLaunchKernelGGL(fn, dim3(unsigned(blocks)), dim3(unsigned(a.M > 128 ? snt_for<256>() : STHREADS)), size_t(lds),
-                     s, a);
+  hipLaunchKernelGGL(fn, dim3(unsigned(blocks)), dim3(unsigned(wide ? 512 : STHREADS)), size_t(lds), s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t per_tok = a.mode == kSwiGLU ? int64_t(a.seg[0].rows) : int64_t(a.ldp);
