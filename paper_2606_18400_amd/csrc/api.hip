@@ -369,14 +369,16 @@ struct SplitPlan {
 
 // K slices per skinny row tile: about 1024 workgroups in total (512 above
 // 64 tokens, where each slice's FP32 partial sums cost more traffic), but no
-// slice shorter than 8 K steps.  Above 128 tokens a workgroup holds 96 KiB of
-// LDS, one per CU: as many slices as keep the launch within one pass over
-// MI355X's 256 CUs (one slice when the row tiles alone exceed them).
+// slice shorter than 8 K steps.  Tiles that take a whole CU (above 128
+// tokens, and BF16 above 64 through the LDS ring): as many slices as keep
+// the launch within one pass over MI355X's 256 CUs (one slice when the row
+// tiles alone exceed them).
 constexpr int64_t kSkinnyWideSlots = 256;
-SplitPlan plan_split(int64_t tiles_n, int64_t K, int64_t M) {
+SplitPlan plan_split(int64_t tiles_n, int64_t K, int64_t M, int32_t dtype) {
   const int64_t nk = K / gemm_k_step();
   const int64_t target = M > 64 ? 512 : 1024;
-  int64_t ks = M > 128 ? kSkinnyWideSlots / tiles_n : (target + tiles_n - 1) / tiles_n;
+  const bool whole_cu = M > 128 || (M > 64 && dtype == CLOAK_BF16);
+  int64_t ks = whole_cu ? kSkinnyWideSlots / tiles_n : (target + tiles_n - 1) / tiles_n;
   const int64_t cap = nk / 8 > 1 ? nk / 8 : 1;
   if (ks > cap) ks = cap;
   if (ks < 1) ks = 1;
@@ -422,7 +424,7 @@ uint64_t proj_ws_bytes(const cloak_layout* L, const Proj& p, int64_t M) {
     b += a256(uint64_t(M) * uint64_t(p.K) * 2);
   if (path == kPathSkinny) {
     const int64_t lr = launch_rows(L, p, skinny_tile_rows(M));
-    const SplitPlan sp = plan_split(lr / skinny_tile_rows(M), p.K, M);
+    const SplitPlan sp = plan_split(lr / skinny_tile_rows(M), p.K, M, p.dtype);
     b += a256(uint64_t(sp.ksplit) * uint64_t(M) * uint64_t(lr) * 4);
   }
   return b;
@@ -535,7 +537,7 @@ int run_proj(const cloak_layout* L, const void* pool, const Proj& p, const void*
   g.tiles_m = int32_t((M + gemm_tile_rows() - 1) / gemm_tile_rows());
   g.vec_store = aligned ? 1 : 0;
   if (path == kPathSkinny) {
-    const SplitPlan sp = plan_split(g.tiles_n, p.K, M);
+    const SplitPlan sp = plan_split(g.tiles_n, p.K, M, p.dtype);
     g.part = reinterpret_cast<float*>(wsb);
     g.ldp = lr;
     g.ksplit = sp.ksplit;
