@@ -8,7 +8,7 @@
  * heads too), and the resulting byte
  * streams are cut into pages scattered over a pool through a seeded
  * virtual->physical page map that is re-randomised periodically (Section 4.2,
- * "Physical page remapping", Table 1b).  All randomness is drawn from one seed
+ * paragraph on physical page remapping; Table 1b).  All randomness is drawn from one seed
  * before any weight is transferred (Section 5, Implementation Details).
  *
  * In this library the page map is resolved in software, inside the kernels

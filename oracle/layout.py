@@ -2,10 +2,10 @@
 
 What the paper fixes (CloakLM, arXiv 2606.18400):
 
-* Inter-layer randomisation: the order in which tensors are transferred and
-  mapped is permuted, so adjacent virtual regions no longer mean adjacent
-  layers (Section 4.2, "Inter-layer randomization via virtual address
-  shuffling"; Table 1a).
+* Inter-layer randomisation (Section 4.2, paragraph on virtual address
+  shuffling; Table 1a): tensors cross the bus and take their virtual
+  addresses in a seeded order unrelated to the model's layer order, so
+  neighbouring address ranges say nothing about neighbouring layers.
 * Intra-layer shuffling is named in the abstract without a mechanism.
   Reading: a seeded permutation of each FFN's hidden neurons -- rows of gate
   and up, columns of down -- which leaves the FFN function unchanged.  The
@@ -14,9 +14,9 @@ What the paper fixes (CloakLM, arXiv 2606.18400):
   permuted, and the value dimensions inside a head are permuted, all in ways
   the attention function cannot see (query/key dimensions stay in place: the
   rotary embedding pairs them by position inside the head).
-* Physical page remapping: tensors are spread over non-contiguous,
-  non-sequential physical pages of a pool (Section 4.2, "Physical page
-  remapping"; Table 1b).  Pages are 2 MB in the paper; any power of two works.
+* Page scattering (Section 4.2, paragraph on physical page remapping;
+  Table 1b): the pages of a tensor land on physical pages of a pool that are
+  neither adjacent nor in order.  Pages are 2 MB in the paper; any power of two works.
 * Everything is drawn from the seeded generator before any weight is
   transferred (Section 5, Implementation Details).
 

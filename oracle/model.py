@@ -1,8 +1,8 @@
 """FP64 reference decoder for the serving loop (oracle).
 
 The paper serves Llama / Qwen decoders under vLLM (Section 5 setup) and
-requires that cloaking leaves results unchanged (Section 4.1,
-"Leveraging Virtual-Physical Address Decoupling").  This module is the plain
+requires that cloaking leaves results unchanged (Section 4.1, paragraph on
+virtual-physical address decoupling).  This module is the plain
 definition of the decoder the serving loop runs, in FP64 on logical weights:
 
     r_0      = E[token]

@@ -1,7 +1,7 @@
 """Exact values of stored weights and FP64 reference results (oracle).
 
 The paper's defence must leave inference results unchanged (Section 4.1,
-"Leveraging Virtual-Physical Address Decoupling"; Section 6.1): a cloaked
+paragraph on virtual-physical address decoupling; Section 6.1): a cloaked
 layer has to compute what the plain layer computes.  The reference values are
 therefore the plain definitions, evaluated in FP64 on the *logical*
 (unshuffled) weights:

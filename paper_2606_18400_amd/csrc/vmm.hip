@@ -2,8 +2,8 @@
 //
 // CloakLM itself keeps kernels unmodified and lets the GPU's MMU resolve the
 // shuffled placement: physical pages are mapped into the model's virtual
-// range in the seeded order (arXiv 2606.18400, Section 4.2, "Physical page
-// remapping", built on the GPU's virtual memory management API).  This
+// range in the seeded order (arXiv 2606.18400, Section 4.2, paragraph on
+// physical page remapping, built on the GPU's virtual memory management API).  This
 // file builds that arrangement on MI355X for an A/B against the in-kernel
 // translation of the rest of the library: every physical page of the pool is
 // its own VMM allocation, mapped twice,
