@@ -98,3 +98,111 @@ def test_remap_slices_touch_only_their_pairs():
     for p in range(P):
         same = np.array_equal(first[0][p * B:(p + 1) * B], pool[p * B:(p + 1) * B])
         assert same == (p not in moved)
+
+
+# ---------------------------------------------------------------- uniform remap
+
+def test_uniform_draw_is_fisher_yates_on_its_own_substream():
+    P = 11
+    want = prng.fisher_yates(P, prng.substream(77, prng.TAG_REMAP, 1))
+    assert R.uniform_draw(77, P) == want
+    assert R.uniform_draw(77, P) != prng.fisher_yates(P, prng.substream(77, prng.TAG_REMAP, 0))
+
+
+def test_uniform_remap_moves_each_page_to_rho_brute_force():
+    P, B = 13, 8
+    pool = (np.arange(P * B) * 7 % 251).astype(np.uint8)
+    phi = prng.fisher_yates(P, prng.substream(3, prng.TAG_PAGE_MAP, 0))
+    rho = R.uniform_draw(21, P)
+    out, phi2 = R.remap_uniform(pool, phi, 21, B)
+    for p in range(P):
+        for i in range(B):
+            assert out[rho[p] * B + i] == pool[p * B + i]
+    for v in range(P):
+        assert phi2[v] == rho[phi[v]]
+
+
+@pytest.mark.parametrize("remap_seed", [1, 2, 3])
+def test_uniform_remap_preserves_every_tensor(remap_seed):
+    shapes = tiny_shapes("bf16")
+    lay = L.build_layout(8, shapes, 64, 64 * 256)
+    ws = random_weights(shapes, 3)
+    pool = L.pack(lay, ws)
+    pool2, phi2 = R.remap_uniform(pool, lay.phi, remap_seed, 64)
+    assert sorted(phi2) == list(range(lay.P))
+    lay2 = L.Layout(**{**lay.__dict__, "phi": phi2})
+    for t in range(lay.T):
+        assert np.array_equal(L.unpack(lay2, pool2, t), ws[t])
+
+
+def test_uniform_remap_is_uniform_whatever_the_map():
+    # chi-square of phi' over all 24 maps of a 4-page pool, from a fixed
+    # non-identity phi: every map equally likely (23 degrees of freedom; the
+    # 0.999 quantile is 49.7), and on average one page keeps its place
+    import itertools
+    phi = [2, 0, 3, 1]
+    index = {p: i for i, p in enumerate(itertools.permutations(range(4)))}
+    counts = np.zeros(24)
+    fixed = 0
+    n = 4800
+    for s in range(n):
+        _, phi2 = R.remap_uniform(np.zeros(4, np.uint8), phi, 1000 + s, 1)
+        counts[index[tuple(phi2)]] += 1
+        fixed += sum(phi2[v] == phi[v] for v in range(4))
+    chi2 = float(np.sum((counts - n / 24) ** 2 / (n / 24)))
+    assert chi2 < 49.7, chi2
+    assert abs(fixed / n - 1.0) < 0.1
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 5, 16, 257])
+@pytest.mark.parametrize("seed", [4, 5])
+def test_two_passes_of_disjoint_swaps_realise_rho(P, seed):
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    rho = R.uniform_draw(seed, P)
+    one, two = R.uniform_passes(seed, P)
+    where = list(range(P))        # where[item] = page holding it; item p starts on page p
+    at = list(range(P))           # at[page] = item on it
+    for pas in (one, two):
+        touched = [x for pr in pas for x in pr]
+        assert len(touched) == len(set(touched)), "a pass must be disjoint transpositions"
+        assert pas == sorted(pas) and all(a < b for a, b in pas)
+        for a, b in pas:
+            ia, ib = at[a], at[b]
+            at[a], at[b] = ib, ia
+            where[ia], where[ib] = b, a
+    assert where == rho
+    # the fewest transpositions that realise rho: P minus its number of cycles
+    g = coo_matrix((np.ones(P), (np.arange(P), np.array(rho))), shape=(P, P))
+    ncyc, _ = connected_components(g, directed=True, connection="weak")
+    assert len(one) + len(two) == P - ncyc
+
+
+def test_uniform_slices_keep_every_tensor_and_end_at_the_whole_remap():
+    shapes = tiny_shapes("f32")
+    lay = L.build_layout(5, shapes, 64, 64 * 257)
+    ws = random_weights(shapes, 4)
+    pool = L.pack(lay, ws)
+    one, two = R.uniform_passes(31, lay.P)
+    states = list(R.remap_uniform_in_slices(pool, lay.phi, 31, 64, 10))
+    assert len(states) == -(-len(one) // 10) + -(-len(two) // 10)
+    for pool_k, phi_k in states:
+        assert sorted(phi_k) == list(range(lay.P))
+        lay_k = L.Layout(**{**lay.__dict__, "phi": phi_k})
+        for t in range(lay.T):
+            assert np.array_equal(L.unpack(lay_k, pool_k, t), ws[t])
+    whole_pool, whole_phi = R.remap_uniform(pool, lay.phi, 31, 64)
+    assert np.array_equal(states[-1][0], whole_pool) and states[-1][1] == whole_phi
+
+
+def test_planted_pass_mistake_is_visible():
+    # swapping the order of the two passes gives rho^-1 on cycles longer than 2
+    rho = R.uniform_draw(8, 64)
+    one, two = R.uniform_passes(8, 64)
+    where, at = list(range(64)), list(range(64))
+    for pas in (two, one):
+        for a, b in pas:
+            ia, ib = at[a], at[b]
+            at[a], at[b] = ib, ia
+            where[ia], where[ib] = b, a
+    assert where != rho
