@@ -74,8 +74,15 @@
  *           npages = ceil(N*K*elt / page_bytes), zero padded
  *   phi     = FY(P, tag 3) over all P = pool_bytes/page_bytes pages; virtual
  *           page v lives at physical page phi[v]; pages V..P-1 are free
- *   remap   s = FY(P, tag 5); pair (s[2i], s[2i+1]); each pair swaps contents;
- *           phi' = tau o phi
+ *   remap   s = FY(P, tag 5, idx 0); pair (s[2i], s[2i+1]); each pair swaps
+ *           contents; phi' = tau o phi
+ *   uniform remap (CLOAK_REMAP_UNIFORM) rho = FY(P, tag 5, idx 1); the contents
+ *           of physical page p move to rho[p]; phi' = rho o phi.  In place as
+ *           two passes of disjoint swaps: for each cycle c_0 -> c_1 -> ... of
+ *           rho (c_0 its smallest page, c_{i+1} = rho[c_i], length k), pass 1
+ *           swaps c_i with c_{k-i} (0 < i < k-i), pass 2 swaps c_0 with c_1
+ *           and c_i with c_{k+1-i} (2 <= i, 2i < k+1); each pass in ascending
+ *           order of its pairs' lower page
  *   masked map (CLOAK_MASKED_MAP) the k-th upload of the device page map uses
  *           key_k = the k-th nonzero word of the counter-mode SHA-256 stream
  *           (seed, tag 8, idx 0) and stores entry v as phi[v] XOR m_k(v): with
@@ -146,6 +153,10 @@ typedef struct {
                              above) under a key that changes at every upload of the map
                              (cloak_layout_to_device, every remap slice) and reaches the
                              kernels only as a launch argument */
+#define CLOAK_REMAP_UNIFORM 16u /* every remap of this layout re-draws the whole page map
+                             uniformly (definition above): phi' = rho o phi for a fresh
+                             rho, in two passes of page-pair swaps (about twice the
+                             traffic of the matching remap, still no scratch page) */
 
 /* cloak_query() selectors. */
 #define CLOAK_QUERY_P            1  /* int64: pages in the pool                        */
@@ -192,25 +203,39 @@ int cloak_layout_build(uint64_t seed, const cloak_shape* shapes, int32_t n_shape
                        uint64_t page_bytes, uint64_t pool_bytes, uint32_t flags,
                        cloak_layout** out);
 
-/* Free the layout and its device tables (waits for nothing: the caller must
- * not free while kernels that use the layout are in flight). NULL is a no-op. */
+/* Free the layout drawn by cloak_layout_build (the host-side secret of
+ * Section 5, Implementation Details: permutations and page placement) and its
+ * device tables.  Waits for nothing: the caller must not free while kernels
+ * that use the layout are in flight.  NULL is a no-op; always returns CLOAK_OK. */
 int cloak_layout_free(cloak_layout* layout);
 
-/* Allocate and upload the device tables (page map, hidden permutations, FP8
- * scales) on the current device; required before any device call.  Idempotent. */
+/* Allocate and upload the device tables on the current device: the page map
+ * (Table 1b; the virtual->physical indirection of Section 4.1 that the
+ * kernels resolve), the hidden and head permutations, the FP8 scale table and
+ * the remap pair list.  Required before any device call.  Idempotent.
+ * Errors: EINVAL (null layout), EHIP (allocation or copy failed; nothing is
+ * kept). */
 int cloak_layout_to_device(cloak_layout* layout, void* stream);
 
-/* Copy a property of the layout into `out` (out_bytes must be large enough;
- * sizes listed with the selectors).  EINVAL on unknown selector / short buffer. */
+/* Copy a property of the layout into `out`: the tensor order (Section 4.2,
+ * Table 1a), the page map (Table 1b), the hidden permutations (abstract), the
+ * contiguity statistic of Table 2, remap state.  out_bytes must be large
+ * enough (sizes listed with the selectors); `index` selects the tensor or
+ * layer where a selector needs one.  Host only.  EINVAL on an unknown
+ * selector, a bad index or a short buffer. */
 int cloak_query(const cloak_layout* layout, int32_t what, int64_t index, void* out,
                 uint64_t out_bytes);
 
 /* Copy the device page map table as stored (masked on CLOAK_MASKED_MAP
- * layouts) into h_out[P] (for verification).  Synchronises `stream`. */
+ * layouts) into h_out[P] (for verification of the Table 1b indirection the
+ * kernels read).  Synchronises `stream`.  ESTATE before
+ * cloak_layout_to_device, EINVAL on a null h_out. */
 int cloak_device_map_read(const cloak_layout* layout, int32_t* h_out, void* stream);
 
-/* Zero the whole pool (free pages and padding hold zeros).  d_pool must be
- * 256-byte aligned and at least pool_bytes long. */
+/* Zero the whole pool (free pages and padding hold zeros): the page pool of
+ * Section 4.2 whose pages the layout scatters tensors over.  d_pool must be
+ * 256-byte aligned and at least pool_bytes long; the caller owns it.
+ * Enqueued on `stream`. */
 int cloak_pool_init(const cloak_layout* layout, void* d_pool, void* stream);
 
 /* Fill every free virtual page (V..P-1, at its current physical page) with
@@ -230,22 +255,40 @@ int cloak_pool_decoy_host(const cloak_layout* layout, void* h_pool, uint64_t h_p
  * page phi[v], pages in the seeded upload order (Section 4.2: the transfer
  * order is permuted; Section 5: layout fixed before transfer).  h_scales
  * ([N] f32, logical order) is required for FP8 and must be NULL otherwise.
+ * The FIRST upload of each tensor must follow the tensor order sigma
+ * (CLOAK_QUERY_SIGMA): a tensor that is not sigma[number of tensors uploaded
+ * so far] is refused with ESTATE, so the bus never sees tensors in their
+ * architectural order; a tensor already uploaded may be sent again.
  * Synchronises `stream` before returning. */
 int cloak_load(cloak_layout* layout, void* d_pool, int32_t tensor, const void* h_src,
                const float* h_scales, void* stream);
 
-/* Inverse of cloak_load (for verification): gather tensor `tensor` from the
- * pool into the logical array h_dst.  Synchronises `stream`. */
+/* Upload every tensor, in the tensor order sigma (the library iterates
+ * sigma; Section 4.2, Section 5): h_srcs[t] is tensor t's logical array (t the
+ * index in the shape list given to cloak_layout_build), h_scales[t] its FP8
+ * row scales or NULL; h_scales itself may be NULL when no tensor is FP8.
+ * Every entry is checked before the first page is sent (EINVAL).  Then as
+ * cloak_load for each tensor.  Synchronises `stream`. */
+int cloak_load_all(cloak_layout* layout, void* d_pool, const void* const* h_srcs,
+                   const float* const* h_scales, void* stream);
+
+/* Inverse of cloak_load (for verification): follow the page map (Table 1b)
+ * and undo the hidden permutation (abstract) to gather tensor `tensor` from
+ * the pool into the logical array h_dst ([N][K] of its storage type,
+ * caller-owned host memory).  Synchronises `stream`.  EINVAL on a bad
+ * tensor index or null h_dst, ESTATE before cloak_layout_to_device. */
 int cloak_unload(const cloak_layout* layout, const void* d_pool, int32_t tensor, void* h_dst,
                  void* stream);
 
-/* Host-side image of cloak_load: write tensor `tensor`'s pages into a host
- * buffer h_pool of pool_bytes (the same bytes cloak_load writes to the
- * device).  No device needed.  FP8 scales are not part of the pool image. */
+/* Host-side image of cloak_load (Section 4.2 placement): write tensor
+ * `tensor`'s pages into a host buffer h_pool of pool_bytes (the same bytes
+ * cloak_load writes to the device).  No device needed; any order.  FP8 scales
+ * are not part of the pool image.  EINVAL on a short buffer or bad index. */
 int cloak_pack_host(const cloak_layout* layout, int32_t tensor, const void* h_src,
                     void* h_pool, uint64_t h_pool_bytes);
 
-/* Bytes of device workspace `op` needs for `index` at M tokens: the FP32
+/* Bytes of device workspace `op` needs for `index` at M tokens (for the
+ * projections of Section 4.2's bandwidth-bound inference): the FP32
  * partial sums of the split-K decode GEMM (5..256 tokens), for a down
  * projection called through cloak_linear its activations gathered through
  * pi, and for FP8 weights above 256 tokens the per-token E4M3 activations and
@@ -253,22 +296,31 @@ int cloak_pack_host(const cloak_layout* layout, int32_t tensor, const void* h_sr
  * UINT64_MAX on bad arguments. */
 uint64_t cloak_ws_bytes(const cloak_layout* layout, int32_t op, int32_t index, int64_t M);
 
-/* Workspace of cloak_linear_fused for these n tensors at M tokens. */
+/* Workspace of cloak_linear_fused for these n tensors at M tokens (as
+ * cloak_ws_bytes; UINT64_MAX on bad arguments). */
 uint64_t cloak_linear_fused_ws_bytes(const cloak_layout* layout, const int32_t* tensors, int32_t n,
                                      int64_t M);
 
-/* y[M][N] = x[M][K] . W^T for tensor `tensor`, with x and y in LOGICAL
+/* The cloaked linear layer: the weights stay resident and are read in place
+ * on every forward pass (Section 2.3), from pages the layout scattered
+ * (Section 4.2, Table 1b), at the bandwidth the performance paragraph of
+ * Section 4.2 requires of a bandwidth-bound step.
+ * y[M][N] = x[M][K] . W^T for tensor `tensor`, with x and y in LOGICAL
  * order: for gate/up (and head-permuted q/k/v) the kernel scatters stored
  * row j to column p[j]; for down (and head-permuted o) it gathers x through
  * the column permutation while staging it.  Weights are read straight
  * from the scattered pages (virtual tile -> physical page resolved in the
- * kernel).  M = 0 is a no-op.  Workspace as reported by cloak_ws_bytes. */
+ * kernel).  M = 0 is a no-op.  Workspace as reported by cloak_ws_bytes.
+ * x 16-byte aligned; errors EINVAL (sizes, null buffers, short workspace),
+ * ESTATE (no device tables, wrong device), EHIP (launch failed). */
 int cloak_linear(const cloak_layout* layout, const void* d_pool, int32_t tensor,
                  const void* d_x, int64_t M, void* d_y, void* d_ws, uint64_t ws_bytes,
                  void* stream);
 
-/* Several tensors with the same K in one launch (e.g. q, k, v): y is
- * [M][sum N_i], tensor i's columns at offset sum_{j<i} N_j.  n <= 4. */
+/* cloak_linear over several tensors with the same K in one launch (e.g.
+ * q, k, v; Section 4.2 performance paragraph): y is [M][sum N_i], tensor i's
+ * columns at offset sum_{j<i} N_j.  n <= 4; ESHAPE if K or dtype differ or a
+ * tensor with permuted columns is fused with others. */
 int cloak_linear_fused(const cloak_layout* layout, const void* d_pool, const int32_t* tensors,
                        int32_t n, const void* d_x, int64_t M, void* d_y, void* d_ws,
                        uint64_t ws_bytes, void* stream);
@@ -284,28 +336,33 @@ int cloak_linear_stored(const cloak_layout* layout, const void* d_pool, const in
                         const void* d_x, int64_t M, void* d_y, void* d_ws, uint64_t ws_bytes,
                         void* stream);
 
-/* SwiGLU FFN of layer `layer`: y = (silu(x Wg^T) * (x Wu^T)) Wd^T, with
- * silu(z) = z / (1 + e^-z), run directly on the shuffled weights: the hidden
- * activations stay in permuted order (bf16 for bf16/fp8 weights, f32 for f32)
- * in the workspace, so the permutation cancels between up/gate and down. */
+/* SwiGLU FFN of layer `layer` under the intra-layer shuffle (abstract: the
+ * hidden neurons of each FFN are permuted): y = (silu(x Wg^T) * (x Wu^T)) Wd^T,
+ * with silu(z) = z / (1 + e^-z), run directly on the shuffled weights: the
+ * hidden activations stay in permuted order (bf16 for bf16/fp8 weights, f32
+ * for f32) in the workspace, so the permutation cancels between up/gate and
+ * down.  x, y: [M][d_model] in logical order.  Workspace: cloak_mlp_ws_bytes.
+ * Errors: EINVAL (layer lacks gate/up/down, null buffers, short workspace). */
+uint64_t cloak_mlp_ws_bytes(const cloak_layout* layout, int32_t layer, int64_t M);
 int cloak_mlp(const cloak_layout* layout, const void* d_pool, int32_t layer, const void* d_x,
               int64_t M, void* d_y, void* d_ws, uint64_t ws_bytes, void* stream);
 
-/* First half of cloak_mlp, one launch: h[M][d_ffn] = silu(x Wg^T) * (x Wu^T)
+/* First half of cloak_mlp (abstract, intra-layer shuffle), one launch: h[M][d_ffn] = silu(x Wg^T) * (x Wu^T)
  * with h left in the layer's PERMUTED hidden order (column j holds hidden
  * unit pi[j]); each workgroup reads matching gate and up rows.  h is bf16
  * (f32 for f32 weights). */
 int cloak_swiglu(const cloak_layout* layout, const void* d_pool, int32_t layer, const void* d_x,
                  int64_t M, void* d_h, void* d_ws, uint64_t ws_bytes, void* stream);
 
-/* Second half of cloak_mlp, one launch: y[M][d_model] = h . Wd^T for h in the
+/* Second half of cloak_mlp (abstract, intra-layer shuffle), one launch: y[M][d_model] = h . Wd^T for h in the
  * permuted hidden order cloak_swiglu produces (down's stored columns carry
  * the same permutation, so nothing is gathered).  Workspaces: cloak_ws_bytes
  * with CLOAK_OP_SWIGLU / CLOAK_OP_DOWN. */
 int cloak_down(const cloak_layout* layout, const void* d_pool, int32_t layer, const void* d_h,
                int64_t M, void* d_y, void* d_ws, uint64_t ws_bytes, void* stream);
 
-/* Bandwidth calibration (not part of the cloaked path): stream every byte of
+/* Bandwidth calibration for the bandwidth-bound decode that the performance
+ * paragraph of Section 4.2 speaks of (not part of the cloaked path): stream every byte of
  * d_src once with non-temporal 16-byte loads, as the weight-reading kernels
  * do, and fold them into one word that is written to *d_out only when it
  * equals a constant.  Gives the device's plain streaming-read rate, the
@@ -348,20 +405,27 @@ int cloak_moe(const cloak_layout* layout, const void* d_pool, int32_t first_laye
 int cloak_quantize_fp8(const void* d_x, int64_t M, int64_t K, int64_t ldx, void* d_q, void* d_s,
                        void* stream);
 
-/* Re-randomise page placement in place (Section 4.2, periodic remapping
- * with no extra memory footprint): draw the matching tau from remap_seed,
- * swap every page pair in the pool on `stream`, and set phi' = tau o phi on
- * host and device.  Refused (ESTATE) on CLOAK_NATIVE layouts and while an
- * incremental remap is in progress. */
+/* Re-randomise page placement in place (Section 4.2, physical page
+ * remapping: the map is re-drawn from time to time and no memory is added
+ * for it).  Default: draw the matching tau from remap_seed, swap every page
+ * pair in the pool on `stream`, and set phi' = tau o phi on host and device
+ * (one pass, each pool byte read and written once).  On CLOAK_REMAP_UNIFORM
+ * layouts: draw rho from remap_seed and run its two passes of swaps (one
+ * launch each), phi' = rho o phi.  Refused (ESTATE) on CLOAK_NATIVE layouts
+ * and while an incremental remap is in progress.  Device memory stays as it
+ * was: no allocation, the pair list goes into a table made by
+ * cloak_layout_to_device. */
 int cloak_remap(cloak_layout* layout, void* d_pool, uint64_t remap_seed, void* stream);
 
 /* Incremental remap (spreads one remap over several serving steps, so no
  * single step pays the whole move; the paper leaves the cadence to the
- * operator, Section 4.2 and Figure 7).  cloak_remap_begin draws the matching
- * tau from remap_seed; each cloak_remap_step then swaps the next max_pairs
- * page pairs (all remaining if max_pairs <= 0; pairs in ascending order of
- * their lower page) on `stream` and updates phi for exactly those pages,
- * host and device, in stream order.  Between steps the pool and phi are a
+ * operator, Section 4.2 and Figure 7).  cloak_remap_begin draws tau (or rho
+ * and its two passes, on CLOAK_REMAP_UNIFORM layouts) from remap_seed; each
+ * cloak_remap_step then swaps the next max_pairs page pairs (pairs in the
+ * order of the definition; a step never runs pairs of both passes, so a
+ * bounded step stops at the end of pass 1; max_pairs <= 0 runs everything
+ * left, one launch per pass) on `stream` and updates phi for exactly those
+ * pages, host and device, in stream order.  Between steps the pool and phi are a
  * complete, consistent layout, so any cloak_* call may run between them;
  * after the last pair the result equals cloak_remap(remap_seed).
  * *remaining (may be NULL) receives the pairs still to swap.
@@ -393,9 +457,11 @@ int cloak_remap_step_host(cloak_layout* layout, void* h_pool, uint64_t h_pool_by
 int cloak_vmm_pool_create(cloak_layout* layout, void** d_pool_view);
 int cloak_vmm_pool_free(cloak_layout* layout);
 
-/* Host-side remap of a pool image h_pool (pool_bytes) and of the layout's
- * page map; the same result cloak_remap produces on the device.  Updates
- * only the host copy of phi: do not mix with device calls on one layout. */
+/* Host-side remap (Section 4.2, physical page remapping) of a pool image
+ * h_pool (pool_bytes) and of the layout's page map; the same result
+ * cloak_remap produces on the device, matching or uniform as the layout's
+ * flags say.  Updates only the host copy of phi: do not mix with device calls
+ * on one layout.  ESTATE on native layouts or during an incremental remap. */
 int cloak_remap_host(cloak_layout* layout, void* h_pool, uint64_t h_pool_bytes,
                      uint64_t remap_seed);
 
@@ -437,7 +503,8 @@ typedef struct {
   void* d_out_logits;            /* [n_logits][vocab] bf16, or NULL           */
 } cloak_step;
 
-/* Bind a layout, its pool, RMSNorm gains (d_gains: [2*n_layers+1][d_model]
+/* Serving model over a cloaked layout (Section 4.1: the engine's KV blocks;
+ * Section 5.2: iteration latency of prefill and decode).  Bind a layout, its pool, RMSNorm gains (d_gains: [2*n_layers+1][d_model]
  * bf16 in the order attn_0, mlp_0, ..., final; NULL = all ones) and the KV
  * cache (d_kv: [n_layers][2][num_blocks][n_kv_heads][block_size][head_dim]
  * bf16, caller-owned).  head_dim must be 128 and n_heads/n_kv_heads <= 8.
@@ -446,8 +513,9 @@ int cloak_model_create(const cloak_layout* layout, const void* d_pool, const clo
                        const void* d_gains, void* d_kv, cloak_model** out);
 int cloak_model_free(cloak_model* model);
 
-/* Workspace for steps of at most max_tokens tokens, max_logits logit rows
- * and max_tiles * max_splits attention slices. */
+/* Workspace of cloak_model_step (Section 4.1 serving step) for steps of at
+ * most max_tokens tokens, max_logits logit rows and max_tiles * max_splits
+ * attention slices.  UINT64_MAX on bad arguments. */
 uint64_t cloak_model_ws_bytes(const cloak_model* model, int64_t max_tokens, int64_t max_logits,
                               int64_t max_tiles, int64_t max_splits);
 
@@ -458,7 +526,10 @@ uint64_t cloak_model_ws_bytes(const cloak_model* model, int64_t max_tokens, int6
 int cloak_model_step(cloak_model* model, const cloak_step* step, void* d_ws, uint64_t ws_bytes,
                      void* stream);
 
-/* Message describing the last error on the calling thread ("" if none). */
+/* Message describing the last error on the calling thread ("" if none);
+ * every call above reports its failures here (the error convention at the
+ * top of this file).  The string is owned by the library and valid until the
+ * thread's next call. */
 const char* cloak_last_error(void);
 
 #ifdef __cplusplus

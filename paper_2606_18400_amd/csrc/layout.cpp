@@ -100,16 +100,59 @@ std::vector<int32_t> remap_matching(uint64_t remap_seed, int64_t P, bool csprng)
   return tau;
 }
 
+std::vector<int32_t> remap_uniform_draw(uint64_t remap_seed, int64_t P, bool csprng) {
+  return fisher_yates(P, stream(remap_seed, kTagRemap, 1, csprng));
+}
+
+// A cycle c_0 -> c_1 -> ... -> c_{k-1} -> c_0 of rho (c_0 its smallest page)
+// shifts contents by one place.  That shift is the reflection i -> -i
+// (mod k) followed by the reflection i -> 1 - i, and each reflection is a
+// set of disjoint transpositions: pass 1 pairs c_i with c_{k-i}, pass 2
+// pairs c_0 with c_1 and c_i with c_{k+1-i}.  Together they use k - 1 swaps.
+void remap_uniform_passes(const std::vector<int32_t>& rho, std::vector<int32_t>& pass1, std::vector<int32_t>& pass2) {
+  const int64_t P = int64_t(rho.size());
+  std::vector<std::pair<int32_t, int32_t>> one, two;
+  std::vector<char> seen(size_t(P), 0);
+  std::vector<int32_t> c;
+  for (int64_t start = 0; start < P; ++start) {
+    if (seen[size_t(start)]) continue;
+    c.clear();
+    for (int32_t q = int32_t(start); !seen[size_t(q)]; q = rho[size_t(q)]) {
+      seen[size_t(q)] = 1;
+      c.push_back(q);
+    }
+    const int64_t k = int64_t(c.size());
+    auto lohi = [](int32_t a, int32_t b) { return a < b ? std::make_pair(a, b) : std::make_pair(b, a); };
+    for (int64_t i = 1; 2 * i < k; ++i) one.push_back(lohi(c[size_t(i)], c[size_t(k - i)]));
+    if (k > 1) two.push_back(lohi(c[0], c[1]));
+    for (int64_t i = 2; 2 * i < k + 1; ++i) two.push_back(lohi(c[size_t(i)], c[size_t(k + 1 - i)]));
+  }
+  std::sort(one.begin(), one.end());
+  std::sort(two.begin(), two.end());
+  pass1.clear();
+  pass2.clear();
+  for (const auto& q : one) pass1.insert(pass1.end(), {q.first, q.second});
+  for (const auto& q : two) pass2.insert(pass2.end(), {q.first, q.second});
+}
+
 bool remap_epoch_begin(cloak_layout* L, uint64_t remap_seed) {
   RemapEpoch& e = L->epoch;
   if (e.active) return false;
-  const std::vector<int32_t> tau = remap_matching(remap_seed, L->P, L->csprng());
   e.pairs.clear();
-  for (int64_t p = 0; p < L->P; ++p)
-    if (tau[p] > p) {
-      e.pairs.push_back(int32_t(p));
-      e.pairs.push_back(tau[p]);
-    }
+  if (L->uniform_remap()) {
+    std::vector<int32_t> two;
+    remap_uniform_passes(remap_uniform_draw(remap_seed, L->P, L->csprng()), e.pairs, two);
+    e.pass_end = e.npairs();
+    e.pairs.insert(e.pairs.end(), two.begin(), two.end());
+  } else {
+    const std::vector<int32_t> tau = remap_matching(remap_seed, L->P, L->csprng());
+    for (int64_t p = 0; p < L->P; ++p)
+      if (tau[p] > p) {
+        e.pairs.push_back(int32_t(p));
+        e.pairs.push_back(tau[p]);
+      }
+    e.pass_end = e.npairs();
+  }
   e.where.assign(size_t(L->P), 0);
   for (int64_t v = 0; v < L->P; ++v) e.where[size_t(L->phi[v])] = int32_t(v);
   e.next = 0;
@@ -259,7 +302,7 @@ extern "C" int cloak_layout_build(uint64_t seed, const cloak_shape* shapes, int3
     set_error("cloak_layout_build: pool_bytes must be a positive multiple of page_bytes");
     return CLOAK_EINVAL;
   }
-  if ((flags & ~(CLOAK_IDENTITY | CLOAK_NATIVE | CLOAK_CSPRNG | CLOAK_MASKED_MAP)) != 0 ||
+  if ((flags & ~(CLOAK_IDENTITY | CLOAK_NATIVE | CLOAK_CSPRNG | CLOAK_MASKED_MAP | CLOAK_REMAP_UNIFORM)) != 0 ||
       ((flags & CLOAK_NATIVE) && !(flags & CLOAK_IDENTITY))) {
     set_error("cloak_layout_build: bad flags 0x%x (CLOAK_NATIVE needs CLOAK_IDENTITY)", flags);
     return CLOAK_EINVAL;
@@ -465,6 +508,7 @@ extern "C" int cloak_layout_build(uint64_t seed, const cloak_shape* shapes, int3
   } else {
     L->phi = fisher_yates(P, stream(seed, kTagPageMap, 0, L->csprng()));
   }
+  L->loaded.assign(size_t(n_shapes), 0);
   *out = L;
   return CLOAK_OK;
 }
@@ -730,6 +774,21 @@ extern "C" int cloak_remap_begin(cloak_layout* L, uint64_t remap_seed) {
   return CLOAK_OK;
 }
 
+namespace {
+// Swap pairs [e.next, e.next + n) of the active epoch in a host pool image.
+void swap_pairs_host(cloak_layout* L, uint8_t* pool, int64_t n) {
+  const RemapEpoch& e = L->epoch;
+  std::vector<uint8_t> tmp(size_t(L->page_bytes));
+  for (int64_t i = e.next; i < e.next + n; ++i) {
+    uint8_t* a = pool + int64_t(e.pairs[2 * i]) * L->page_bytes;
+    uint8_t* b = pool + int64_t(e.pairs[2 * i + 1]) * L->page_bytes;
+    std::memcpy(tmp.data(), a, size_t(L->page_bytes));
+    std::memcpy(a, b, size_t(L->page_bytes));
+    std::memcpy(b, tmp.data(), size_t(L->page_bytes));
+  }
+}
+}  // namespace
+
 extern "C" int cloak_remap_step_host(cloak_layout* L, void* h_pool, uint64_t h_pool_bytes, int64_t max_pairs,
                                      int64_t* remaining) {
   clear_error();
@@ -747,16 +806,9 @@ extern "C" int cloak_remap_step_host(cloak_layout* L, void* h_pool, uint64_t h_p
   }
   RemapEpoch& e = L->epoch;
   const int64_t left = e.npairs() - e.next;
-  const int64_t n = max_pairs <= 0 || max_pairs > left ? left : max_pairs;
-  auto* pool = static_cast<uint8_t*>(h_pool);
-  std::vector<uint8_t> tmp(size_t(L->page_bytes));
-  for (int64_t i = e.next; i < e.next + n; ++i) {
-    uint8_t* a = pool + int64_t(e.pairs[2 * i]) * L->page_bytes;
-    uint8_t* b = pool + int64_t(e.pairs[2 * i + 1]) * L->page_bytes;
-    std::memcpy(tmp.data(), a, size_t(L->page_bytes));
-    std::memcpy(a, b, size_t(L->page_bytes));
-    std::memcpy(b, tmp.data(), size_t(L->page_bytes));
-  }
+  // a bounded slice stops at the end of its pass; max_pairs <= 0 runs both
+  const int64_t n = max_pairs <= 0 ? left : std::min(max_pairs, e.launchable());
+  swap_pairs_host(L, static_cast<uint8_t*>(h_pool), n);
   remap_epoch_advance(L, n);
   if (remaining) *remaining = left - n;
   return CLOAK_OK;
@@ -780,19 +832,9 @@ extern "C" int cloak_remap_host(cloak_layout* L, void* h_pool, uint64_t h_pool_b
     set_error("cloak_remap_host: a remap is in progress (finish it with cloak_remap_step_host)");
     return CLOAK_ESTATE;
   }
-  std::vector<int32_t> tau = remap_matching(remap_seed, L->P, L->csprng());
-  auto* pool = static_cast<uint8_t*>(h_pool);
-  std::vector<uint8_t> tmp(size_t(L->page_bytes));
-  for (int64_t p = 0; p < L->P; ++p) {
-    const int64_t q = tau[p];
-    if (q <= p) continue;  // each pair once
-    uint8_t* a = pool + p * L->page_bytes;
-    uint8_t* b = pool + q * L->page_bytes;
-    std::memcpy(tmp.data(), a, size_t(L->page_bytes));
-    std::memcpy(a, b, size_t(L->page_bytes));
-    std::memcpy(b, tmp.data(), size_t(L->page_bytes));
-  }
-  for (auto& v : L->phi) v = tau[v];
-  L->remaps += 1;
+  remap_epoch_begin(L, remap_seed);
+  const int64_t n = L->epoch.npairs() - L->epoch.next;
+  swap_pairs_host(L, static_cast<uint8_t*>(h_pool), n);
+  remap_epoch_advance(L, n);
   return CLOAK_OK;
 }
