@@ -224,15 +224,16 @@ extern "C" int cloak_layout_to_device(cloak_layout* L, void* stream) {
   return CLOAK_OK;
 }
 
-extern "C" int cloak_layout_free(cloak_layout* L) {
-  clear_error();
-  if (!L) return CLOAK_OK;
+namespace {
+// Device state of a layout, released by cloak_layout_free (layout.cpp) before
+// the host object goes.
+void release_device(cloak_layout* L) {
   if (L->vmm.active) (void)cloak_vmm_pool_free(L);
   drop_ring(L);
   free_tables(L->dev);
-  delete L;
-  return CLOAK_OK;
 }
+[[maybe_unused]] const bool g_release_registered = (cloak::release_device_state = release_device, true);
+}  // namespace
 
 extern "C" int cloak_pool_init(const cloak_layout* L, void* d_pool, void* stream) {
   clear_error();

@@ -186,6 +186,9 @@ struct cloak_layout {
 };
 
 namespace cloak {
+// Frees the device side of a layout (device tables, staging, VMM twin); set
+// by the device code of the library, null in a host-only build.
+extern void (*release_device_state)(cloak_layout*);
 // host pack/unpack helpers (layout.cpp)
 void stream_page(const cloak_layout* L, int32_t t, const uint8_t* src, int64_t page, uint8_t* dst);
 void unstream_page(const cloak_layout* L, int32_t t, const uint8_t* page_bytes, int64_t page, uint8_t* dst);

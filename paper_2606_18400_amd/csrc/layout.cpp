@@ -284,6 +284,18 @@ using namespace cloak;
 
 extern "C" const char* cloak_last_error(void) { return cloak::last_error(); }
 
+namespace cloak {
+void (*release_device_state)(cloak_layout*) = nullptr;
+}
+
+extern "C" int cloak_layout_free(cloak_layout* L) {
+  clear_error();
+  if (!L) return CLOAK_OK;
+  if (release_device_state) release_device_state(L);
+  delete L;
+  return CLOAK_OK;
+}
+
 extern "C" int cloak_layout_build(uint64_t seed, const cloak_shape* shapes, int32_t n_shapes,
                                   uint64_t page_bytes, uint64_t pool_bytes, uint32_t flags,
                                   cloak_layout** out) {

@@ -179,6 +179,8 @@ def test_vmm_twin_matches_software_translation(C):
             assert torch.equal(soft.mlp(0, x).view(torch.int16), hard.mlp(0, x).view(torch.int16)), (tag, M)
 
     same_results("loaded")
+    for M in (1, 8, 300):     # the MMU-translated twin against the oracle itself
+        check_linear_all(C, hard, shapes, ws, scs, M)
     for t, w in enumerate(ws):
         back = np.zeros_like(w)
         C.cloak_unload(hard.layout, hard.pool, t, back)
@@ -186,6 +188,7 @@ def test_vmm_twin_matches_software_translation(C):
     soft.remap(5)
     hard.remap(5)
     same_results("remapped")
+    check_linear_all(C, hard, shapes, ws, scs, 8)
     soft.remap_begin(6)
     hard.remap_begin(6)
     while soft.remap_step(3):
@@ -833,7 +836,9 @@ def test_decode_full_layer4096_bench_calls(C):
     cw.load(ws, scs)
     L = cw.layout
     W = [w64(shapes, ws, scs, t) for t in range(len(shapes))]
-    for M in (1, 8, 32, 64):
+    # 100 and 128 tokens run the 4-stage LDS-ring tile with K slices sized to
+    # one pass over the CUs, 256 the 3-stage ring on 8 waves
+    for M in (1, 8, 32, 64, 100, 128, 256):
         x_np = synth.activations(M, d, "bf16", seed=100 + M)
         x, x64 = to_device_x(x_np), values_f64(x_np)
         need = max(C.cloak_linear_fused_ws_bytes(L, [0, 1, 2], M), C.cloak_ws_bytes(L, C.CLOAK_OP_LINEAR, 3, M),
@@ -881,6 +886,22 @@ def test_fp8_stack_layer5120_full_size_sampled(C):
         y = from_device(cw.mlp(0, x))[rows]
         ref, _ = ON.swiglu_ffn(x64, W[4], W[5], W[6])
         assert ON.normwise_err(values_f64(y), ref) <= TOL["fp8"], M
+    # prefill: 8192 tokens through FP8 x FP8 MFMA on per-token E4M3
+    # activations, the configuration the stack's prefill figure is taken on;
+    # quantisation is per row, so the sampled rows' codes are the oracle's own
+    M = 8192
+    x_np = synth.activations(M, d, "bf16", seed=8192)
+    x = to_device_x(x_np)
+    rows = np.unique(np.concatenate([[0, M - 1], rng.choice(M, size=24, replace=False)]))
+    x64 = values_f64(x_np[rows])
+    xq = ON.fp8_activations_f64(*ON.quantize_rows_e4m3(synth.bf16_to_f32(x_np[rows])))
+    for t in (0, 3):
+        y = values_f64(from_device(cw.linear(t, x))[rows])
+        assert ON.normwise_err(y, ON.linear(xq, W[t])) <= 1e-2, ("a8", t)
+        assert ON.normwise_err(y, ON.linear(x64, W[t])) <= TOL["fp8"], ("a8", t)
+    y = values_f64(from_device(cw.mlp(0, x))[rows])
+    ref, _ = ON.swiglu_ffn(x64, W[4], W[5], W[6])
+    assert ON.normwise_err(y, ref) <= TOL["fp8"], "a8 mlp"
     del W
     cw.close()
     torch.cuda.empty_cache()
@@ -902,10 +923,15 @@ def test_prefill_full_layer4096_sampled_tokens(C):
     rows = np.sort(rng.choice(M, size=48, replace=False))
     rows[0], rows[-1] = 0, M - 1
     x64 = values_f64(x_np[rows])
-    for t in (0, 3):   # q and o (K = 4096)
+    for t in (0, 1, 2, 3):   # q, k, v and o (K = 4096)
         y = from_device(cw.linear(t, x))[rows]
         err = ON.normwise_err(values_f64(y), ON.linear(x64, w64(shapes, ws, scs, t)))
         assert err <= 1e-2, (t, err)
+    # the fused q/k/v call the bench times
+    y = from_device(cw.linear_fused([0, 1, 2], x))[rows]
+    ref = np.concatenate([ON.linear(x64, w64(shapes, ws, scs, t)) for t in (0, 1, 2)], axis=1)
+    err = ON.normwise_err(values_f64(y), ref)
+    assert err <= 1e-2, ("qkv", err)
     y = from_device(cw.mlp(0, x))[rows]
     ref, _ = ON.swiglu_ffn(x64, w64(shapes, ws, scs, 4), w64(shapes, ws, scs, 5), w64(shapes, ws, scs, 6))
     err = ON.normwise_err(values_f64(y), ref)

@@ -149,3 +149,35 @@ def test_admission_never_overcommits_kv(S):
     assert all(r.done and len(r.out) == r.max_new for r in reqs)
     assert peak <= 12
     eng.close()
+
+
+# the serving geometry's attention: 32 query heads over 8 kv heads of 128
+# (d_model 4096), with a small FFN and vocabulary so the FP64 reference stays
+# quick; one layer, so attention's output dominates the residual stream
+ATTN32 = dict(n_layers=1, d_model=4096, n_heads=32, n_kv_heads=8, head_dim=128, d_ffn=512, vocab=1024,
+              theta=500000.0, eps=1e-5)
+
+
+def test_attention_32_8_heads_long_context_matches_fp64_oracle(S):
+    """A 4,200-token prompt prefilled in 512-token chunks (tiles of 16 new
+    tokens against up to 4,200 keys, contexts cut into 512-key slices), then
+    decode steps whose single query reads the whole context: the logits of the
+    last prompt position and of each decoded position against the FP64
+    decoder (stored-order permuted heads, 2 MiB pages)."""
+    shapes, ws = tiny_weights(ATTN32)
+    rng = np.random.Generator(np.random.PCG64(15))
+    prompt = rng.integers(0, ATTN32["vocab"], 4200).astype(np.int32)
+    forced = rng.integers(0, ATTN32["vocab"], 3).astype(np.int32)
+    eng = make_engine(S, ATTN32, ws, pool_bytes=256 << 20, page_bytes=2 << 20, kv_blocks=300, max_tokens=512,
+                      prefill_chunk=512, max_seqs=4, split_keys=512)
+    r = S.Request(0, prompt, len(forced), forced=forced)
+    eng.run([r], realtime=False)
+    ref = oracle_decoder(ATTN32, shapes, ws).forward(np.concatenate([prompt, forced[:-1]]))
+    assert len(r.logits) == len(forced)
+    worst = 0.0
+    for i, lg in enumerate(r.logits):
+        err = ON.normwise_err(lg, ref[len(prompt) - 1 + i])
+        worst = max(worst, err)
+        assert err <= 3e-2, (i, err)
+    print(f"32/8-head attention over 4200+ keys: worst normwise logit error vs FP64 {worst:.3e}")
+    eng.close()
