@@ -347,6 +347,22 @@ uint64_t cloak_mlp_ws_bytes(const cloak_layout* layout, int32_t layer, int64_t M
 int cloak_mlp(const cloak_layout* layout, const void* d_pool, int32_t layer, const void* d_x,
               int64_t M, void* d_y, void* d_ws, uint64_t ws_bytes, void* stream);
 
+/* cloak_mlp for callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * kernels and results, with the workspace taken from a static device array of
+ * CLOAK_MLP_NOALLOC_MAX_BYTES per GPU (held until the process ends; its device
+ * address is looked up once per device on the first call there).  The caller
+ * still owns x and y.  No call allocates or frees memory.  Calls whose
+ * cloak_mlp_ws_bytes exceeds the maximum are refused with EINVAL (64 MiB
+ * covers a 4096/14336 BF16 layer up to 2048 tokens and a 5120/27648 FP8 layer
+ * up to 128).  Every call on one GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (several streams, several threads) race and give
+ * undefined results; calls on one stream are ordered and safe.  Nothing in the
+ * array needs to start at zero: a call reads only bytes it has written. */
+#define CLOAK_MLP_NOALLOC_MAX_BYTES (64ull << 20)
+int cloak_mlp_noalloc(const cloak_layout* layout, const void* d_pool, int32_t layer, const void* d_x,
+                      int64_t M, void* d_y, void* stream);
+
 /* First half of cloak_mlp (abstract, intra-layer shuffle), one launch: h[M][d_ffn] = silu(x Wg^T) * (x Wu^T)
  * with h left in the layer's PERMUTED hidden order (column j holds hidden
  * unit pi[j]); each workgroup reads matching gate and up rows.  h is bf16

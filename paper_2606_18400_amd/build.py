@@ -18,7 +18,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-W
              "-I", os.path.join(ROOT, "include")]
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include")]
 
-HIP_SOURCES = ["api.hip", "gemv.hip", "gemm.hip", "remap.hip", "serve.hip", "model.hip", "vmm.hip"]
+HIP_SOURCES = ["api.hip", "gemv.hip", "gemm.hip", "remap.hip", "serve.hip", "model.hip", "vmm.hip", "noalloc.hip"]
 CXX_SOURCES = ["layout.cpp", "sha256.cpp"]
 
 

@@ -95,6 +95,7 @@ _SIGS = {
     "cloak_linear_stored": ([_vp, _vp, ctypes.POINTER(_i32), _i32, _vp, _i64, _vp, _vp, _u64, _vp], _i32),
     "cloak_mlp": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _u64, _vp], _i32),
     "cloak_mlp_ws_bytes": ([_vp, _i32, _i64], _u64),
+    "cloak_mlp_noalloc": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp], _i32),
     "cloak_swiglu": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _u64, _vp], _i32),
     "cloak_down": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _u64, _vp], _i32),
     "cloak_quantize_fp8": ([_vp, _i64, _i64, _i64, _vp, _vp, _vp], _i32),
@@ -304,6 +305,11 @@ def cloak_linear_stored(layout, pool, tensors, x, M, y, ws=None, ws_bytes=0, str
 def cloak_mlp(layout, pool, layer, x, M, y, ws, ws_bytes, stream=None):
     _check(_lib.cloak_mlp(layout, _ptr(pool), layer, _ptr(x), M, _ptr(y), _ptr(ws), ws_bytes, _stream(stream)),
            "cloak_mlp")
+
+
+def cloak_mlp_noalloc(layout, pool, layer, x, M, y, stream=None):
+    _check(_lib.cloak_mlp_noalloc(layout, _ptr(pool), layer, _ptr(x), M, _ptr(y), _stream(stream)),
+           "cloak_mlp_noalloc")
 
 
 def cloak_swiglu(layout, pool, layer, x, M, h, ws=None, ws_bytes=0, stream=None):
