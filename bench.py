@@ -109,7 +109,10 @@ class Variant:
         C.cloak_down(L, pool, l, b["h"], M, b["y"], ws, wsb)
 
 
-def time_steps(var, M, steps, warmup, kernel_events=False):
+def time_steps(var, M, steps, warmup, kernel_events=False, spread=None):
+    """Mean ms per step over `steps` back-to-back steps (events around the whole
+    loop).  With `spread` (a dict), also events between consecutive steps on
+    the launch stream, whose p10/p50/p90 are stored into it."""
     import torch
     b = var.buffers(M)
     for i in range(warmup):
@@ -117,17 +120,25 @@ def time_steps(var, M, steps, warmup, kernel_events=False):
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(steps)] if kernel_events else None
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)] if spread is not None else None
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record()
     for i in range(steps):
+        if marks:
+            marks[i].record()
         var.step(i, M, b, evs[i] if evs else None)
+    if marks:
+        marks[steps].record()
     stop.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / steps
     kms = None
     if evs:
         kms = float(np.mean([a.elapsed_time(z) for a, z in evs]))
+    if marks:
+        per = np.array([marks[i].elapsed_time(marks[i + 1]) for i in range(steps)])
+        spread.update({f"ms_p{q}": float(np.percentile(per, q)) for q in (10, 50, 90)})
     return ms, kms
 
 
@@ -223,6 +234,107 @@ def time_remap(var, reps, with_copy=True):
                 frac_of_peak=traffic / ms / 1e6 / HBM_PEAK_GBS)
 
 
+def vendor_gemm(M, shapes_nk, reps=10):
+    """The library GEMM (torch.nn.functional.linear on a contiguous nn.Linear
+    [N][K] BF16 weight, untranslated) at the prefill shapes for comparison:
+    TFLOP/s per (N, K)."""
+    import torch
+    import torch.nn.functional as F
+    out = {}
+    x = {}
+    for (n, k) in shapes_nk:
+        if k not in x:
+            x[k] = torch.empty((M, k), dtype=torch.bfloat16, device="cuda").normal_()
+        w = torch.empty((n, k), dtype=torch.bfloat16, device="cuda").normal_()
+        y = F.linear(x[k], w)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            y = F.linear(x[k], w)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        out[f"{n}x{k}"] = dict(ms=ms, tflops=2 * M * n * k / ms / 1e9)
+        del w, y
+    del x
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_prefill(args):
+    """The BF16 prefill GEMM alone: the gate/up SwiGLU launch of the 4096/14336
+    layer at 8192 tokens (cloaked and native), back to back over 16 layer
+    copies, and the library GEMM at the same shapes.  A short run for
+    hardware-counter passes of the prefill kernel."""
+    import torch
+    from paper_2606_18400_amd import cloak as C
+    from paper_2606_18400_amd import synth
+    cfg = synth.LAYER4096
+    d, f, kv = cfg["d_model"], cfg["d_ffn"], cfg["d_kv"]
+    one = synth.decoder_layer_shapes(d, f, kv, "bf16", layer=0)
+    shapes = [(l, k, n, kk, dt) for l in range(COPIES) for (_, k, n, kk, dt) in one]
+    w1 = [synth.weight(t, s[2], s[3], "bf16")[0] for t, s in enumerate(one)]
+    weights = [w1[t % TENSORS_PER_LAYER] for t in range(len(shapes))]
+    M = args.prefill_tokens
+    res = {}
+    for name, flags in (("cloaked", 0), ("native", C.CLOAK_IDENTITY | C.CLOAK_NATIVE)):
+        var = Variant(C, shapes, weights, cfg, flags, seed=1)
+        b = var.buffers(M)
+        cw = var.cw
+        ws, wsb = b["ws"], b["ws"].numel()
+        reps = max(args.steps // 20, 5)
+        for i in range(2):
+            C.cloak_swiglu(cw.layout, cw.pool, i, b["x"], M, b["h"], ws, wsb)
+        torch.cuda.synchronize()
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for i in range(reps):
+            C.cloak_swiglu(cw.layout, cw.pool, i % COPIES, b["x"], M, b["h"], ws, wsb)
+        z.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(z) / reps
+        fl = 2 * M * 2 * f * d
+        res[name] = dict(ms=ms, tflops=fl / ms / 1e9, frac=fl / ms / 1e9 / MFMA_BF16_PEAK_TFLOPS)
+        log(f"{name} SwiGLU GEMM {M} tokens: {ms:.3f} ms, {fl / ms / 1e9:.0f} TFLOP/s")
+        del b
+        cw.close()
+        torch.cuda.empty_cache()
+    res["library_gemm"] = vendor_gemm(M, [(2 * f, d)])
+    out = {"metric": "prefill SwiGLU GEMM TFLOP/s", "value": res["cloaked"]["tflops"], "unit": "TFLOP/s",
+           "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": f"gate/up SwiGLU GEMM of the 4096/14336 BF16 layer at {M} tokens, 2 MiB pages "
+                                  f"over an 8 GiB pool, 16 layer copies cycled"},
+           "prefill": res}
+    print(json.dumps(out), flush=True)
+
+
+def time_uniform_remap(C, shapes, cfg, reps):
+    """The uniform remap (CLOAK_REMAP_UNIFORM: a fresh rho over all pages, two
+    passes of page-pair swaps) on a layout of the same shapes and pool.  Bytes
+    moved: each swapped pair reads and writes two pages."""
+    import torch
+    cw = C.CloakedWeights(shapes, cfg["page_bytes"], cfg["pool_bytes"], seed=1, flags=C.CLOAK_REMAP_UNIFORM)
+    cw.remap(2000)
+    torch.cuda.synchronize()
+    pairs = []
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    total = 0.0
+    for r in range(reps):
+        C.cloak_remap_begin(cw.layout, 2001 + r)
+        pairs.append(C.cloak_query(cw.layout, "REMAP_PENDING"))
+        start.record()
+        C.cloak_remap_step(cw.layout, cw.pool, 0)
+        stop.record()
+        torch.cuda.synchronize()
+        total += start.elapsed_time(stop)
+    ms = total / reps
+    moved = 4 * cfg["page_bytes"] * float(np.mean(pairs))
+    cw.close()
+    return dict(ms=ms, pairs_mean=float(np.mean(pairs)), bytes_moved=moved, gbs=moved / ms / 1e6,
+                frac_of_peak=moved / ms / 1e6 / HBM_PEAK_GBS, pool_remaps_per_s=1e3 / ms)
+
+
 def copy_calibration(nbytes=1 << 30):
     """A plain elementwise copy of known size (reads and writes nbytes once);
     hardware byte counters of the decode kernels are scaled by what they read
@@ -288,35 +400,92 @@ def vendor_gemv(rows, cols, copies=16, reps=64):
     return dict(rows=rows, cols=cols, ms=ms, gbs=(rows * cols + cols + rows) * 2 / ms / 1e6)
 
 
-def cpu_oracle_baseline(cfg, weights, budget_s=12.0):
-    """The oracle's FP64 decode step (decode stored weights, then the products)."""
+def cpu_model_name():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_oracle_baseline(cfg, weights, runs=3, budget_s=4.0):
+    """The oracle's FP64 decode step (decode stored weights, then the products),
+    timed around the compute only: `runs` runs of about budget_s each with the
+    BLAS pool at its default size (median reported), then one run on 1 thread."""
     from oracle import numerics as ON
     from paper_2606_18400_amd import synth
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
+        threadpool_limits = None
         threads = os.cpu_count()
     d = cfg["d_model"]
     x = ON.bf16_bits_to_f64(synth.activations(1, d, "bf16"))
     step_bytes = sum(layer_bytes(cfg, 1))
-    steps, t0 = 0, time.perf_counter()
-    while True:
-        w = [ON.weights_f64(weights[t], "bf16") for t in range(TENSORS_PER_LAYER)]
-        for t in range(4):
-            ON.linear(x, w[t])
-        ON.swiglu_ffn(x, w[4], w[5], w[6])
-        del w
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or steps >= 20:
-            break
-    return dict(value=step_bytes * steps / el / 1e9, unit="GB/s", cores=int(threads), kind="oracle",
-                sample=f"{steps} decode steps (M=1) of one 4096/14336 BF16 layer: bf16->FP64 weight decode "
-                       f"plus FP64 products, {el:.1f} s")
+
+    def one_run(budget):
+        steps, el = 0, 0.0
+        while el < budget and steps < 20:
+            t0 = time.perf_counter()
+            w = [ON.weights_f64(weights[t], "bf16") for t in range(TENSORS_PER_LAYER)]
+            for t in range(4):
+                ON.linear(x, w[t])
+            ON.swiglu_ffn(x, w[4], w[5], w[6])
+            el += time.perf_counter() - t0
+            del w
+            steps += 1
+        return step_bytes * steps / el / 1e9, steps, el
+
+    res = [one_run(budget_s) for _ in range(runs)]
+    vals = sorted(r[0] for r in res)
+    one_thread = None
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            one_thread = one_run(budget_s)[0]
+    steps, el = sum(r[1] for r in res), sum(r[2] for r in res)
+    return dict(value=float(np.median(vals)), unit="GB/s", cores=int(threads), kind="oracle",
+                runs=[float(v) for v in vals], one_thread_value=one_thread, cpu=cpu_model_name(),
+                sample=f"{runs} runs, {steps} decode steps (M=1) in all, of one 4096/14336 BF16 layer: bf16->FP64 "
+                       f"weight decode plus FP64 products, {el:.1f} s of compute; median of the runs")
 
 
-def bench_serve(args):
+def gpu_clocks():
+    """Clocks and power of the GPU now (rocm-smi in a child process), or None."""
+    import shutil
+    import subprocess
+    exe = shutil.which("rocm-smi") or "/opt/rocm/bin/rocm-smi"
+    try:
+        r = subprocess.run([exe, "--showclocks", "--showpower", "--json"], capture_output=True, text=True,
+                           timeout=30)
+        data = json.loads(r.stdout)
+    except Exception:
+        return None
+    card = data.get("card0") or next(iter(data.values()), {})
+    keep = {}
+    for k, v in card.items():
+        kl = k.lower()
+        if "sclk" in kl or "mclk" in kl or "fclk" in kl or "power" in kl:
+            keep[k] = v
+    return keep or None
+
+
+def serve_weights():
+    """Weights of the 32-layer serving stack: one decoder layer's random weights
+    in every layer (each layer still has its own placement), embed and head."""
+    from paper_2606_18400_amd import serve, synth
+    cfg = serve.LLAMA8B
+    shapes = serve.model_shapes(cfg)
+    layer_w = [synth.weight(t, s[2], s[3], "bf16")[0] for t, s in enumerate(shapes[:TENSORS_PER_LAYER])]
+    emb = synth.weight(len(shapes) - 2, cfg["vocab"], cfg["d_model"], "bf16")[0]
+    head = synth.weight(len(shapes) - 1, cfg["vocab"], cfg["d_model"], "bf16")[0]
+    return [layer_w[t % TENSORS_PER_LAYER] for t in range(len(shapes) - 2)] + [emb, head]
+
+
+def serve_variants(weights, rates, requests, hardened=False, remap_sweep=""):
     """Serving trace on the 32-layer 4096/14336 BF16 stack (vocab 128256):
     Poisson arrivals, prompts U[128,4096], outputs U[64,1024], continuous
     batching with paged KV, remap every 256 steps (cloaked) vs the identity
@@ -325,17 +494,10 @@ def bench_serve(args):
     from paper_2606_18400_amd import cloak as C
     from paper_2606_18400_amd import serve, synth
     cfg = serve.LLAMA8B
-    shapes = serve.model_shapes(cfg)
-    log("generating weights (one decoder layer's random weights in every layer, distinct placement)")
-    layer_w = [synth.weight(t, s[2], s[3], "bf16")[0] for t, s in enumerate(shapes[:TENSORS_PER_LAYER])]
-    emb = synth.weight(len(shapes) - 2, cfg["vocab"], cfg["d_model"], "bf16")[0]
-    head = synth.weight(len(shapes) - 1, cfg["vocab"], cfg["d_model"], "bf16")[0]
-    weights = [layer_w[t % TENSORS_PER_LAYER] for t in range(len(shapes) - 2)] + [emb, head]
-    rates = [float(r) for r in args.rates.split(",")]
     results = {}
     every_default = 256
     variants = [("cloaked", 0, every_default, None), ("native", C.CLOAK_IDENTITY | C.CLOAK_NATIVE, 0, None)]
-    if args.hardened:
+    if hardened:
         # permuted heads (default), SHA-256 draws, masked device map re-keyed by every remap, decoy free pages
         variants.append(("hardened", C.CLOAK_CSPRNG | C.CLOAK_MASKED_MAP, every_default, True))
     for name, flags, every, decoy in variants:
@@ -346,7 +508,7 @@ def bench_serve(args):
         results[name] = {}
 
         def one_run(rate):
-            trace = synth.poisson_trace(args.requests, rate, 128, 4096, 64, 1024, cfg["vocab"], seed=7)
+            trace = synth.poisson_trace(requests, rate, 128, 4096, 64, 1024, cfg["vocab"], seed=7)
             reqs = [serve.Request(t["id"], t["prompt"], t["max_new"], t["arrival"]) for t in trace]
             steps0, remaps0, ms0, ev0 = eng.steps, eng.remaps, len(eng.step_ms), len(eng.remap_events)
             rep = eng.run(reqs)
@@ -368,10 +530,10 @@ def bench_serve(args):
             log(f"{name} rate {rate}/s: ttft p50 {rep['ttft_ms_p50']:.0f} p99 {rep['ttft_ms_p99']:.0f} ms, "
                 f"tpot p50 {rep['tpot_ms_p50']:.1f} p99 {rep['tpot_ms_p99']:.1f} ms, "
                 f"{rep['output_tok_per_s']:.0f} tok/s, {rep['steps']} steps, {rep['remaps']} remaps")
-        if name == "cloaked" and args.remap_sweep:
+        if name == "cloaked" and remap_sweep:
             # cadence sweep at the first rate: remap every N steps, spread over S steps (N=0: never)
             results["cadence"] = {}
-            for item in args.remap_sweep.split(","):
+            for item in remap_sweep.split(","):
                 every, slices = (int(v) for v in item.split(":"))
                 eng.remap_every, eng.remap_slices = every, slices
                 rep = one_run(rates[0])
@@ -382,7 +544,17 @@ def bench_serve(args):
                     f"{100 * rep['remap_share_of_step_time']:.2f}%")
             eng.remap_every, eng.remap_slices = every_default, 1
         eng.close()
+        del eng
         torch.cuda.empty_cache()
+    return results
+
+
+def bench_serve(args):
+    from paper_2606_18400_amd import serve
+    log("generating weights (one decoder layer's random weights in every layer, distinct placement)")
+    weights = serve_weights()
+    rates = [float(r) for r in args.rates.split(",")]
+    results = serve_variants(weights, rates, args.requests, args.hardened, args.remap_sweep)
     first = str(rates[0])
     out = {"metric": METRIC, "value": results["cloaked"][first]["output_tok_per_s"], "unit": "tokens/s",
            "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
@@ -518,6 +690,103 @@ def bench_stack(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_oracle(args):
+    """The CPU oracle timed on the host at every workload it can finish: the
+    decode step of the 4096/14336 layer, its 8192-token prefill (full FP64
+    products per tensor), the 64-layer FP8 5120/27648 stack (one layer and
+    the head timed, extrapolated to 64 layers), and the page remap of an 8 GiB
+    pool in NumPy.  Compute only, inputs made beforehand; median of `runs` runs
+    with the BLAS pool at its default size, and one run on one thread (for the
+    prefill on 512 of the 8192 tokens, scaled)."""
+    from oracle import numerics as ON
+    from oracle import remap as OR
+    from paper_2606_18400_amd import synth
+    from threadpoolctl import threadpool_info, threadpool_limits
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    runs = 3
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        fn()
+        return time.perf_counter() - t0
+
+    def med_and_one(fn, one=None, scale=1.0):
+        ts = sorted(timed(fn) for _ in range(runs))
+        with threadpool_limits(limits=1):
+            t1 = timed(one or fn) * scale
+        return dict(s_median=ts[len(ts) // 2], s_runs=ts, s_one_thread=t1)
+
+    out = {"threads": int(threads), "cpu": cpu_model_name(), "runs": runs}
+    cfg = synth.LAYER4096
+    d, f, kv = cfg["d_model"], cfg["d_ffn"], cfg["d_kv"]
+    shapes = synth.decoder_layer_shapes(d, f, kv, "bf16", layer=0)
+    log("oracle: 4096/14336 layer weights")
+    stored = [synth.weight(t, s[2], s[3], "bf16")[0] for t, s in enumerate(shapes)]
+    x1 = ON.bf16_bits_to_f64(synth.activations(1, d, "bf16"))
+
+    def decode(x):
+        # the oracle's step: exact FP64 values of the stored weights, then the products
+        w64 = [ON.weights_f64(w, "bf16") for w in stored]
+        for t in range(4):
+            ON.linear(x, w64[t])
+        ON.swiglu_ffn(x, w64[4], w64[5], w64[6])
+
+    r = med_and_one(lambda: decode(x1))
+    r["gbs_median"] = sum(layer_bytes(cfg, 1)) / r["s_median"] / 1e9
+    out["decode_layer4096_M1"] = r
+    log(f"oracle decode M=1: {r['s_median'] * 1e3:.0f} ms")
+    M = 8192
+    xp = ON.bf16_bits_to_f64(synth.activations(M, d, "bf16"))
+    r = med_and_one(lambda: decode(xp), lambda: decode(xp[:512]), M / 512)
+    r["tflops_median"] = layer_flops(cfg, M) / r["s_median"] / 1e12
+    r["note"] = "one-thread figure: 512 of the 8192 tokens, scaled by 16"
+    out["prefill_layer4096_M8192"] = r
+    log(f"oracle prefill 8192 tokens: {r['s_median']:.1f} s ({r['tflops_median'] * 1e3:.0f} GFLOP/s)")
+    del stored, xp
+    sc = synth.STACK5120
+    d, f, kv, V = sc["d_model"], sc["d_ffn"], sc["d_kv"], sc["vocab"]
+    fshapes = synth.decoder_layer_shapes(d, f, kv, "fp8", layer=0)
+    log("oracle: 5120/27648 FP8 layer and the 152064 x 5120 head")
+    fw = [synth.weight(t, s[2], s[3], "fp8") for t, s in enumerate(fshapes)]
+    head = synth.weight(7, V, d, "bf16")[0]
+    xs = ON.bf16_bits_to_f64(synth.activations(1, d, "bf16"))
+
+    def one_layer():
+        # the layer decoded from its stored E4M3 bytes and row scales, then the products
+        w = [ON.weights_f64(q, "fp8", s) for q, s in fw]
+        for t in range(4):
+            ON.linear(xs, w[t])
+        ON.swiglu_ffn(xs, w[4], w[5], w[6])
+
+    def head_step():
+        ON.linear(xs, ON.weights_f64(head, "bf16"))
+
+    r = med_and_one(one_layer)
+    rh = med_and_one(head_step)
+    r["head"] = rh
+    r["note"] = "one layer timed (s_median), the head separately; s_extrapolated = 64 layers + the head"
+    r["s_extrapolated_64_layers"] = r["s_median"] * 64 + rh["s_median"]
+    r["s_extrapolated_one_thread"] = r["s_one_thread"] * 64 + rh["s_one_thread"]
+    out["stack5120_fp8_M1"] = r
+    log(f"oracle stack: {r['s_median']:.1f} s per layer, head {rh['s_median']:.1f} s, "
+        f"64 layers ~{r['s_extrapolated_64_layers']:.0f} s")
+    del fw, head
+    B, P = 2 << 20, 4096
+    log("oracle: remap of an 8 GiB pool")
+    pool = np.zeros(B * P, np.uint8)
+    phi = list(range(P))
+    ts = []
+    for rsd in range(runs):
+        t0 = time.perf_counter()
+        OR.remap(pool, phi, 1 + rsd, B)
+        ts.append(time.perf_counter() - t0)
+    ts.sort()
+    out["remap_pool8GiB"] = dict(s_median=ts[len(ts) // 2], s_runs=ts, gbs_median=2 * B * P / ts[len(ts) // 2] / 1e9,
+                                 note="NumPy page copies into a second pool image (the oracle's definition)")
+    log(f"oracle remap of 8 GiB: {ts[len(ts) // 2]:.1f} s")
+    print(json.dumps({"metric": "CPU oracle host timings", "oracle": out}), flush=True)
+
+
 MOE = dict(slots=8, experts=128, top_k=8, d_model=2048, d_ffn=768, page_bytes=2 << 20, pool_bytes=12 << 30)
 
 
@@ -603,19 +872,24 @@ def main():
     ap.add_argument("--remap-reps", type=int, default=5)
     ap.add_argument("--prefill-tokens", type=int, default=8192, help="prefill batch (0 skips the prefill pass)")
     ap.add_argument("--moe-batches", default="1,8,32,64,256", help="moe: decode batch sizes")
-    ap.add_argument("--workload", default="layer", choices=["layer", "serve", "stack", "moe"],
+    ap.add_argument("--workload", default="layer", choices=["layer", "serve", "stack", "moe", "oracle", "prefill"],
                     help="layer: the headline decode layer (default); serve: serving trace; stack: 64-layer FP8")
     ap.add_argument("--rates", default="2,8", help="serve: Poisson arrival rates (req/s)")
     ap.add_argument("--requests", type=int, default=32, help="serve: requests per rate")
     ap.add_argument("--remap-sweep", default="",
                     help="serve: cadence sweep 'every:slices,...' (e.g. 64:1,256:1,256:32,0:1) at the first rate")
     ap.add_argument("--stack-batches", default="1,8,32,64,256", help="stack: decode batch sizes")
+    ap.add_argument("--serve-requests", type=int, default=24,
+                    help="layer: requests of the short serving pass (0 skips it)")
+    ap.add_argument("--serve-rate", type=float, default=2.0, help="layer: arrival rate of the short serving pass")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the multi-GPU (tensor-parallel) "
               "path is not built; each GPU would hold its own cloaked shard with its own seed", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "oracle":
+        return bench_oracle(args)
     import torch
     from paper_2606_18400_amd import cloak as C
     from paper_2606_18400_amd import synth
@@ -628,6 +902,8 @@ def main():
         return bench_stack(args)
     if args.workload == "moe":
         return bench_moe(args)
+    if args.workload == "prefill":
+        return bench_prefill(args)
     cfg = synth.LAYER4096
     d, f, kv = cfg["d_model"], cfg["d_ffn"], cfg["d_kv"]
     one = synth.decoder_layer_shapes(d, f, kv, "bf16", layer=0)
@@ -641,26 +917,40 @@ def main():
     cl = Variant(C, shapes, weights, cfg, 0, seed=1)
     log("uploading 16 native copies")
     nat = Variant(C, shapes, weights, cfg, C.CLOAK_IDENTITY | C.CLOAK_NATIVE, seed=1)
+    # the translating kernels on the contiguous identity layout: separates the
+    # cost of in-kernel translation from the effect of scattered placement
+    log("uploading 16 identity-layout copies for the translating kernels")
+    ident = Variant(C, shapes, weights, cfg, C.CLOAK_IDENTITY, seed=1)
+    clocks_before = gpu_clocks()
 
     step_bytes = sum(layer_bytes(cfg, 1))
     swiglu_bytes = layer_bytes(cfg, 1)[2]
     log(f"timing M=1: {args.warmup} warmup + {args.steps} steps")
-    ms, _ = time_steps(cl, 1, args.steps, args.warmup)
-    ms_nat, _ = time_steps(nat, 1, args.steps, args.warmup)
+    spread, spread_nat, spread_id = {}, {}, {}
+    ms, _ = time_steps(cl, 1, args.steps, args.warmup, spread=spread)
+    ms_nat, _ = time_steps(nat, 1, args.steps, args.warmup, spread=spread_nat)
+    ms_id, _ = time_steps(ident, 1, args.steps, args.warmup, spread=spread_id)
     # the dominant kernel alone, back to back, events around the whole loop
     k_ms = time_swiglu_loop(cl, 1, max(args.steps, 64))
     k_ms_nat = time_swiglu_loop(nat, 1, max(args.steps, 64))
     value = step_bytes / ms / 1e6
     native = step_bytes / ms_nat / 1e6
     log(f"M=1 cloaked {value:.0f} GB/s native {native:.0f} GB/s")
-    decode = {"1": dict(cloaked_gbs=value, native_gbs=native, ratio=value / native, ms=ms, native_ms=ms_nat)}
+    decode = {"1": dict(cloaked_gbs=value, native_gbs=native, ratio=value / native, ms=ms, native_ms=ms_nat,
+                        identity_translated_gbs=step_bytes / ms_id / 1e6, identity_translated_ms=ms_id,
+                        cloaked_step_ms=spread, native_step_ms=spread_nat, identity_translated_step_ms=spread_id)}
     for M in [int(m) for m in args.batches.split(",") if m]:
         b = sum(layer_bytes(cfg, M))
-        m_cl, _ = time_steps(cl, M, max(args.steps // 4, 10), args.warmup)
-        m_nat, _ = time_steps(nat, M, max(args.steps // 4, 10), args.warmup)
+        n_steps = max(args.steps // 4, 10)
+        sp, sp_nat = {}, {}
+        m_cl, _ = time_steps(cl, M, n_steps, args.warmup, spread=sp)
+        m_nat, _ = time_steps(nat, M, n_steps, args.warmup, spread=sp_nat)
+        m_id, _ = time_steps(ident, M, n_steps, args.warmup)
         decode[str(M)] = dict(cloaked_gbs=b / m_cl / 1e6, native_gbs=b / m_nat / 1e6, ratio=m_nat / m_cl,
-                              ms=m_cl, native_ms=m_nat)
-        log(f"M={M} cloaked {b / m_cl / 1e6:.0f} GB/s native {b / m_nat / 1e6:.0f} GB/s")
+                              ms=m_cl, native_ms=m_nat, identity_translated_gbs=b / m_id / 1e6,
+                              identity_translated_ms=m_id, cloaked_step_ms=sp, native_step_ms=sp_nat)
+        log(f"M={M} cloaked {b / m_cl / 1e6:.0f} GB/s native {b / m_nat / 1e6:.0f} GB/s "
+            f"identity-translated {b / m_id / 1e6:.0f} GB/s")
 
     pm = args.prefill_tokens
     prefill = None
@@ -668,15 +958,20 @@ def main():
         log(f"timing prefill M={pm}")
         p_ms, p_kms = time_prefill(cl, pm, max(args.steps // 20, 5), 2)
         n_ms, n_kms = time_prefill(nat, pm, max(args.steps // 20, 5), 2)
+        i_ms, _ = time_prefill(ident, pm, max(args.steps // 20, 5), 2)
         fl = layer_flops(cfg, pm)
         sw_fl = 2 * pm * 2 * f * d
         prefill = dict(tokens=pm, cloaked_tflops=fl / p_ms / 1e9, native_tflops=fl / n_ms / 1e9,
-                       ratio=n_ms / p_ms, ms=p_ms, native_ms=n_ms,
+                       ratio=n_ms / p_ms, ms=p_ms, native_ms=n_ms, identity_translated_tflops=fl / i_ms / 1e9,
+                       identity_translated_ms=i_ms,
                        roofline=dict(kernel="gemm_kernel SwiGLU (gate+up, bf16 MFMA)", bound="mfma",
                                      achieved=sw_fl / p_kms / 1e9, peak=MFMA_BF16_PEAK_TFLOPS, unit="TFLOP/s",
                                      frac=sw_fl / p_kms / 1e9 / MFMA_BF16_PEAK_TFLOPS, flops_per_launch=sw_fl,
                                      avg_launch_ms=p_kms, native_avg_launch_ms=n_kms))
         log(f"prefill cloaked {fl / p_ms / 1e9:.0f} TFLOP/s native {fl / n_ms / 1e9:.0f} TFLOP/s")
+        prefill["library_gemm"] = vendor_gemm(pm, [(d + 2 * kv, d), (d, d), (2 * f, d), (d, f)])
+        log("library GEMM (torch linear) at the prefill shapes: " +
+            ", ".join(f"{k} {v['tflops']:.0f}" for k, v in prefill["library_gemm"].items()) + " TFLOP/s")
     calib = copy_calibration()
     vendor = vendor_gemv(2 * f, d)
     log(f"library GEMV (torch.mv, {2 * f}x{d} bf16): {vendor['gbs']:.0f} GB/s")
@@ -685,6 +980,9 @@ def main():
     log("timing remap of the whole pool")
     remap = time_remap(cl, args.remap_reps)
     log(f"remap {remap['gbs']:.0f} GB/s vs device copy {remap['memcpy_gbs']:.0f} GB/s")
+    remap["uniform"] = time_uniform_remap(C, shapes, cfg, args.remap_reps)
+    log(f"uniform remap {remap['uniform']['ms']:.2f} ms, {remap['uniform']['gbs']:.0f} GB/s over "
+        f"{remap['uniform']['pairs_mean']:.0f} pairs")
     vmm = None
     if args.vmm:
         # the paper's own arrangement: the same cloaked layout with its pages
@@ -743,6 +1041,28 @@ def main():
                     kernel_sources=digest, read_ceiling_gbs=ceiling["gbs"],
                     frac_of_read_ceiling=achieved / ceiling["gbs"])
 
+    clocks_after = gpu_clocks()
+    contiguity = C.cloak_query(cl.cw.layout, "CONTIGUITY")
+    for v in (cl, nat, ident):
+        v.cw.close()
+    del cl, nat, ident
+    torch.cuda.empty_cache()
+
+    serving = None
+    if args.serve_requests > 0:
+        from paper_2606_18400_amd import serve
+        log(f"short serving pass: {args.serve_requests} requests at {args.serve_rate} req/s, cloaked and native")
+        sres = serve_variants(serve_weights(), [args.serve_rate], args.serve_requests)
+        key = str(float(args.serve_rate))
+        keys = ("ttft_ms_p50", "ttft_ms_p99", "tpot_ms_p50", "tpot_ms_p99", "itl_ms_p50", "itl_ms_p99",
+                "output_tok_per_s", "steps", "remaps", "completed")
+        serving = {"rate_req_s": args.serve_rate, "requests": args.serve_requests,
+                   "workload": "32-layer 4096/14336/1024 BF16 stack, vocab 128256, Poisson arrivals, prompts "
+                               "U[128,4096], outputs U[64,1024], remap every 256 steps (cloaked)"}
+        for name in ("cloaked", "native"):
+            serving[name] = {k: sres[name][key][k] for k in keys}
+        serving["tpot_p50_ratio"] = serving["native"]["tpot_ms_p50"] / serving["cloaked"]["tpot_ms_p50"]
+
     cpu = None
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")
@@ -765,11 +1085,11 @@ def main():
         "vendor_gemv": vendor,
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "contiguity": C.cloak_query(cl.cw.layout, "CONTIGUITY"),
+        "contiguity": contiguity,
+        "serving": serving,
+        "gpu_clocks": {"before": clocks_before, "after": clocks_after},
     }
     print(json.dumps(out), flush=True)
-    cl.cw.close()
-    nat.cw.close()
 
 
 if __name__ == "__main__":

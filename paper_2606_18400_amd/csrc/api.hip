@@ -413,10 +413,11 @@ struct SplitPlan {
 // the launch within one pass over MI355X's 256 CUs (one slice when the row
 // tiles alone exceed them).
 constexpr int64_t kSkinnyWideSlots = 256;
-SplitPlan plan_split(int64_t tiles_n, int64_t K, int64_t M, int32_t dtype) {
-  const int64_t nk = K / gemm_k_step();
+// a8: FP8 x FP8 tiles (K steps of 128 elements, LDS ring like BF16)
+SplitPlan plan_split(int64_t tiles_n, int64_t K, int64_t M, int32_t dtype, bool a8) {
+  const int64_t nk = K / (a8 ? gemm_k_step_a8() : gemm_k_step());
   const int64_t target = M > 64 ? 512 : 1024;
-  const bool whole_cu = M > 128 || (M > 64 && dtype == CLOAK_BF16);
+  const bool whole_cu = M > 128 || (M > 64 && (dtype == CLOAK_BF16 || a8));
   int64_t ks = whole_cu ? kSkinnyWideSlots / tiles_n : (target + tiles_n - 1) / tiles_n;
   const int64_t cap = nk / 8 > 1 ? nk / 8 : 1;
   if (ks > cap) ks = cap;
@@ -448,22 +449,26 @@ int64_t launch_rows(const cloak_layout* L, const Proj& p, int64_t tile) {
   return r;
 }
 
-// FP8 weights on the 256x256 GEMM: FP8 x FP8 MFMA on activations quantised
-// per token (the quantisation also applies the gather of a down projection)
-bool use_a8(const Proj& p, Path path) {
-  return path == kPathGemm && p.dtype == CLOAK_FP8_E4M3 && p.K % gemm_k_step_a8() == 0;
+// FP8 weights from kA8MinTokens tokens (the skinny direct-to-LDS tiles and
+// the 256x256 GEMM): FP8 x FP8 MFMA on activations quantised per token (the
+// quantisation also applies the gather of a down projection).  Below that the
+// FP8 weights are widened to BF16 and meet unquantised activations.
+constexpr int64_t kA8MinTokens = 65;
+bool use_a8(const Proj& p, Path path, int64_t M) {
+  return path != kPathGemv && M >= kA8MinTokens && p.dtype == CLOAK_FP8_E4M3 && p.K % gemm_k_step_a8() == 0;
 }
 
 uint64_t proj_ws_bytes(const cloak_layout* L, const Proj& p, int64_t M) {
   const Path path = pick_path(p.dtype, p.K, M);
+  const bool a8 = use_a8(p, path, M);
   uint64_t b = 0;
-  if (use_a8(p, path))
+  if (a8)
     b += a256(uint64_t(M) * uint64_t(p.K)) + a256(uint64_t(M) * 4);
   else if (p.gather && path != kPathGemv)
     b += a256(uint64_t(M) * uint64_t(p.K) * 2);
   if (path == kPathSkinny) {
     const int64_t lr = launch_rows(L, p, skinny_tile_rows(M));
-    const SplitPlan sp = plan_split(lr / skinny_tile_rows(M), p.K, M, p.dtype);
+    const SplitPlan sp = plan_split(lr / skinny_tile_rows(M), p.K, M, p.dtype, a8);
     b += a256(uint64_t(sp.ksplit) * uint64_t(M) * uint64_t(lr) * 4);
   }
   return b;
@@ -508,12 +513,14 @@ int run_proj(const cloak_layout* L, const void* pool, const Proj& p, const void*
     a.ldx = ldx;
     a.ldy = ldy;
     a.mode = p.mode;
+    const int xelt = p.dtype == CLOAK_F32 ? 4 : 2;
+    a.x_vec = !p.x_perm && reinterpret_cast<uintptr_t>(x) % 16 == 0 && (ldx * xelt) % 16 == 0 ? 1 : 0;
     return run_gemv(L, a, wtype_of(p.dtype), M, st, fn);
   }
   // MFMA paths read x in the tensors' stored column order
   uint8_t* wsb = static_cast<uint8_t*>(ws);
   const void* xin = x;
-  const bool a8 = use_a8(p, path);
+  const bool a8 = use_a8(p, path, M);
   float* sx = nullptr;
   if (a8) {
     uint8_t* q = wsb;
@@ -576,7 +583,7 @@ int run_proj(const cloak_layout* L, const void* pool, const Proj& p, const void*
   g.tiles_m = int32_t((M + gemm_tile_rows() - 1) / gemm_tile_rows());
   g.vec_store = aligned ? 1 : 0;
   if (path == kPathSkinny) {
-    const SplitPlan sp = plan_split(g.tiles_n, p.K, M, p.dtype);
+    const SplitPlan sp = plan_split(g.tiles_n, p.K, M, p.dtype, a8);
     g.part = reinterpret_cast<float*>(wsb);
     g.ldp = lr;
     g.ksplit = sp.ksplit;

@@ -788,18 +788,22 @@ constexpr int sds_stages() { return SBM == 256 ? 3 : 4; }
 template <int SBM>
 constexpr int sds_stage_bytes() { return (SBM + 128) * ROWB; }
 
-template <int SBM, bool TR, int EPI>
+// A8: FP8 weights meet per-token E4M3 activations (quantised beforehand) in
+// v_mfma_f32_16x16x128_f8f6f4; a K step is then 128 elements, still 128 bytes
+// of every tile row, so the ring, the loads and the swizzle are the same.
+template <int SBM, bool TR, int EPI, bool A8>
 __global__ __launch_bounds__(512) void skinny_dma_kernel(const SkinnyArgs a) {
   constexpr int SBN = 128, NW = 8;
   constexpr int SDS_STAGES = sds_stages<SBM>(), SDS_STAGE_BYTES = sds_stage_bytes<SBM>();
   constexpr int XT = SBM * ROWB;
   constexpr int XLD = SBM / 8 / NW, WLD = SBN / 8 / NW;   // wave loads per stage: 4 token, 2 weight
+  constexpr int KSTEP = A8 ? ROWB : SBK;                   // elements per K step
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];   // sds_stages * sds_stage_bytes
   const int ks = blockIdx.x % a.ksplit;
   const int tile_n = blockIdx.x / a.ksplit;
   const int kb_begin = ks * a.kblocks_per_split;
   int kb_end = kb_begin + a.kblocks_per_split;
-  if (kb_end > a.K / SBK) kb_end = a.K / SBK;
+  if (kb_end > a.K / KSTEP) kb_end = a.K / KSTEP;
   const int nloc = kb_end - kb_begin;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -810,7 +814,7 @@ __global__ __launch_bounds__(512) void skinny_dma_kernel(const SkinnyArgs a) {
   for (int j = 0; j < XLD; ++j) {
     const int r = 8 * (XLD * wave + j) + (lane >> 3);
     const int c = (lane & 7) ^ (r & 7);
-    xptr[j] = reinterpret_cast<const uint8_t*>(a.x) + int64_t(r < a.M ? r : 0) * a.ldx * 2 + c * 16;
+    xptr[j] = reinterpret_cast<const uint8_t*>(a.x) + int64_t(r < a.M ? r : 0) * a.ldx * (A8 ? 1 : 2) + c * 16;
   }
   RowRef wr[WLD];
 #pragma unroll
@@ -870,19 +874,42 @@ __global__ __launch_bounds__(512) void skinny_dma_kernel(const SkinnyArgs a) {
     if (i < 0) continue;
     const uint8_t* xs = smem + (i % SDS_STAGES) * SDS_STAGE_BYTES;
     const uint8_t* wsm = xs + XT;
+    if constexpr (A8) {
+      // a lane's 32 bytes of a 128-element K step: the same two swizzled
+      // chunks on both operands, so k pairs up whatever order the
+      // instruction uses inside its K slice
+      const int c0 = 2 * (lane >> 4);
+      auto frag = [&](const uint8_t* tile, int r) {
+        const u32x4 lo = *reinterpret_cast<const u32x4*>(tile + swz(r, c0));
+        const u32x4 hi = *reinterpret_cast<const u32x4*>(tile + swz(r, c0 + 1));
+        return i32x8{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
+      };
+      i32x8 fa[RB];
 #pragma unroll
-    for (int s = 0; s < SBK / 32; ++s) {
-      const int chunk = s * 4 + (lane >> 4);
-      bf16x8_t fa[RB];
-#pragma unroll
-      for (int b = 0; b < RB; ++b)
-        fa[b] = *reinterpret_cast<const bf16x8_t*>(wsm + swz(wrow + b * 16 + (lane & 15), chunk));
+      for (int b = 0; b < RB; ++b) fa[b] = frag(wsm, wrow + b * 16 + (lane & 15));
 #pragma unroll
       for (int j = 0; j < TB; ++j) {
-        const int mb = gt * TB + j;
-        const bf16x8_t fb = *reinterpret_cast<const bf16x8_t*>(xs + swz(mb * 16 + (lane & 15), chunk));
+        const i32x8 fb = frag(xs, (gt * TB + j) * 16 + (lane & 15));
 #pragma unroll
-        for (int b = 0; b < RB; ++b) acc[b][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[b], fb, acc[b][j], 0, 0, 0);
+        for (int b = 0; b < RB; ++b)
+          acc[b][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fa[b], fb, acc[b][j], 0, 0, 0, 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < SBK / 32; ++s) {
+        const int chunk = s * 4 + (lane >> 4);
+        bf16x8_t fa[RB];
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+          fa[b] = *reinterpret_cast<const bf16x8_t*>(wsm + swz(wrow + b * 16 + (lane & 15), chunk));
+#pragma unroll
+        for (int j = 0; j < TB; ++j) {
+          const int mb = gt * TB + j;
+          const bf16x8_t fb = *reinterpret_cast<const bf16x8_t*>(xs + swz(mb * 16 + (lane & 15), chunk));
+#pragma unroll
+          for (int b = 0; b < RB; ++b)
+            acc[b][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[b], fb, acc[b][j], 0, 0, 0);
+        }
       }
     }
     asm volatile("" ::: "memory");
@@ -919,6 +946,10 @@ __global__ __launch_bounds__(256) void skinny_reduce_kernel(const SkinnyArgs a) 
         g += p[rg];
         u += p[ru];
       }
+      if (a.a8) {
+        g *= a.sx[m];
+        u *= a.sx[m];
+      }
       if (a.seg[0].scale) g *= a.seg[0].scale[c];
       if (a.seg[1].scale) u *= a.seg[1].scale[c];
       static_cast<uint16_t*>(a.y)[int64_t(m) * a.ldy + c] = f32_to_bf16_rne(g / (1.0f + expf(-g)) * u);
@@ -931,6 +962,7 @@ __global__ __launch_bounds__(256) void skinny_reduce_kernel(const SkinnyArgs a) 
       if (n >= a.seg[seg].rows) continue;
       float v = 0.f;
       for (int ks = 0; ks < a.ksplit; ++ks) v += a.part[(int64_t(ks) * a.M + m) * a.ldp + c];
+      if (a.a8) v *= a.sx[m];
       if (a.seg[seg].scale) v *= a.seg[seg].scale[n];
       const int32_t* perm = a.seg[seg].out_perm;
       static_cast<uint16_t*>(a.y)[int64_t(m) * a.ldy + a.seg[seg].out_off + (perm ? perm[n] : n)] =
@@ -1190,11 +1222,16 @@ void (*skinny_fn2(bool translate, int mode))(const SkinnyArgs) {
   return translate ? skinny_kernel<SBM, true, kStore, F8> : skinny_kernel<SBM, false, kStore, F8>;
 }
 
-template <int SBM>
-void (*skinny_dma_fn(bool translate, int mode))(const SkinnyArgs) {
+template <int SBM, bool A8>
+void (*skinny_dma_fn2(bool translate, int mode))(const SkinnyArgs) {
   if (mode == kSwiGLU)
-    return translate ? skinny_dma_kernel<SBM, true, kSwiGLU> : skinny_dma_kernel<SBM, false, kSwiGLU>;
-  return translate ? skinny_dma_kernel<SBM, true, kStore> : skinny_dma_kernel<SBM, false, kStore>;
+    return translate ? skinny_dma_kernel<SBM, true, kSwiGLU, A8> : skinny_dma_kernel<SBM, false, kSwiGLU, A8>;
+  return translate ? skinny_dma_kernel<SBM, true, kStore, A8> : skinny_dma_kernel<SBM, false, kStore, A8>;
+}
+
+template <int SBM>
+void (*skinny_dma_fn(bool translate, int mode, bool a8))(const SkinnyArgs) {
+  return a8 ? skinny_dma_fn2<SBM, true>(translate, mode) : skinny_dma_fn2<SBM, false>(translate, mode);
 }
 
 template <int SBM>
@@ -1206,17 +1243,19 @@ hipError_t launch_skinny(const SkinnyArgs& a, bool translate, hipStream_t s) {
   const int64_t blocks = int64_t(a.tiles_n) * a.ksplit;
   if (blocks <= 0 || a.M <= 0) return hipSuccess;
   if (a.M > kSkinnyMaxTokens || a.K % SBK != 0 || a.tile_rows != skinny_tile_rows(a.M)) return hipErrorInvalidValue;
-  const bool f8 = a.f8 != 0;
+  const bool f8 = a.f8 != 0, a8 = a.a8 != 0;
+  // FP8 x FP8 runs only on the direct-to-LDS tiles (above 64 tokens), in K steps of 128
+  if (a8 && (!f8 || a.M <= 64 || a.K % (2 * SBK) != 0 || !a.sx)) return hipErrorInvalidValue;
   void (*fn)(const SkinnyArgs);
   int lds;
   if (a.M <= 16) fn = skinny_fn<16>(translate, a.mode, f8), lds = skinny_lds_bytes<16>();
   else if (a.M <= 32) fn = skinny_fn<32>(translate, a.mode, f8), lds = skinny_lds_bytes<32>();
   else if (a.M <= 64) fn = skinny_fn<64>(translate, a.mode, f8), lds = skinny_lds_bytes<64>();
-  else if (f8 && a.M <= 128) fn = skinny_fn<128>(translate, a.mode, f8), lds = skinny_lds_bytes<128>();
-  else if (f8) fn = skinny_fn<256>(translate, a.mode, f8), lds = skinny_lds_bytes<256>();
-  else if (a.M <= 128) fn = skinny_dma_fn<128>(translate, a.mode), lds = sds_stages<128>() * sds_stage_bytes<128>();
-  else fn = skinny_dma_fn<256>(translate, a.mode), lds = sds_stages<256>() * sds_stage_bytes<256>();
-  const bool wide = a.M > 128 || (a.M > 64 && !f8);   // 8-wave tiles
+  else if (f8 && !a8 && a.M <= 128) fn = skinny_fn<128>(translate, a.mode, f8), lds = skinny_lds_bytes<128>();
+  else if (f8 && !a8) fn = skinny_fn<256>(translate, a.mode, f8), lds = skinny_lds_bytes<256>();
+  else if (a.M <= 128) fn = skinny_dma_fn<128>(translate, a.mode, a8), lds = sds_stages<128>() * sds_stage_bytes<128>();
+  else fn = skinny_dma_fn<256>(translate, a.mode, a8), lds = sds_stages<256>() * sds_stage_bytes<256>();
+  const bool wide = a.M > 128 || (a.M > 64 && (!f8 || a8));   // 8-wave tiles
   if (lds > 64 * 1024)
     if (hipError_t e = raise_lds_limit(reinterpret_cast<const void*>(fn), lds)) return e;
   hipLaunchKernelGGL(fn, dim3(unsigned(blocks)), dim3(unsigned(wide ? 512 : STHREADS)), size_t(lds), s, a);

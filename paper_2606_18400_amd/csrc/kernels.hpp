@@ -61,7 +61,7 @@ struct GemvArgs {
   int64_t ldx, ldy;
   int32_t m0, mcount;       // token block handled by this launch
   int32_t mode;             // Epilogue
-  int32_t pad;
+  int32_t x_vec;            // 1: x unpermuted, 16-byte aligned rows (lanes load x 16 B at a time)
 };
 
 // Decode GEMV (VALU dot products, wave-level K split, 1 KiB page-translated

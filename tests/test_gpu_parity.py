@@ -72,7 +72,7 @@ def test_upload_order_is_kept_by_the_library(C):
     tensor already uploaded may be sent again."""
     import torch
     shapes = decoder_shapes(512, 1024, 128, "bf16", layers=2)
-    B, P = 65536, 128
+    B, P = 65536, 256
     ws, scs = make_weights(shapes)
     lay_c = C.cloak_layout_build(11, shapes, B, B * P)
     C.cloak_layout_to_device(lay_c)
@@ -712,10 +712,11 @@ def test_prefill_gemm_cloaked_equals_native(C, M):
 
 @pytest.mark.parametrize("M", [5, 17, 64, 128, 256, 300])
 def test_fp8_mfma_paths_vs_fp64(C, M):
-    # FP8 weights through the MFMA paths: up to 256 tokens the skinny split-K
+    # FP8 weights through the MFMA paths: up to 64 tokens the skinny split-K
     # kernel widens them to BF16 exactly in LDS (row scales applied after the
-    # contraction); above, FP8 x FP8 on quantised activations.  K = 1280 /
-    # 3456, d_ffn 3456 and the 700-row head leave ragged row tiles
+    # contraction); from 65 tokens, FP8 x FP8 on quantised activations (the
+    # skinny direct-to-LDS tiles, then the 256x256 GEMM).  K = 1280 / 3456,
+    # d_ffn 3456 and the 700-row head leave ragged row tiles
     shapes = decoder_shapes(1280, 3456, 256, "fp8", layers=1, extra=[(-1, "head", 700, 1280, "fp8")])
     ws, scs = make_weights(shapes)
     cw = C.CloakedWeights(shapes, 65536, 65536 * 512, seed=29)
@@ -768,7 +769,7 @@ def test_fp8_mfma_one_hot_bit_exact(C, M):
         ws_buf = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
         y = torch.empty((M, s[2]), dtype=torch.bfloat16, device="cuda")
         C.cloak_linear(cw.layout, cw.pool, t, to_device_x(x), M, y, ws_buf, ws_buf.numel())
-        want = one_hot_expected(shapes, ws, scs, t, ks) if M <= 256 else one_hot_expected_a8(shapes, ws, scs, t, ks)
+        want = one_hot_expected(shapes, ws, scs, t, ks) if M <= 64 else one_hot_expected_a8(shapes, ws, scs, t, ks)
         assert np.array_equal(plus_zero(from_device(y)), want), (t, s)
     cw.close()
 
@@ -790,10 +791,11 @@ def test_quantize_fp8_codes_and_scales_bit_exact(C):
         assert np.array_equal(sc.cpu().numpy().view(np.uint32), ws_.view(np.uint32)), (M, K)
 
 
-@pytest.mark.parametrize("M", [257, 600])
+@pytest.mark.parametrize("M", [65, 128, 200, 256, 257, 600])
 def test_fp8_x_fp8_gemm_vs_oracle(C, M):
-    # above 256 tokens FP8 weights run FP8 x FP8 MFMA on per-token quantised
-    # activations: against the oracle's product of the same quantised
+    # from 65 tokens FP8 weights run FP8 x FP8 MFMA on per-token quantised
+    # activations (65..256: the skinny split-K direct-to-LDS tiles; above:
+    # the 256x256 GEMM): against the oracle's product of the same quantised
     # activations the only differences are FP32 summation order and the bf16
     # output rounding (1e-2); against unquantised FP64 the FP8 bar (5e-2)
     shapes = decoder_shapes(1280, 3456, 256, "fp8", layers=1)
