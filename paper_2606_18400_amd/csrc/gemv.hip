@@ -160,25 +160,41 @@ __device__ inline void load_x(const GemvArgs& a, int c, int m, int lane, uint32_
   }
 }
 
-// This lane's 16 B of chunk c of a row: p0 is the physical page holding the
-// chunk's first byte, p1 the next page (used only by lanes past a page
-// boundary, in rows whose size is not a multiple of 1 KiB), inpage the
-// chunk's offset in p0.  The load is unconditional (lanes past the end of
-// the row read the chunk's first 16 B, which lie in the row) so that a wave's
-// loads form one straight-line batch; the caller zeroes what lies past the
-// row.
-__device__ inline u32x4 load_chunk(const GemvArgs& a, uint32_t p0, uint32_t p1, uint32_t inpage, int lane,
-                                   bool lane_ok) {
-  const uint32_t page_bytes = 1u << a.log2_page;
-  const uint32_t lo = inpage + (lane_ok ? uint32_t(lane) * 16u : 0u);
-  const bool second = lo >= page_bytes;
-  const uint64_t phys = second ? p1 : p0;
-  const uint8_t* addr = a.pool + (phys << a.log2_page) + (second ? lo - page_bytes : lo);
-  return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(addr));
+// Where chunk c of stored row n lives: the physical pages holding its first
+// byte (p0) and, for a chunk that crosses a page boundary (rows whose size
+// is not a multiple of 1 KiB), the next one (p1); `inpage` is the chunk's
+// offset in p0.  All wave-uniform: scalar loads only.
+struct ChunkLoc {
+  int64_t p0, p1, inpage;
+};
+
+// TR: 0 untranslated twin, 1 plain page map, 2 masked page map
+template <int TR>
+__device__ inline ChunkLoc locate(const GemvArgs& a, const SegView& v, int n, int c) {
+  const int64_t o = int64_t(n) * a.row_bytes + int64_t(c) * kChunkBytes;
+  const int64_t page_bytes = int64_t(1) << a.log2_page;
+  const int64_t vp = o >> a.log2_page;
+  ChunkLoc L;
+  L.inpage = o & (page_bytes - 1);
+  const int64_t vpage = v.vbase + vp;
+  // the second lookup is unconditional (index clamped to the tensor's last
+  // page) so that both scalar loads of every row can be in flight together
+  const int64_t vnext = vp + 1 < v.npages ? vpage + 1 : vpage;
+  L.p0 = TR ? page_of<TR == 2>(a.phi, a.phi_key, vpage) : vpage;
+  L.p1 = TR ? page_of<TR == 2>(a.phi, a.phi_key, vnext) : vnext;
+  return L;
 }
 
-__device__ inline u32x4 keep_if(bool ok, const u32x4 w) {
-  return u32x4{ok ? w.x : 0u, ok ? w.y : 0u, ok ? w.z : 0u, ok ? w.w : 0u};
+// This lane's 16 B of a located chunk (zero past the end of the row).
+__device__ inline u32x4 load_chunk(const GemvArgs& a, const ChunkLoc& L, int lane, bool lane_ok) {
+  const int64_t page_bytes = int64_t(1) << a.log2_page;
+  const int64_t lo = L.inpage + int64_t(lane) * 16;
+  const bool second = lo >= page_bytes;
+  const int64_t phys = second ? L.p1 : L.p0;
+  const uint8_t* addr = a.pool + (phys << a.log2_page) + (second ? lo - page_bytes : lo);
+  u32x4 w = {0u, 0u, 0u, 0u};
+  if (lane_ok) w = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(addr));
+  return w;
 }
 
 template <int WT>
@@ -245,64 +261,33 @@ struct GroupLoads {
   u32x4 w[CPW][R];
 };
 
-// Issue every weight load of group `grp` for this wave, one chunk slot at a
-// time: the R page lookups of a slot go out as one batch of scalar loads
-// (plus a second batch for rows whose size is not a multiple of 1 KiB, where
-// a chunk can cross into the next page), then its R independent 16 B loads
-// per lane follow with no branch in between.  A slot past the row's last
-// chunk loads nothing; rows past the tensor load row 0 (valid memory) and
-// are zeroed afterwards.
+// Issue every weight load of group `grp` for this wave (page lookups first,
+// as one batch of scalar loads, then R*CPW independent 16 B loads per lane).
 template <int WT, int R, int CPW, int TR, int EPI>
 __device__ inline void issue_group(const GemvArgs& a, int grp, int wave, int nwaves, int lane,
                                    GroupLoads<WT, R, CPW, TR, EPI>& L) {
   constexpr int EPL = WTraits<WT>::EPL;
   const SegView sv = seg_at(a, EPI == kSwiGLU ? 0 : group_segment<R, EPI>(a, grp));
   const SegView up = seg_at(a, EPI == kSwiGLU ? 1 : 0);
-  const bool whole_kib = (a.row_bytes & (kChunkBytes - 1)) == 0;
-  const int64_t page_mask = (int64_t(1) << a.log2_page) - 1;
 #pragma unroll
   for (int i = 0; i < CPW; ++i) {
     const int c = wave + i * nwaves;
-    if (c >= a.nchunks) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) L.w[i][r] = u32x4{0u, 0u, 0u, 0u};
-      continue;
-    }
-    const bool lane_ok = (c * 64 * EPL + lane * EPL) < a.K;
-    uint32_t p0[R], p1[R], inp[R];
-    int64_t vp[R], vl[R];
+    const bool c_ok = c < a.nchunks;
+    const int cc = c_ok ? c : 0;
+    const bool lane_ok = (cc * 64 * EPL + lane * EPL) < a.K;
+    ChunkLoc loc[R];
     bool rok[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int n = EPI == kSwiGLU ? grp * (R / 2) + (r % (R / 2)) : grp * R + r - sv.row0;
       const SegView v = (EPI == kSwiGLU && r >= R / 2) ? up : sv;
-      rok[r] = n < v.rows;
-      const int64_t o = int64_t(rok[r] ? n : 0) * a.row_bytes + int64_t(c) * kChunkBytes;
-      vp[r] = uniform64(v.vbase + (o >> a.log2_page));
-      vl[r] = v.vbase + v.npages - 1;
-      inp[r] = uint32_t(o & page_mask);
-    }
-    // one branch around a whole batch, so each batch stays straight-line
-    if (whole_kib) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        p0[r] = TR ? uint32_t(page_of<TR == 2>(a.phi, a.phi_key, vp[r])) : uint32_t(vp[r]);
-        p1[r] = p0[r];
-      }
-    } else {
-      // also the next page (clamped to the tensor's last one); only lanes
-      // past a page boundary use it
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int64_t vnext = vp[r] + 1 <= vl[r] ? vp[r] + 1 : vl[r];
-        p0[r] = TR ? uint32_t(page_of<TR == 2>(a.phi, a.phi_key, vp[r])) : uint32_t(vp[r]);
-        p1[r] = TR ? uint32_t(page_of<TR == 2>(a.phi, a.phi_key, vnext)) : uint32_t(vnext);
-      }
+      rok[r] = c_ok && n < v.rows;
+      // rows past the end look up row 0 (always valid) and skip their load
+      loc[r] = locate<TR>(a, v, rok[r] ? n : 0, cc);
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r) L.w[i][r] = load_chunk(a, p0[r], p1[r], inp[r], lane, lane_ok);
-#pragma unroll
-    for (int r = 0; r < R; ++r) L.w[i][r] = keep_if(rok[r] && lane_ok, L.w[i][r]);
+    for (int r = 0; r < R; ++r)
+      L.w[i][r] = rok[r] ? load_chunk(a, loc[r], lane, lane_ok) : u32x4{0u, 0u, 0u, 0u};
   }
 }
 

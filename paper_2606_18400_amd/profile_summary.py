@@ -3,6 +3,7 @@
 Usage:
   python -m paper_2606_18400_amd.profile_summary stats <kernel_stats.csv | results.db> [--top N]
   python -m paper_2606_18400_amd.profile_summary trace <kernel_trace.csv> [--match moe]
+  python -m paper_2606_18400_amd.profile_summary counters <counter_collection.csv> [...] [--match gemm]
   python -m paper_2606_18400_amd.profile_summary pmc <fetch counter_collection.csv> <write counter_collection.csv>
           [--copy-match MulFunctor] [--copy-bytes 1073741824]
 
@@ -13,6 +14,14 @@ microseconds and total milliseconds, sorted by total time (CSV from
 `trace` prints, per (kernel, grid), dispatch count and average duration from
 the per-dispatch CSV of `--kernel-trace` (grid sizes separate the batch sizes
 of one run).
+
+`counters` prints, per kernel (and grid), the mean per dispatch of every
+counter in one or more `--pmc` passes (counter_collection.csv files), with
+the derived figures the SQ counters allow: MFMA busy share
+(SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE x SIMDs; GRBM_GUI_ACTIVE is
+summed over the XCDs, `--xcds`), LDS active share (SQ_LDS_IDX_ACTIVE over
+the cycles of every CU) and the share of wave time spent
+waiting (SQ_WAIT_ANY over SQ_WAVE_CYCLES).
 
 `pmc` reads one `--pmc FETCH_SIZE` and one `--pmc WRITE_SIZE` pass (KiB per
 dispatch) and scales each counter by what it reads for a plain elementwise
@@ -93,6 +102,32 @@ def print_pmc(fetch_csv, write_csv, copy_match, copy_bytes):
               f"{short_name(k[0])[:80]} ({k[1]})")
 
 
+def print_counters(paths, match, cus, simds_per_cu, xcds):
+    d = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path in paths:
+        for r in csv.DictReader(open(path)):
+            if match and match not in r["Kernel_Name"]:
+                continue
+            d[(short_name(r["Kernel_Name"]).split("(")[0], r["Grid_Size"])][r["Counter_Name"]].append(
+                float(r["Counter_Value"]))
+    for (k, grid), cs in sorted(d.items()):
+        m = {c: sum(v) / len(v) for c, v in cs.items()}
+        n = max(len(v) for v in cs.values())
+        print(f"{k[:100]}  grid {grid}  ({n} dispatches per pass)")
+        for c in sorted(m):
+            print(f"    {c:36s} {m[c]:16.6g}")
+        g = m.get("GRBM_GUI_ACTIVE")
+        if g:
+            cyc = g / xcds
+            if "SQ_VALU_MFMA_BUSY_CYCLES" in m:
+                print(f"    -> MFMA busy {100 * m['SQ_VALU_MFMA_BUSY_CYCLES'] / (cyc * cus * simds_per_cu):.1f}% "
+                      f"of {cyc:.4g} cycles per XCD")
+            if "SQ_LDS_IDX_ACTIVE" in m:
+                print(f"    -> LDS active {100 * m['SQ_LDS_IDX_ACTIVE'] / (cyc * cus):.1f}% of CU cycles")
+        if "SQ_WAIT_ANY" in m and "SQ_WAVE_CYCLES" in m:
+            print(f"    -> waves waiting {100 * m['SQ_WAIT_ANY'] / m['SQ_WAVE_CYCLES']:.1f}% of wave time")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -102,6 +137,12 @@ def main(argv=None):
     t = sub.add_parser("trace")
     t.add_argument("path")
     t.add_argument("--match", default="")
+    c = sub.add_parser("counters")
+    c.add_argument("paths", nargs="+")
+    c.add_argument("--match", default="")
+    c.add_argument("--cus", type=int, default=256)
+    c.add_argument("--simds-per-cu", type=int, default=4)
+    c.add_argument("--xcds", type=int, default=8)
     p = sub.add_parser("pmc")
     p.add_argument("fetch_csv")
     p.add_argument("write_csv")
@@ -112,6 +153,8 @@ def main(argv=None):
         print_stats(a.path, a.top)
     elif a.cmd == "trace":
         print_trace(a.path, a.match)
+    elif a.cmd == "counters":
+        print_counters(a.paths, a.match, a.cus, a.simds_per_cu, a.xcds)
     else:
         print_pmc(a.fetch_csv, a.write_csv, a.copy_match, a.copy_bytes)
 
