@@ -503,10 +503,13 @@ typedef struct {
  * are consecutive in the arrays with consecutive positions; its KV blocks are
  * block_table[seq][0 .. ceil(ctx/block_size)).  Attention work: n_tiles tiles
  * of <= 16 consecutive tokens of one sequence (tile_seq/tok0/ntok), the
- * context cut into n_splits slices of split_keys keys. */
+ * context cut into n_splits slices of split_keys keys.  The first n_single
+ * tiles are expected to hold one token each (decode tokens): they run on the
+ * single-token attention path, which still computes any tile correctly but
+ * is slow on long ones.  0 <= n_single <= n_tiles. */
 typedef struct {
   int32_t n_tokens, n_seqs, max_blocks, n_logits;
-  int32_t n_tiles, n_splits, split_keys, reserved;
+  int32_t n_tiles, n_splits, split_keys, n_single;
   const int32_t* d_tokens;       /* [n_tokens] token ids (< vocab)            */
   const int32_t* d_positions;    /* [n_tokens]                                */
   const int32_t* d_tok_seq;      /* [n_tokens] sequence slot of each token    */

@@ -66,7 +66,7 @@ class cloak_model_config(ctypes.Structure):
 class cloak_step(ctypes.Structure):
     _fields_ = [("n_tokens", ctypes.c_int32), ("n_seqs", ctypes.c_int32), ("max_blocks", ctypes.c_int32),
                 ("n_logits", ctypes.c_int32), ("n_tiles", ctypes.c_int32), ("n_splits", ctypes.c_int32),
-                ("split_keys", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("split_keys", ctypes.c_int32), ("n_single", ctypes.c_int32),
                 ("d_tokens", ctypes.c_void_p), ("d_positions", ctypes.c_void_p), ("d_tok_seq", ctypes.c_void_p),
                 ("d_block_table", ctypes.c_void_p), ("d_tile_seq", ctypes.c_void_p),
                 ("d_tile_tok0", ctypes.c_void_p), ("d_tile_ntok", ctypes.c_void_p),

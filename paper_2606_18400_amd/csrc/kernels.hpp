@@ -200,6 +200,8 @@ struct AttnArgs {
   const int32_t* positions;
   int32_t n_tiles, n_splits, split_keys;
   int32_t n_heads, n_kv;
+  int32_t n_single;         // leading tiles expected to hold one token each
+  int32_t tile0;            // first tile of a launch (set by launch_attention)
   float scale;
   float* part_o;            // [tiles][n_kv][splits][group][16][128]
   float* part_ml;           // [tiles][n_kv][splits][group][16][2]

@@ -199,7 +199,7 @@ extern "C" int cloak_model_step(cloak_model* m, const cloak_step* s, void* d_ws,
   const cloak_model_config& c = m->cfg;
   const int64_t T = s->n_tokens, R = s->n_logits;
   if (T <= 0 || s->n_seqs <= 0 || R < 0 || R > T || s->max_blocks <= 0 || s->n_tiles <= 0 || s->n_splits <= 0 ||
-      s->split_keys <= 0 || !s->d_tokens || !s->d_positions || !s->d_tok_seq || !s->d_block_table ||
+      s->split_keys <= 0 || s->n_single < 0 || s->n_single > s->n_tiles || !s->d_tokens || !s->d_positions || !s->d_tok_seq || !s->d_block_table ||
       !s->d_tile_seq || !s->d_tile_tok0 || !s->d_tile_ntok || (R > 0 && (!s->d_logit_rows || !s->d_out_tokens))) {
     set_error("cloak_model_step: bad batch description");
     return CLOAK_EINVAL;
@@ -284,6 +284,7 @@ extern "C" int cloak_model_step(cloak_model* m, const cloak_step* s, void* d_ws,
     aa.tile_ntok = s->d_tile_ntok;
     aa.positions = s->d_positions;
     aa.n_tiles = s->n_tiles;
+    aa.n_single = s->n_single;
     aa.n_splits = s->n_splits;
     aa.split_keys = s->split_keys;
     aa.n_heads = c.n_heads;

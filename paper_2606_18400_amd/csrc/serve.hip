@@ -18,6 +18,7 @@ namespace cloak {
 namespace {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -48,6 +49,67 @@ __global__ __launch_bounds__(256) void embed_kernel(const EmbedArgs a) {
 // ------------------------------------------------------------------ RMSNorm
 // row i of the output uses source row rows[i] (or i): r = x + add, rounded
 // to bf16 (and stored to r_out when given); h = r / sqrt(mean(r^2) + eps) * g.
+// Rows of D % 8 == 0 and D <= 8 * 256 * kNormChunks: each thread keeps its
+// 16-byte chunks of the row in registers (one read of x and add).
+constexpr int kNormChunks = 4;
+
+__device__ inline float block_sum256(float v, float* red) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float tot = 0.f;
+  for (int w = 0; w < int(blockDim.x >> 6); ++w) tot += red[w];
+  return tot;
+}
+
+__global__ __launch_bounds__(256) void rmsnorm_vec_kernel(const NormArgs a) {
+  const int i = blockIdx.x;
+  const int src = a.rows ? a.rows[i] : i;
+  const int nch = a.D / 8;
+  const u32x4* x = reinterpret_cast<const u32x4*>(a.x + int64_t(src) * a.D);
+  const u32x4* add = a.add ? reinterpret_cast<const u32x4*>(a.add + int64_t(src) * a.D) : nullptr;
+  __shared__ float red[8];
+  float r[kNormChunks][8];
+  float ss = 0.f;
+#pragma unroll
+  for (int j = 0; j < kNormChunks; ++j) {
+    const int c = threadIdx.x + j * 256;
+    if (c >= nch) break;
+    const u32x4 xv = x[c];
+    u32x4 av = {0u, 0u, 0u, 0u};
+    if (add) av = add[c];
+    const uint32_t xw[4] = {xv.x, xv.y, xv.z, xv.w}, aw[4] = {av.x, av.y, av.z, av.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      float v = bf2f(uint16_t(xw[e / 2] >> (16 * (e & 1))));
+      if (add) v = bf2f(f2bf(v + bf2f(uint16_t(aw[e / 2] >> (16 * (e & 1))))));
+      r[j][e] = v;
+      ss += v * v;
+    }
+  }
+  const float inv = rsqrtf(block_sum256(ss, red) / float(a.D) + a.eps);
+  u32x4* r_out = a.r_out ? reinterpret_cast<u32x4*>(a.r_out + int64_t(src) * a.D) : nullptr;
+  u32x4* h = reinterpret_cast<u32x4*>(a.h + int64_t(i) * a.D);
+  const u32x4* gain = a.gain ? reinterpret_cast<const u32x4*>(a.gain) : nullptr;
+#pragma unroll
+  for (int j = 0; j < kNormChunks; ++j) {
+    const int c = threadIdx.x + j * 256;
+    if (c >= nch) break;
+    u32x4 gv = {0x3F803F80u, 0x3F803F80u, 0x3F803F80u, 0x3F803F80u};   // bf16 ones
+    if (gain) gv = gain[c];
+    const uint32_t gw[4] = {gv.x, gv.y, gv.z, gv.w};
+    uint32_t ho[4], ro[4];
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) {
+      const float g0 = bf2f(uint16_t(gw[e / 2])), g1 = bf2f(uint16_t(gw[e / 2] >> 16));
+      ho[e / 2] = uint32_t(f2bf(r[j][e] * inv * g0)) | (uint32_t(f2bf(r[j][e + 1] * inv * g1)) << 16);
+      ro[e / 2] = uint32_t(f2bf(r[j][e])) | (uint32_t(f2bf(r[j][e + 1])) << 16);
+    }
+    h[c] = u32x4{ho[0], ho[1], ho[2], ho[3]};
+    if (r_out) r_out[c] = u32x4{ro[0], ro[1], ro[2], ro[3]};
+  }
+}
+
 __global__ __launch_bounds__(256) void rmsnorm_kernel(const NormArgs a) {
   const int i = blockIdx.x;
   const int src = a.rows ? a.rows[i] : i;
@@ -80,6 +142,7 @@ __global__ __launch_bounds__(256) void rmsnorm_kernel(const NormArgs a) {
 // ------------------------------------------------------------------ RoPE + KV write
 // Rotate-half convention: pair (i, i + d/2) turns by pos * theta^(-2i/d).
 // Angles are formed in double so long positions keep their accuracy.
+constexpr int kMaxHalf = 64;   // head_dim 128
 __global__ __launch_bounds__(256) void rope_kv_kernel(const RopeArgs a) {
   const int t = blockIdx.x;
   const int pos = a.positions[t];
@@ -93,13 +156,20 @@ __global__ __launch_bounds__(256) void rope_kv_kernel(const RopeArgs a) {
   const int off = pos % a.bs;
   uint16_t* row = a.qkv + int64_t(t) * a.ldqkv;
   const int nq = a.n_heads * half, nk = a.n_kv * half;
+  // every head turns pair i by the same angle: half cosines and sines per token
+  __shared__ float cs[2][kMaxHalf];
+  for (int i = threadIdx.x; i < half; i += blockDim.x) {
+    const double ang = double(pos) * pow(double(a.theta), -2.0 * double(i) / double(a.hd));
+    cs[0][i] = float(cos(ang));
+    cs[1][i] = float(sin(ang));
+  }
+  __syncthreads();
   for (int it = threadIdx.x; it < nq + 2 * nk; it += blockDim.x) {
     if (it < nq + nk) {
       const bool is_q = it < nq;
       const int j = is_q ? it : it - nq;
       const int head = j / half, i = j % half;
-      const double ang = double(pos) * pow(double(a.theta), -2.0 * double(i) / double(a.hd));
-      const float c = float(cos(ang)), s = float(sin(ang));
+      const float c = cs[0][i], s = cs[1][i];
       uint16_t* base = row + (is_q ? head * a.hd : (a.n_heads + head) * a.hd);
       const float x1 = bf2f(base[i]), x2 = bf2f(base[i + half]);
       const uint16_t y1 = f2bf(x1 * c - x2 * s), y2 = f2bf(x2 * c + x1 * s);
@@ -138,11 +208,16 @@ constexpr int kKB = 64;   // keys per block
 __device__ inline int kswz(int key, int chunk) { return key * (kHD * 2) + ((chunk ^ (key & 15)) << 4); }
 __device__ inline int vswz(int dim, int chunk) { return dim * (kKB * 2) + ((chunk ^ (dim & 7)) << 4); }
 
-__global__ __launch_bounds__(512) void attention_kernel(const AttnArgs a) {
+// One block per (tile, kv head, key slice), one wave per query head of the
+// group.  The next 64 keys are fetched into registers while the current 64
+// are multiplied out of LDS.
+template <int GROUP>
+__global__ __launch_bounds__(64 * GROUP) void attention_kernel(const AttnArgs a) {
+  constexpr int NT = 64 * GROUP;
+  constexpr int NPT = (kKB * 16 + NT - 1) / NT;   // 16-byte K (and V) chunks per thread
   __shared__ __attribute__((aligned(16))) uint8_t kl[kKB * kHD * 2];
   __shared__ __attribute__((aligned(16))) uint8_t vl[kKB * kHD * 2];
-  const int nthreads = blockDim.x;
-  const int group = nthreads >> 6;
+  constexpr int group = GROUP;
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int g = lane >> 4, col = lane & 15;
@@ -151,13 +226,16 @@ __global__ __launch_bounds__(512) void attention_kernel(const AttnArgs a) {
   const int sp = b % a.n_splits;
   b /= a.n_splits;
   const int kvh = b % a.n_kv;
-  const int tile = b / a.n_kv;
+  const int tile = a.tile0 + b / a.n_kv;
   const int seq = a.tile_seq[tile];
   const int tok0 = a.tile_tok0[tile];
   const int ntok = a.tile_ntok[tile];
   const int p0 = a.positions[tok0];
   const int maxpos = a.positions[tok0 + ntok - 1];
   const int k_lo = sp * a.split_keys;
+  // slices past the tile's last position hold no key; the combine stops
+  // before them
+  if (k_lo > maxpos) return;
   int k_hi = k_lo + a.split_keys;
   if (k_hi > maxpos + 1) k_hi = maxpos + 1;
   const int qh = kvh * group + w;
@@ -180,22 +258,37 @@ __global__ __launch_bounds__(512) void attention_kernel(const AttnArgs a) {
   const int my_pos = p0 + col;
   const bool col_ok = col < ntok;
 
-  for (int kb0 = k_lo; kb0 < k_hi; kb0 += kKB) {
-    // stage K and V^T of keys kb0 .. kb0+63 (zeros past the slice)
-    for (int i = threadIdx.x; i < kKB * 16; i += nthreads) {
+  // K and V chunks of keys kb0 .. kb0+63 (zeros past the slice)
+  u32x4 kr[NPT], vr[NPT];
+  auto fetch = [&](int kb0) {
+#pragma unroll
+    for (int n = 0; n < NPT; ++n) {
+      const int i = int(threadIdx.x) + n * NT;
       const int key = i >> 4, ch = i & 15;
       const int kp = kb0 + key;
-      u32x4 kv = {0u, 0u, 0u, 0u}, vv = {0u, 0u, 0u, 0u};
-      if (kp < k_hi) {
+      kr[n] = u32x4{0u, 0u, 0u, 0u};
+      vr[n] = u32x4{0u, 0u, 0u, 0u};
+      if (i < kKB * 16 && kp < k_hi) {
         const int bidx = min(kp / a.bs, a.max_blocks - 1);
         const int blk = int(min(max(int64_t(a.block_table[int64_t(seq) * a.max_blocks + bidx]), int64_t(0)),
                                 a.num_blocks - 1));
         const int64_t off = ((int64_t(blk) * a.n_kv + kvh) * a.bs + kp % a.bs) * kHD + ch * 8;
-        kv = *reinterpret_cast<const u32x4*>(a.kc + off);
-        vv = *reinterpret_cast<const u32x4*>(a.vc + off);
+        kr[n] = *reinterpret_cast<const u32x4*>(a.kc + off);
+        vr[n] = *reinterpret_cast<const u32x4*>(a.vc + off);
       }
-      *reinterpret_cast<u32x4*>(kl + kswz(key, ch)) = kv;
-      const uint16_t* ve = reinterpret_cast<const uint16_t*>(&vv);
+    }
+  };
+  if (k_lo < k_hi) fetch(k_lo);
+
+  for (int kb0 = k_lo; kb0 < k_hi; kb0 += kKB) {
+    // stage K and V^T of this block
+#pragma unroll
+    for (int n = 0; n < NPT; ++n) {
+      const int i = int(threadIdx.x) + n * NT;
+      if (i >= kKB * 16) break;
+      const int key = i >> 4, ch = i & 15;
+      *reinterpret_cast<u32x4*>(kl + kswz(key, ch)) = kr[n];
+      const uint16_t* ve = reinterpret_cast<const uint16_t*>(&vr[n]);
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int dim = ch * 8 + e;
@@ -203,6 +296,7 @@ __global__ __launch_bounds__(512) void attention_kernel(const AttnArgs a) {
       }
     }
     __syncthreads();
+    if (kb0 + kKB < k_hi) fetch(kb0 + kKB);
 
     // S^T blocks: lane holds keys kb0 + 16*j + 4g + r of token col
     f32x4 st[4];
@@ -283,50 +377,255 @@ __global__ __launch_bounds__(512) void attention_kernel(const AttnArgs a) {
   }
 }
 
-// out[token][head*128 + d] from the context slices of its tile
-__global__ __launch_bounds__(128) void attn_combine_kernel(const AttnArgs a) {
-  const int group = a.n_heads / a.n_kv;
+// ------------------------------------------------------------------ single-token attention
+// A decode token has one query row per head, too few to fill a matrix-core
+// tile, so the GROUP query heads that share a KV head share one:
+// S^T = K Q^T runs on MFMA with those heads as columns and K read straight
+// from the cache in the operand layout (key c, dims 32s + 8g).  P.V runs on
+// the vector ALUs as packed bf16 dot products over pairs of keys.  Each
+// 16-lane row g of a wave keeps its own online-softmax state over keys
+// 4g..4g+3 of every 16-key run; rows and waves merge through LDS at the end.
+// One block of four waves per (tile, KV head, key slice); wave w takes the
+// runs w, w + 4, ... of the slice.  A run lies in one KV block: block_size
+// and split_keys are multiples of 16 (checked by the launcher).
+template <int H, int GROUP>
+__device__ inline void pv_heads(float (&o)[GROUP][8], float alpha, uint32_t p01, uint32_t p23,
+                                const uint32_t (&v01)[8], const uint32_t (&v23)[8]) {
+  if constexpr (H < GROUP) {
+    // lane H of the row holds head H's alpha and packed probabilities
+    const float al = __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, alpha), 0x150 + H,
+                                                                        0xF, 0xF, false));
+    const bf16x2_t q01 = __builtin_bit_cast(bf16x2_t, __builtin_amdgcn_mov_dpp(int(p01), 0x150 + H, 0xF, 0xF, false));
+    const bf16x2_t q23 = __builtin_bit_cast(bf16x2_t, __builtin_amdgcn_mov_dpp(int(p23), 0x150 + H, 0xF, 0xF, false));
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float t = __builtin_amdgcn_fdot2_f32_bf16(q01, __builtin_bit_cast(bf16x2_t, v01[e]), o[H][e] * al, false);
+      o[H][e] = __builtin_amdgcn_fdot2_f32_bf16(q23, __builtin_bit_cast(bf16x2_t, v23[e]), t, false);
+    }
+    pv_heads<H + 1, GROUP>(o, alpha, p01, p23, v01, v23);
+  }
+}
+
+__device__ inline uint32_t pack_bf16x2(float lo, float hi) {
+  return uint32_t(__builtin_bit_cast(uint16_t, __bf16(lo))) | (uint32_t(__builtin_bit_cast(uint16_t, __bf16(hi))) << 16);
+}
+
+template <int GROUP>
+__global__ __launch_bounds__(256) void attention_single_kernel(const AttnArgs a) {
+  __shared__ __attribute__((aligned(16))) float so[4][4][GROUP][kHD];   // wave, row, head: unnormalised o
+  __shared__ float sml[4][4][GROUP][2];                                   // wave, row, head: m, l
   int b = blockIdx.x;
-  const int tcol = b % 16;
-  b /= 16;
-  const int qh = b % a.n_heads;
-  const int tile = b / a.n_heads;
-  if (tcol >= a.tile_ntok[tile]) return;
+  const int sp = b % a.n_splits;
+  b /= a.n_splits;
+  const int kvh = b % a.n_kv;
+  const int tile = b / a.n_kv;
+  const int seq = a.tile_seq[tile], tok0 = a.tile_tok0[tile], ntok = a.tile_ntok[tile];
+  const int k_lo = sp * a.split_keys;
+  if (k_lo > a.positions[tok0 + ntok - 1]) return;
+  // wave-uniform, so that the block-table lookups are scalar loads
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4, c = lane & 15;
+  const int32_t* table = a.block_table + int64_t(seq) * a.max_blocks;
+  const int64_t blk_elems = int64_t(a.n_kv) * a.bs * kHD;
+
+  for (int tcol = 0; tcol < ntok; ++tcol) {
+    const int tok = tok0 + tcol;
+    const int hi = min(k_lo + a.split_keys, a.positions[tok] + 1);   // keys [k_lo, hi)
+    bf16x8_t qf[4];   // column c = query head kvh*GROUP + c, dims 32s + 8g
+    {
+      const bool ok = c < GROUP;
+      const uint16_t* qrow = a.q + int64_t(tok) * a.ldq + (kvh * GROUP + (ok ? c : 0)) * kHD;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const u32x4 v = ok ? *reinterpret_cast<const u32x4*>(qrow + s * 32 + g * 8) : u32x4{0u, 0u, 0u, 0u};
+        qf[s] = __builtin_bit_cast(bf16x8_t, v);
+      }
+    }
+    // K of a run in the operand layout; V rows 4g + j, dims 8c .. 8c+7
+    auto fetch = [&](int run, u32x4 (&kq)[4], u32x4 (&vq)[4]) {
+      const int kp0 = k_lo + 16 * run;
+      const int bidx = __builtin_amdgcn_readfirstlane(min(kp0 / a.bs, a.max_blocks - 1));
+      // the block table is read through the constant address space: a
+      // scalar load, which leaves the vector loads of the run in flight
+      const int32_t e = ((const int32_t __attribute__((address_space(4)))*)table)[bidx];
+      const int64_t blk = min(max(int64_t(e), int64_t(0)), a.num_blocks - 1);
+      const int64_t base = blk * blk_elems + (int64_t(kvh) * a.bs + kp0 % a.bs) * kHD;
+      const uint16_t* kb = a.kc + base;
+      const uint16_t* vb = a.vc + base;
+      // keys past hi read the run's first key instead (scores masked, p = 0),
+      // so the loads need no branch and stay in flight together
+      const int rk = kp0 + c < hi ? c : 0;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) kq[s] = *reinterpret_cast<const u32x4*>(kb + rk * kHD + s * 32 + g * 8);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int rv = kp0 + 4 * g + j < hi ? 4 * g + j : 0;
+        vq[j] = *reinterpret_cast<const u32x4*>(vb + rv * kHD + c * 8);
+      }
+    };
+    float m = -INFINITY, l = 0.f;   // the row's state for head c
+    float o[GROUP][8];
+#pragma unroll
+    for (int h = 0; h < GROUP; ++h)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) o[h][e] = 0.f;
+    // one 16-key run: scores on MFMA, online softmax per row, P.V on VALU
+    auto step = [&](const u32x4 (&kq)[4], const u32x4 (&vq)[4], int run) {
+      f32x4 st = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        st = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, kq[s]), qf[s], st, 0, 0, 0);
+      // st[j]: key k_lo + 16 run + 4g + j, head c
+      const int kp0 = k_lo + 16 * run;
+      float bm = -INFINITY;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        st[j] = kp0 + 4 * g + j < hi ? st[j] * a.scale : -INFINITY;
+        bm = fmaxf(bm, st[j]);
+      }
+      const float m_new = fmaxf(m, bm);
+      const float alpha = m_new == -INFINITY ? 1.f : __expf(m - m_new);
+      float p[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) p[j] = st[j] == -INFINITY ? 0.f : __expf(st[j] - m_new);
+      l = l * alpha + ((p[0] + p[1]) + (p[2] + p[3]));
+      m = m_new;
+      const uint32_t p01 = pack_bf16x2(p[0], p[1]), p23 = pack_bf16x2(p[2], p[3]);
+      // pairs of keys per dim: lo half key j, hi half key j + 1
+      uint32_t v01[8], v23[8];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        v01[2 * d] = __builtin_amdgcn_perm(vq[1][d], vq[0][d], 0x05040100u);
+        v01[2 * d + 1] = __builtin_amdgcn_perm(vq[1][d], vq[0][d], 0x07060302u);
+        v23[2 * d] = __builtin_amdgcn_perm(vq[3][d], vq[2][d], 0x05040100u);
+        v23[2 * d + 1] = __builtin_amdgcn_perm(vq[3][d], vq[2][d], 0x07060302u);
+      }
+      pv_heads<0, GROUP>(o, alpha, p01, p23, v01, v23);
+    };
+    // two register sets in turn: the next run's loads are in flight while
+    // the current run is computed
+    // (the last run fetches itself again rather than branch around a fetch,
+    // which would make the first set wait for the second)
+    u32x4 ka[4], va[4], kb[4], vb[4];
+    int run = w;
+    if (k_lo + 16 * run < hi) {
+      fetch(run, ka, va);
+      for (;;) {
+        bool more = k_lo + 16 * (run + 4) < hi;
+        fetch(more ? run + 4 : run, kb, vb);
+        __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the math
+        step(ka, va, run);
+        if (!more) break;
+        run += 4;
+        more = k_lo + 16 * (run + 4) < hi;
+        fetch(more ? run + 4 : run, ka, va);
+        __builtin_amdgcn_sched_barrier(0);
+        step(kb, vb, run);
+        if (!more) break;
+        run += 4;
+      }
+    }
+    // merge the 16 row states of each head
+    if (c < GROUP) {
+      sml[w][g][c][0] = m;
+      sml[w][g][c][1] = l;
+    }
+#pragma unroll
+    for (int h = 0; h < GROUP; ++h) {
+      *reinterpret_cast<f32x4*>(&so[w][g][h][8 * c]) = f32x4{o[h][0], o[h][1], o[h][2], o[h][3]};
+      *reinterpret_cast<f32x4*>(&so[w][g][h][8 * c + 4]) = f32x4{o[h][4], o[h][5], o[h][6], o[h][7]};
+    }
+    __syncthreads();
+    for (int h = w; h < GROUP; h += 4) {
+      float M = -INFINITY;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) M = fmaxf(M, sml[i >> 2][i & 3][h][0]);
+      float L = 0.f, ax = 0.f, ay = 0.f;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const float mi = sml[i >> 2][i & 3][h][0];
+        if (mi == -INFINITY) continue;
+        const float e = __expf(mi - M);
+        L += sml[i >> 2][i & 3][h][1] * e;
+        const float2 v = *reinterpret_cast<const float2*>(&so[i >> 2][i & 3][h][2 * lane]);
+        ax += v.x * e;
+        ay += v.y * e;
+      }
+      const int64_t slot = ((int64_t(tile) * a.n_kv + kvh) * a.n_splits + sp) * GROUP + h;
+      *reinterpret_cast<float2*>(a.part_o + (slot * 16 + tcol) * kHD + 2 * lane) = float2{ax, ay};
+      if (lane == 0) {
+        a.part_ml[(slot * 16 + tcol) * 2] = M;
+        a.part_ml[(slot * 16 + tcol) * 2 + 1] = L;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// out[token][head*128 + d] from the partials of the slices that reach the
+// tile: one wave per (tile, query head), two dims per lane
+__global__ __launch_bounds__(256) void attn_combine_kernel(const AttnArgs a) {
+  const int item = __builtin_amdgcn_readfirstlane(int(blockIdx.x) * 4 + int(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  if (item >= a.n_tiles * a.n_heads) return;
+  const int group = a.n_heads / a.n_kv;
+  const int qh = item % a.n_heads, tile = item / a.n_heads;
   const int kvh = qh / group, w = qh % group;
-  const int d = threadIdx.x;
-  float M = -INFINITY;
-  for (int sp = 0; sp < a.n_splits; ++sp) {
-    const int64_t slot = ((int64_t(tile) * a.n_kv + kvh) * a.n_splits + sp) * group + w;
-    M = fmaxf(M, a.part_ml[(slot * 16 + tcol) * 2]);
+  const int ntok = a.tile_ntok[tile], tok0 = a.tile_tok0[tile];
+  // slices that start past the tile's last position were never written
+  const int nsp = min(a.n_splits, a.positions[tok0 + ntok - 1] / a.split_keys + 1);
+  const int64_t slot0 = (int64_t(tile) * a.n_kv + kvh) * a.n_splits * group + w;
+  for (int tcol = 0; tcol < ntok; ++tcol) {
+    float M = -INFINITY;
+    for (int sp = lane; sp < nsp; sp += 64) M = fmaxf(M, a.part_ml[((slot0 + int64_t(sp) * group) * 16 + tcol) * 2]);
+    for (int off = 32; off >= 1; off >>= 1) M = fmaxf(M, __shfl_xor(M, off));
+    float L = 0.f, ax = 0.f, ay = 0.f;
+    for (int sp = 0; sp < nsp; ++sp) {
+      const int64_t s16 = (slot0 + int64_t(sp) * group) * 16 + tcol;
+      const float mi = a.part_ml[s16 * 2];
+      if (mi == -INFINITY) continue;
+      const float e = __expf(mi - M);
+      L += a.part_ml[s16 * 2 + 1] * e;
+      const float2 v = *reinterpret_cast<const float2*>(a.part_o + s16 * kHD + 2 * lane);
+      ax += v.x * e;
+      ay += v.y * e;
+    }
+    const float inv = L > 0.f ? 1.f / L : 0.f;
+    const uint32_t pk = uint32_t(f2bf(ax * inv)) | (uint32_t(f2bf(ay * inv)) << 16);
+    *reinterpret_cast<uint32_t*>(a.out + int64_t(tok0 + tcol) * a.ldo + qh * kHD + 2 * lane) = pk;
   }
-  float L = 0.f, acc = 0.f;
-  for (int sp = 0; sp < a.n_splits; ++sp) {
-    const int64_t slot = ((int64_t(tile) * a.n_kv + kvh) * a.n_splits + sp) * group + w;
-    const float m = a.part_ml[(slot * 16 + tcol) * 2];
-    if (m == -INFINITY) continue;
-    const float e = __expf(m - M);
-    L += a.part_ml[(slot * 16 + tcol) * 2 + 1] * e;
-    acc += a.part_o[(slot * 16 + tcol) * kHD + d] * e;
-  }
-  const int tok = a.tile_tok0[tile] + tcol;
-  a.out[int64_t(tok) * a.ldo + qh * kHD + d] = f2bf(L > 0.f ? acc / L : 0.f);
 }
 
 // ------------------------------------------------------------------ argmax
-__global__ __launch_bounds__(256) void argmax_kernel(const uint16_t* __restrict__ logits, int64_t V,
-                                                     int32_t* __restrict__ out) {
+// Greedy token: the largest logit of the row, the smallest index among equal
+// ones.  Rows whose start is 16-byte aligned are read 8 logits per load.
+constexpr int kArgmaxThreads = 1024;
+__global__ __launch_bounds__(kArgmaxThreads) void argmax_kernel(const uint16_t* __restrict__ logits, int64_t V,
+                                                                int32_t* __restrict__ out) {
   const uint16_t* row = logits + int64_t(blockIdx.x) * V;
   float best = -INFINITY;
   int64_t bi = 0;
-  for (int64_t i = threadIdx.x; i < V; i += blockDim.x) {
-    const float v = bf2f(row[i]);
-    if (v > best) {
+  auto take = [&](float v, int64_t i) {
+    if (v > best || (v == best && i < bi)) {
       best = v;
       bi = i;
     }
+  };
+  int64_t head = 0;
+  if ((reinterpret_cast<uintptr_t>(row) & 15) == 0) {
+    head = V / 8 * 8;
+    const u32x4* r8 = reinterpret_cast<const u32x4*>(row);
+    for (int64_t c = threadIdx.x; c < V / 8; c += blockDim.x) {
+      const u32x4 w = r8[c];
+      const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int e = 0; e < 8; ++e) take(bf2f(uint16_t(ww[e / 2] >> (16 * (e & 1)))), c * 8 + e);
+    }
   }
-  __shared__ float sv[256];
-  __shared__ int64_t si[256];
+  for (int64_t i = head + threadIdx.x; i < V; i += blockDim.x) take(bf2f(row[i]), i);
+  __shared__ float sv[kArgmaxThreads];
+  __shared__ int64_t si[kArgmaxThreads];
   sv[threadIdx.x] = best;
   si[threadIdx.x] = bi;
   __syncthreads();
@@ -354,30 +653,70 @@ hipError_t launch_embed(const EmbedArgs& a, hipStream_t s) {
 
 hipError_t launch_rmsnorm(const NormArgs& a, int rows, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(rmsnorm_kernel, dim3(rows), dim3(256), 0, s, a);
+  const bool vec = a.D % 8 == 0 && a.D <= 8 * 256 * kNormChunks && reinterpret_cast<uintptr_t>(a.x) % 16 == 0 &&
+                   reinterpret_cast<uintptr_t>(a.h) % 16 == 0 && (!a.add || reinterpret_cast<uintptr_t>(a.add) % 16 == 0) &&
+                   (!a.r_out || reinterpret_cast<uintptr_t>(a.r_out) % 16 == 0) &&
+                   (!a.gain || reinterpret_cast<uintptr_t>(a.gain) % 16 == 0);
+  if (vec)
+    hipLaunchKernelGGL(rmsnorm_vec_kernel, dim3(rows), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(rmsnorm_kernel, dim3(rows), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_rope_kv(const RopeArgs& a, int T, hipStream_t s) {
   if (T <= 0) return hipSuccess;
+  if (a.hd / 2 > kMaxHalf) return hipErrorInvalidValue;
   hipLaunchKernelGGL(rope_kv_kernel, dim3(T), dim3(256), 0, s, a);
   return hipGetLastError();
+}
+
+template <int G>
+hipError_t launch_attention_g(const AttnArgs& a, int n_single, hipStream_t s) {
+  if constexpr ((G & (G - 1)) != 0) n_single = 0;
+  else if (n_single > 0) {
+    const int64_t blocks = int64_t(n_single) * a.n_kv * a.n_splits;
+    hipLaunchKernelGGL(attention_single_kernel<G>, dim3(unsigned(blocks)), dim3(256), 0, s, a);
+    if (hipError_t e = hipGetLastError()) return e;
+  }
+  if (a.n_tiles > n_single) {
+    AttnArgs m = a;
+    m.tile0 = n_single;
+    const int64_t blocks = int64_t(a.n_tiles - n_single) * a.n_kv * a.n_splits;
+    hipLaunchKernelGGL(attention_kernel<G>, dim3(unsigned(blocks)), dim3(64 * G), 0, s, m);
+    if (hipError_t e = hipGetLastError()) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_attention(const AttnArgs& a, hipStream_t s) {
   if (a.n_tiles <= 0) return hipSuccess;
   const int group = a.n_heads / a.n_kv;
-  const int64_t blocks = int64_t(a.n_tiles) * a.n_kv * a.n_splits;
-  hipLaunchKernelGGL(attention_kernel, dim3(unsigned(blocks)), dim3(64 * group), 0, s, a);
-  hipError_t e = hipGetLastError();
+  // the single-token path takes group sizes 1, 2, 4 and 8, and 16-key runs
+  // that stay inside one KV block
+  const bool single_ok = (group & (group - 1)) == 0 && a.bs % 16 == 0 && a.split_keys % 16 == 0;
+  const int n_single = single_ok ? min(max(a.n_single, 0), a.n_tiles) : 0;
+  hipError_t e;
+  switch (group) {
+    case 1: e = launch_attention_g<1>(a, n_single, s); break;
+    case 2: e = launch_attention_g<2>(a, n_single, s); break;
+    case 3: e = launch_attention_g<3>(a, 0, s); break;
+    case 4: e = launch_attention_g<4>(a, n_single, s); break;
+    case 5: e = launch_attention_g<5>(a, 0, s); break;
+    case 6: e = launch_attention_g<6>(a, 0, s); break;
+    case 7: e = launch_attention_g<7>(a, 0, s); break;
+    case 8: e = launch_attention_g<8>(a, n_single, s); break;
+    default: return hipErrorInvalidValue;
+  }
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(attn_combine_kernel, dim3(unsigned(int64_t(a.n_tiles) * a.n_heads * 16)), dim3(kHD), 0, s, a);
+  const int64_t waves = int64_t(a.n_tiles) * a.n_heads;
+  hipLaunchKernelGGL(attn_combine_kernel, dim3(unsigned((waves + 3) / 4)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_argmax(const uint16_t* logits, int64_t rows, int64_t V, int32_t* out, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(argmax_kernel, dim3(unsigned(rows)), dim3(256), 0, s, logits, V, out);
+  hipLaunchKernelGGL(argmax_kernel, dim3(unsigned(rows)), dim3(kArgmaxThreads), 0, s, logits, V, out);
   return hipGetLastError();
 }
 

@@ -74,7 +74,7 @@ class Engine:
     def __init__(self, cfg, pool_bytes, page_bytes=2 << 20, seed=None, flags=0, kv_blocks=4096, block_size=16,
                  max_tokens=2048, prefill_chunk=512, max_seqs=64, split_keys=512, remap_every=256,
                  weights=None, gains=None, record_logits=False, max_context=None, remap_slices=1,
-                 head_perm=True, decoy=None):
+                 head_perm=True, decoy=None, single_tiles="decode"):
         import torch
         self.torch = torch
         self.cfg = dict(cfg)
@@ -85,6 +85,11 @@ class Engine:
         self.prefill_chunk = prefill_chunk
         self.max_seqs = max_seqs
         self.split_keys = split_keys
+        # tiles declared single-token: "decode" (the leading decode tokens),
+        # "all" or "none" (the last two exercise the attention paths)
+        if single_tiles not in ("decode", "all", "none"):
+            raise ValueError(f"single_tiles must be decode, all or none, not {single_tiles!r}")
+        self.single_tiles = single_tiles
         self.remap_every = remap_every
         # a remap is spread over remap_slices consecutive steps (1 = all at once)
         self.remap_slices = max(1, int(remap_slices))
@@ -144,6 +149,19 @@ class Engine:
             self.running.append(r)
 
     # ------------------------------------------------------------- one step
+    ATTN_BLOCKS = 1024    # about 4 attention blocks per compute unit
+    MIN_SLICE = 128       # keys per slice at least: 2 runs of 16 keys per wave
+
+    def key_slices(self, n_tiles, max_ctx):
+        """Keys per attention slice for this step: at most split_keys, a
+        multiple of 64, short enough that tiles x kv heads x slices fills the
+        GPU, and no more partials than the workspace holds."""
+        want = max(1, math.ceil(self.ATTN_BLOCKS / (n_tiles * self.cfg["n_kv_heads"])))
+        keys = min(self.split_keys, max(self.MIN_SLICE, math.ceil(max_ctx / want / 64) * 64))
+        while n_tiles * math.ceil(max_ctx / keys) > self.max_tiles * self.max_splits:
+            keys += 64
+        return keys, max(1, math.ceil(max_ctx / keys))
+
     def _plan(self):
         """Decode tokens of running sequences first, then prefill chunks."""
         batch = []    # (request, first position, n tokens, token ids)
@@ -188,7 +206,10 @@ class Engine:
                 logit_reqs.append(r)
             max_ctx = max(max_ctx, p0 + n)
             row += n
-        n_splits = max(1, math.ceil(max_ctx / self.split_keys))
+        split_keys, n_splits = self.key_slices(len(tile_seq), max_ctx)
+        # decode tokens come first, one tile each: the single-token attention path
+        n_single = next((k for k, n in enumerate(tile_ntok) if n != 1), len(tile_ntok))
+        n_single = {"decode": n_single, "all": len(tile_ntok), "none": 0}[self.single_tiles]
         parts = [tokens, positions, tok_seq, table.reshape(-1), np.array(tile_seq, np.int32),
                  np.array(tile_tok0, np.int32), np.array(tile_ntok, np.int32), np.array(logit_rows, np.int32)]
         offs, cur = [], 0
@@ -200,7 +221,7 @@ class Engine:
         self.d_idx[:cur].copy_(self.h_idx[:cur], non_blocking=True)
         base = self.d_idx.data_ptr()
         ptr = [base + 4 * o for o in offs]
-        st = C.cloak_step(T, S, maxb, len(logit_rows), len(tile_seq), n_splits, self.split_keys, 0,
+        st = C.cloak_step(T, S, maxb, len(logit_rows), len(tile_seq), n_splits, split_keys, n_single,
                           ptr[0], ptr[1], ptr[2], ptr[3], ptr[4], ptr[5], ptr[6], ptr[7] if logit_rows else None,
                           self.d_out.data_ptr() if logit_rows else None,
                           self.d_logits.data_ptr() if (self.record_logits and logit_rows) else None)

@@ -181,3 +181,41 @@ def test_attention_32_8_heads_long_context_matches_fp64_oracle(S):
         assert err <= 3e-2, (i, err)
     print(f"32/8-head attention over 4200+ keys: worst normwise logit error vs FP64 {worst:.3e}")
     eng.close()
+
+
+# head groups of 1, 3 and 8 query heads per kv head; group 3 has no
+# single-token kernel, so every tile runs on the matrix-core path
+GROUPS = {1: (2, 2), 3: (3, 1), 8: (8, 1)}
+
+
+@pytest.mark.parametrize("single", ["decode", "all", "none"])
+@pytest.mark.parametrize("group", [1, 3, 8])
+def test_head_groups_and_attention_paths_match_fp64_oracle(S, group, single):
+    """Three requests of uneven prompts decode while others prefill (mixed
+    steps of single-token and 16-token tiles), contexts cut into 512-key
+    slices so each wave of the single-token path walks several 16-key runs
+    with ragged ends.  single='all' also sends 16-token prefill tiles down the
+    single-token path, 'none' sends decode tokens down the matrix-core path:
+    both must match the FP64 decoder as the default routing does."""
+    n_heads, n_kv = GROUPS[group]
+    cfg = dict(n_layers=1, d_model=128 * n_heads, n_heads=n_heads, n_kv_heads=n_kv, head_dim=128, d_ffn=512,
+               vocab=1024, theta=500000.0, eps=1e-5)
+    shapes, ws = tiny_weights(cfg)
+    rng = np.random.Generator(np.random.PCG64(16 + group))
+    lens, outs = [37, 301, 150], [9, 4, 6]
+    reqs = [S.Request(i, rng.integers(0, cfg["vocab"], n).astype(np.int32), m,
+                      forced=rng.integers(0, cfg["vocab"], m).astype(np.int32))
+            for i, (n, m) in enumerate(zip(lens, outs))]
+    eng = make_engine(S, cfg, ws, prefill_chunk=64, max_tokens=128, split_keys=512, single_tiles=single)
+    eng.run(reqs, realtime=False)
+    dec = oracle_decoder(cfg, shapes, ws)
+    worst = 0.0
+    for r in reqs:
+        assert r.done and len(r.logits) == len(r.forced)
+        ref = dec.forward(np.concatenate([r.prompt, r.forced[:-1]]))
+        for i, lg in enumerate(r.logits):
+            err = ON.normwise_err(lg, ref[len(r.prompt) - 1 + i])
+            worst = max(worst, err)
+            assert err <= 3e-2, (r.id, i, err)
+    print(f"group {group}, single={single}: worst normwise logit error vs FP64 {worst:.3e}")
+    eng.close()
