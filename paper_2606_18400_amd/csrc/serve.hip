@@ -155,7 +155,6 @@ __global__ __launch_bounds__(256) void rope_kv_kernel(const RopeArgs a) {
                             a.num_blocks - 1));
   const int off = pos % a.bs;
   uint16_t* row = a.qkv + int64_t(t) * a.ldqkv;
-  const int nq = a.n_heads * half, nk = a.n_kv * half;
   // every head turns pair i by the same angle: half cosines and sines per token
   __shared__ float cs[2][kMaxHalf];
   for (int i = threadIdx.x; i < half; i += blockDim.x) {
@@ -164,30 +163,42 @@ __global__ __launch_bounds__(256) void rope_kv_kernel(const RopeArgs a) {
     cs[1][i] = float(sin(ang));
   }
   __syncthreads();
-  for (int it = threadIdx.x; it < nq + 2 * nk; it += blockDim.x) {
-    if (it < nq + nk) {
-      const bool is_q = it < nq;
-      const int j = is_q ? it : it - nq;
-      const int head = j / half, i = j % half;
-      const float c = cs[0][i], s = cs[1][i];
-      uint16_t* base = row + (is_q ? head * a.hd : (a.n_heads + head) * a.hd);
-      const float x1 = bf2f(base[i]), x2 = bf2f(base[i + half]);
-      const uint16_t y1 = f2bf(x1 * c - x2 * s), y2 = f2bf(x2 * c + x1 * s);
-      if (is_q) {
-        base[i] = y1;
-        base[i + half] = y2;
-      } else {
-        uint16_t* kd = a.kc + ((int64_t(block) * a.n_kv + head) * a.bs + off) * a.hd;
-        kd[i] = y1;
-        kd[i + half] = y2;
+  // 8 pairs (16 bytes of each half) per item: rotations of q and k heads,
+  // then 16-byte copies of the v heads into the cache
+  const int per_head = half / 8;
+  const int nrot = (a.n_heads + a.n_kv) * per_head, ncopy = a.n_kv * (a.hd / 8);
+  for (int it = threadIdx.x; it < nrot + ncopy; it += blockDim.x) {
+    if (it < nrot) {
+      const int head = it / per_head, i0 = (it % per_head) * 8;
+      const uint16_t* src = row + head * a.hd;
+      const u32x4 lo = *reinterpret_cast<const u32x4*>(src + i0);
+      const u32x4 hi = *reinterpret_cast<const u32x4*>(src + i0 + half);
+      const uint32_t lw[4] = {lo.x, lo.y, lo.z, lo.w}, hw[4] = {hi.x, hi.y, hi.z, hi.w};
+      uint32_t y1[4], y2[4];
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        uint16_t r1[2], r2[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const float c = cs[0][i0 + e + u], sn = cs[1][i0 + e + u];
+          const float x1 = bf2f(uint16_t(lw[e / 2] >> (16 * u))), x2 = bf2f(uint16_t(hw[e / 2] >> (16 * u)));
+          r1[u] = f2bf(x1 * c - x2 * sn);
+          r2[u] = f2bf(x2 * c + x1 * sn);
+        }
+        y1[e / 2] = uint32_t(r1[0]) | (uint32_t(r1[1]) << 16);
+        y2[e / 2] = uint32_t(r2[0]) | (uint32_t(r2[1]) << 16);
       }
+      uint16_t* dst = head < a.n_heads
+                          ? row + head * a.hd
+                          : a.kc + ((int64_t(block) * a.n_kv + (head - a.n_heads)) * a.bs + off) * a.hd;
+      *reinterpret_cast<u32x4*>(dst + i0) = u32x4{y1[0], y1[1], y1[2], y1[3]};
+      *reinterpret_cast<u32x4*>(dst + i0 + half) = u32x4{y2[0], y2[1], y2[2], y2[3]};
     } else {
-      const int j = it - nq - nk;   // v: plain copy, two elements per item
-      const int head = j / half, i = j % half;
+      const int j = it - nrot;
+      const int head = j / (a.hd / 8), i0 = (j % (a.hd / 8)) * 8;
       const uint16_t* src = row + (a.n_heads + a.n_kv + head) * a.hd;
       uint16_t* vd = a.vc + ((int64_t(block) * a.n_kv + head) * a.bs + off) * a.hd;
-      vd[2 * i] = src[2 * i];
-      vd[2 * i + 1] = src[2 * i + 1];
+      *reinterpret_cast<u32x4*>(vd + i0) = *reinterpret_cast<const u32x4*>(src + i0);
     }
   }
 }
@@ -577,20 +588,45 @@ __global__ __launch_bounds__(256) void attn_combine_kernel(const AttnArgs a) {
   const int nsp = min(a.n_splits, a.positions[tok0 + ntok - 1] / a.split_keys + 1);
   const int64_t slot0 = (int64_t(tile) * a.n_kv + kvh) * a.n_splits * group + w;
   for (int tcol = 0; tcol < ntok; ++tcol) {
+    auto ml = [&](int sp) { return a.part_ml + ((slot0 + int64_t(sp) * group) * 16 + tcol) * 2; };
     float M = -INFINITY;
-    for (int sp = lane; sp < nsp; sp += 64) M = fmaxf(M, a.part_ml[((slot0 + int64_t(sp) * group) * 16 + tcol) * 2]);
+    for (int sp = lane; sp < nsp; sp += 64) M = fmaxf(M, ml(sp)[0]);
     for (int off = 32; off >= 1; off >>= 1) M = fmaxf(M, __shfl_xor(M, off));
+    // lane k holds the weight of slice base + k; the partial rows are then
+    // read with no load waiting on another
     float L = 0.f, ax = 0.f, ay = 0.f;
-    for (int sp = 0; sp < nsp; ++sp) {
-      const int64_t s16 = (slot0 + int64_t(sp) * group) * 16 + tcol;
-      const float mi = a.part_ml[s16 * 2];
-      if (mi == -INFINITY) continue;
-      const float e = __expf(mi - M);
-      L += a.part_ml[s16 * 2 + 1] * e;
-      const float2 v = *reinterpret_cast<const float2*>(a.part_o + s16 * kHD + 2 * lane);
-      ax += v.x * e;
-      ay += v.y * e;
+    for (int base = 0; base < nsp; base += 64) {
+      float e = 0.f;
+      if (base + lane < nsp) {
+        const float mi = ml(base + lane)[0];
+        if (mi != -INFINITY) {
+          e = __expf(mi - M);
+          L += ml(base + lane)[1] * e;
+        }
+      }
+      const int cnt = min(64, nsp - base);
+      auto row = [&](int k) {
+        return *reinterpret_cast<const float2*>(a.part_o + ((slot0 + int64_t(base + k) * group) * 16 + tcol) * kHD +
+                                                2 * lane);
+      };
+      auto weight = [&](int k) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, e), k));
+      };
+      int k = 0;
+      for (; k + 4 <= cnt; k += 4) {
+        const float2 v0 = row(k), v1 = row(k + 1), v2 = row(k + 2), v3 = row(k + 3);
+        const float e0 = weight(k), e1 = weight(k + 1), e2 = weight(k + 2), e3 = weight(k + 3);
+        ax += v0.x * e0 + v1.x * e1 + v2.x * e2 + v3.x * e3;
+        ay += v0.y * e0 + v1.y * e1 + v2.y * e2 + v3.y * e3;
+      }
+      for (; k < cnt; ++k) {
+        const float2 v = row(k);
+        const float ek = weight(k);
+        ax += v.x * ek;
+        ay += v.y * ek;
+      }
     }
+    for (int off = 32; off >= 1; off >>= 1) L += __shfl_xor(L, off);
     const float inv = L > 0.f ? 1.f / L : 0.f;
     const uint32_t pk = uint32_t(f2bf(ax * inv)) | (uint32_t(f2bf(ay * inv)) << 16);
     *reinterpret_cast<uint32_t*>(a.out + int64_t(tok0 + tcol) * a.ldo + qh * kHD + 2 * lane) = pk;
@@ -666,7 +702,10 @@ hipError_t launch_rmsnorm(const NormArgs& a, int rows, hipStream_t s) {
 
 hipError_t launch_rope_kv(const RopeArgs& a, int T, hipStream_t s) {
   if (T <= 0) return hipSuccess;
-  if (a.hd / 2 > kMaxHalf) return hipErrorInvalidValue;
+  // 16-byte items: half a head a multiple of 8 elements, rows 16-byte aligned
+  if (a.hd / 2 > kMaxHalf || a.hd % 16 != 0 || a.ldqkv % 8 != 0 || reinterpret_cast<uintptr_t>(a.qkv) % 16 != 0 ||
+      reinterpret_cast<uintptr_t>(a.kc) % 16 != 0 || reinterpret_cast<uintptr_t>(a.vc) % 16 != 0)
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL(rope_kv_kernel, dim3(T), dim3(256), 0, s, a);
   return hipGetLastError();
 }
