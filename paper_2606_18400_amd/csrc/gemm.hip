@@ -35,6 +35,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <mutex>
 #include <set>
 
@@ -64,6 +66,15 @@ __device__ inline uint16_t f32_to_bf16_rne(float f) {
   if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);
   u += 0x7fffu + ((u >> 16) & 1u);
   return uint16_t(u >> 16);
+}
+
+// f(integral_constant<int, I>) for I = B .. E-1, unrolled at compile time
+template <int B, int E, typename F>
+__device__ inline void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
 }
 
 // byte offset in a tile of (row, 16-byte chunk): chunks XOR-swizzled by row
@@ -113,7 +124,8 @@ __device__ inline bool tile_row(const GemmArgs& a, int tile_n, int tr, int& seg,
 // v_cvt_scalef32_pk_bf16_fp8 when they are written to LDS, so the MFMA path
 // is the same for both while FP8 weights cross HBM at one byte each.  Each
 // thread keeps its rows for the whole K loop (cached page translation).
-template <int ROWS, int NT, bool F8>
+// D register sets (slots) let a caller keep D K steps in flight.
+template <int ROWS, int NT, bool F8, int D = 1>
 struct WTile {
   static constexpr int PER_ROW = F8 ? 4 : 8;
   static constexpr int N = ROWS * PER_ROW / NT;
@@ -122,7 +134,7 @@ struct WTile {
   static constexpr int ROW_STRIDE = NT / PER_ROW;   // rows between a thread's slots
   RowRef r[N];
   int tr0, c;                                       // first row, 16 B chunk in the row
-  u32x4 g[N];
+  u32x4 g[D][N];
 
   template <typename RowFn>
   __device__ inline void init(int tid, const uint8_t* pool, const WSeg* segs, int64_t row_bytes, RowFn row_of) {
@@ -139,20 +151,27 @@ struct WTile {
       r[i].cbase = 0;
     }
   }
-  template <bool TR>
+  // Rows past the tensor read its row 0 (rowoff was set so): no branch
+  // around the loads, so a caller's later loads stay in flight while it
+  // waits for these.  ZERO clears such rows; callers that never store those
+  // rows' results skip it (the select would make every load of the slot
+  // complete wherever the compiler places it).
+  template <bool TR, int S = 0, bool ZERO = true>
   __device__ inline void load(const int32_t* phi, uint64_t key, int log2_page, int kb) {
     const int64_t koff = int64_t(kb) * STEP_BYTES;
 #pragma unroll
-    for (int i = 0; i < N; ++i)
-      g[i] = r[i].ok ? __builtin_nontemporal_load(
-                           reinterpret_cast<const u32x4*>(row_addr<TR>(phi, key, log2_page, r[i], koff)))
-                     : u32x4{0u, 0u, 0u, 0u};
+    for (int i = 0; i < N; ++i) {
+      const u32x4 v =
+          __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(row_addr<TR>(phi, key, log2_page, r[i], koff)));
+      g[S][i] = !ZERO || r[i].ok ? v : u32x4{0u, 0u, 0u, 0u};
+    }
   }
+  template <int S = 0>
   __device__ inline void store(uint8_t* tile) const {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       if constexpr (F8) {
-        const uint32_t w[4] = {g[i].x, g[i].y, g[i].z, g[i].w};
+        const uint32_t w[4] = {g[S][i].x, g[S][i].y, g[S][i].z, g[S][i].w};
         uint32_t o[8];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -163,7 +182,7 @@ struct WTile {
         *reinterpret_cast<u32x4*>(tile + swz(row, 2 * c)) = u32x4{o[0], o[1], o[2], o[3]};
         *reinterpret_cast<u32x4*>(tile + swz(row, 2 * c + 1)) = u32x4{o[4], o[5], o[6], o[7]};
       } else {
-        *reinterpret_cast<u32x4*>(tile + swz(tr0 + ROW_STRIDE * i, c)) = g[i];
+        *reinterpret_cast<u32x4*>(tile + swz(tr0 + ROW_STRIDE * i, c)) = g[S][i];
       }
     }
   }
@@ -702,21 +721,28 @@ __global__ __launch_bounds__(snt_for<SBM>()) void skinny_kernel(const SkinnyArgs
     xok[i] = xslot[i] && xr[i] < a.M;
     xrow[i] = a.x + int64_t(xok[i] ? xr[i] : 0) * a.ldx + ch * 8;
   }
-  WTile<SBN, NT, F8> wt;
+  // SD K steps are held in registers: the loads of steps kb+1 .. kb+SD are
+  // in flight while step kb is multiplied out of LDS (tiles up to 64 tokens;
+  // the larger ones fill a CU with fewer workgroups and keep one step ahead)
+  constexpr int SD = SBM <= 64 ? 3 : 1;
+  WTile<SBN, NT, F8, SD> wt;
   wt.init(tid, a.pool, a.seg, a.row_bytes,
           [&](int tr, int& seg, int& n) { return skinny_row<EPI, SBN>(a, tile_n, tr, seg, n); });
-  u32x4 gx[XL];
-  auto gload = [&](int kb) {
+  u32x4 gx[SD][XL];
+  // padding tokens read token 0 (valid memory; their sums are never stored),
+  // so the loads carry no branch
+  auto gload = [&](auto slot, int kb) {
+    constexpr int S = decltype(slot)::value;
 #pragma unroll
-    for (int i = 0; i < XL; ++i)
-      gx[i] = xok[i] ? *reinterpret_cast<const u32x4*>(xrow[i] + kb * SBK) : u32x4{0u, 0u, 0u, 0u};
-    wt.template load<TR>(a.phi, a.phi_key, a.log2_page, kb);
+    for (int i = 0; i < XL; ++i) gx[S][i] = *reinterpret_cast<const u32x4*>(xrow[i] + kb * SBK);
+    wt.template load<TR, S, false>(a.phi, a.phi_key, a.log2_page, kb);   // padding rows are never stored
   };
-  auto swrite = [&](int buf) {
+  auto swrite = [&](auto slot, int buf) {
+    constexpr int S = decltype(slot)::value;
 #pragma unroll
     for (int i = 0; i < XL; ++i)
-      if (xslot[i]) *reinterpret_cast<u32x4*>(lds_x(buf) + swz(xr[i], ch)) = gx[i];
-    wt.store(lds_w(buf));
+      if (xslot[i]) *reinterpret_cast<u32x4*>(lds_x(buf) + swz(xr[i], ch)) = gx[S][i];
+    wt.template store<S>(lds_w(buf));
   };
   // wave grid: WR waves along the SBN rows x WT along the tokens.  Tiles of
   // 128+ tokens use 2 x (waves / 2) (each wave 64 rows x 64 tokens), which
@@ -731,14 +757,23 @@ __global__ __launch_bounds__(snt_for<SBM>()) void skinny_kernel(const SkinnyArgs
 #pragma unroll
     for (int j = 0; j < TB; ++j) acc[b][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int wrow = gr * (SBN / WR);
+  const int klast = kb_end - 1;
   if (kb_begin < kb_end) {
-    gload(kb_begin);
-    swrite(0);
+    static_for<0, SD>([&](auto slot) { gload(slot, min(kb_begin + int(decltype(slot)::value), klast)); });
+    swrite(std::integral_constant<int, 0>{}, 0);
   }
   __syncthreads();
-  for (int kb = kb_begin; kb < kb_end; ++kb) {
+  // one K step from LDS buffer buf; slot S held step kb (already in LDS) and
+  // is refilled with step kb + SD (the last step again near the end, rather
+  // than a branch around the loads)
+  // (LAST: the step may be the slice's last, so the write of the next one is
+  // guarded; steps of the steady state write it unconditionally, which keeps
+  // the wait counts exact)
+  auto kstep = [&](auto slot, auto last, int kb) {
+    constexpr int S = decltype(slot)::value;
+    constexpr bool LAST = decltype(last)::value;
     const int buf = (kb - kb_begin) & 1;
-    if (kb + 1 < kb_end) gload(kb + 1);
+    gload(slot, min(kb + SD, klast));
 #pragma unroll
     for (int s = 0; s < SBK / 32; ++s) {
       const int chunk = s * 4 + (lane >> 4);
@@ -754,9 +789,15 @@ __global__ __launch_bounds__(snt_for<SBM>()) void skinny_kernel(const SkinnyArgs
         for (int b = 0; b < RB; ++b) acc[b][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[b], fb, acc[b][j], 0, 0, 0);
       }
     }
-    if (kb + 1 < kb_end) swrite(buf ^ 1);
+    if (!LAST || kb + 1 < kb_end) swrite(std::integral_constant<int, (S + 1) % SD>{}, buf ^ 1);
     __syncthreads();
-  }
+  };
+  int kb = kb_begin;
+  for (; kb + SD < kb_end; kb += SD)
+    static_for<0, SD>([&](auto slot) { kstep(slot, std::false_type{}, kb + int(decltype(slot)::value)); });
+  static_for<0, SD>([&](auto slot) {
+    if (kb + int(decltype(slot)::value) < kb_end) kstep(slot, std::true_type{}, kb + int(decltype(slot)::value));
+  });
   // partial sums: lane holds launch-rows wrow + 16 b + 4*(lane/16) + r of
   // token (gt*TB + j)*16 + lane%16
 #pragma unroll

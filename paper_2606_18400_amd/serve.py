@@ -283,11 +283,15 @@ class Engine:
         return [a.elapsed_time(b) for a, b in self.remap_events[since:]]
 
     # ------------------------------------------------------------- driver
-    def run(self, requests, realtime=True, time_limit=None):
-        """Serve a trace; arrival times are seconds from the start."""
+    def run(self, requests, realtime=True, time_limit=None, progress=None, progress_every=30.0):
+        """Serve a trace; arrival times are seconds from the start.  progress,
+        if given, is called as progress(finished, total, seconds) at most every
+        progress_every seconds."""
         for r in sorted(requests, key=lambda r: r.arrival):
             self.submit(r)
         t_start = time.perf_counter()
+        t_told = t_start
+        n0 = len(self.finished)
         for r in requests:
             r.arrival_wall = t_start + r.arrival if realtime else t_start
         while self.waiting or self.running:
@@ -300,7 +304,11 @@ class Engine:
                 time.sleep(max(0.0, min(nxt - (time.perf_counter() - t_start), 0.05)))
                 continue
             self.step()
-            if time_limit and time.perf_counter() - t_start > time_limit:
+            t_now = time.perf_counter()
+            if progress and t_now - t_told >= progress_every:
+                progress(len(self.finished) - n0, len(requests), t_now - t_start)
+                t_told = t_now
+            if time_limit and t_now - t_start > time_limit:
                 break
         return self.report(requests, time.perf_counter() - t_start)
 
