@@ -197,6 +197,15 @@ __device__ inline u32x4 load_chunk(const GemvArgs& a, const ChunkLoc& L, int lan
   return w;
 }
 
+// The same for rows of whole KiB (every chunk complete and inside one page):
+// a scalar base plus the lane's offset, with no per-lane address arithmetic
+// and no branch.  Callers point rows past the tensor at row 0 (valid
+// memory; those rows are never stored).
+__device__ inline u32x4 load_whole_chunk(const GemvArgs& a, const ChunkLoc& L, int lane) {
+  const uint8_t* base = a.pool + ((L.p0 << a.log2_page) + L.inpage);
+  return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(base + lane * 16));
+}
+
 template <int WT>
 __device__ inline float dot_chunk(const u32x4 w, const uint32_t (&x)[WTraits<WT>::XW], float acc) {
   if constexpr (WT == kF32) {
@@ -269,6 +278,28 @@ __device__ inline void issue_group(const GemvArgs& a, int grp, int wave, int nwa
   constexpr int EPL = WTraits<WT>::EPL;
   const SegView sv = seg_at(a, EPI == kSwiGLU ? 0 : group_segment<R, EPI>(a, grp));
   const SegView up = seg_at(a, EPI == kSwiGLU ? 1 : 0);
+  if ((a.row_bytes & (kChunkBytes - 1)) == 0) {
+    // whole-KiB rows: every lane of a chunk is in the row and in one page
+#pragma unroll
+    for (int i = 0; i < CPW; ++i) {
+      const int c = wave + i * nwaves;
+      if (c >= a.nchunks) {   // wave-uniform: this wave has no chunk in slot i
+#pragma unroll
+        for (int r = 0; r < R; ++r) L.w[i][r] = u32x4{0u, 0u, 0u, 0u};
+        continue;
+      }
+      ChunkLoc loc[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int n = EPI == kSwiGLU ? grp * (R / 2) + (r % (R / 2)) : grp * R + r - sv.row0;
+        const SegView v = (EPI == kSwiGLU && r >= R / 2) ? up : sv;
+        loc[r] = locate<TR>(a, v, n < v.rows ? n : 0, c);
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) L.w[i][r] = load_whole_chunk(a, loc[r], lane);
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < CPW; ++i) {
     const int c = wave + i * nwaves;
