@@ -648,6 +648,52 @@ __global__ __launch_bounds__(256) void quant_rows_kernel(const uint16_t* __restr
   }
 }
 
+// The same with the gather through perm (a down projection's hidden order):
+// the row is read once in its own order with 16-byte loads, for the maximum
+// and into LDS, then the codes are formed in stored order from LDS, four per
+// 16-byte load of perm.  Same arithmetic per element as quant_rows_kernel.
+// Needs K % 8 == 0, 16-byte aligned rows, perm and q rows 4-byte aligned,
+// and K * 2 bytes of LDS.
+__global__ __launch_bounds__(256) void quant_rows_gather_kernel(const uint16_t* __restrict__ x, int64_t ldx,
+                                                                const int32_t* __restrict__ perm,
+                                                                uint8_t* __restrict__ q, float* __restrict__ s,
+                                                                int64_t K) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t xs_raw[];
+  uint16_t* xs = reinterpret_cast<uint16_t*>(xs_raw);
+  __shared__ float red[4];
+  const int64_t m = blockIdx.x;
+  const uint16_t* xr = x + m * ldx;
+  uint8_t* qr = q + m * K;
+  const int t = threadIdx.x;
+  float amax = 0.f;
+  for (int64_t k = int64_t(t) * 8; k < K; k += 256 * 8) {
+    const u32x4 w = *reinterpret_cast<const u32x4*>(xr + k);
+    *reinterpret_cast<u32x4*>(xs + k) = w;
+    const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      amax = fmaxf(amax, fabsf(bf16_bits_to_f32(ww[i] & 0xffffu)));
+      amax = fmaxf(amax, fabsf(bf16_bits_to_f32(ww[i] >> 16)));
+    }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) amax = fmaxf(amax, __shfl_xor(amax, d));
+  if ((t & 63) == 0) red[t >> 6] = amax;
+  __syncthreads();
+  amax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  float sc = amax / 448.0f;
+  if (sc == 0.f) sc = 1.0f;
+  if (t == 0) s[m] = sc;
+  for (int64_t k = int64_t(t) * 4; k < K; k += 256 * 4) {
+    const u32x4 p = *reinterpret_cast<const u32x4*>(perm + k);
+    const uint32_t pp[4] = {p.x, p.y, p.z, p.w};
+    uint32_t out = 0u;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out |= e4m3_code(bf16_bits_to_f32(xs[pp[i]]) / sc) << (8 * i);
+    *reinterpret_cast<uint32_t*>(qr + k) = out;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Skinny split-K GEMM for decode batches (5..256 tokens).  A 256-row tile
 // leaves a 4096-row projection only 16 workgroups; here a workgroup of 4
@@ -1212,6 +1258,13 @@ hipError_t launch_quant_rows(const uint16_t* x, int64_t ldx, const int32_t* perm
                    reinterpret_cast<uintptr_t>(q) % 8 == 0)
                       ? 1
                       : 0;
+  // a gathered row fits in LDS (up to 32768 elements): one read of x, codes from LDS
+  if (perm && K % 8 == 0 && K <= 32768 && ldx % 8 == 0 && reinterpret_cast<uintptr_t>(x) % 16 == 0 &&
+      reinterpret_cast<uintptr_t>(perm) % 16 == 0 && reinterpret_cast<uintptr_t>(q) % 4 == 0) {
+    const int lds = int(K * 2);   // at most 64 KiB, the default dynamic LDS limit
+    hipLaunchKernelGGL(quant_rows_gather_kernel, dim3(unsigned(M)), dim3(256), size_t(lds), st, x, ldx, perm, q, s, K);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(quant_rows_kernel, dim3(unsigned(M)), dim3(256), 0, st, x, ldx, perm, q, s, K, vec);
   return hipGetLastError();
 }
