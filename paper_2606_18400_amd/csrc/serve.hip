@@ -217,7 +217,12 @@ constexpr int kHD = 128;
 constexpr int kKB = 64;   // keys per block
 
 __device__ inline int kswz(int key, int chunk) { return key * (kHD * 2) + ((chunk ^ (key & 15)) << 4); }
-__device__ inline int vswz(int dim, int chunk) { return dim * (kKB * 2) + ((chunk ^ (dim & 7)) << 4); }
+// V^T rows (one per dim): the 16-byte slot of a key chunk is XORed with the
+// dim's low bits and with dim / 8, so that the 16 lanes of a staging write
+// (dims 8c + e for c = 0..15) land on 8 different slots instead of one bank
+__device__ inline int vswz(int dim, int chunk) {
+  return dim * (kKB * 2) + ((chunk ^ (dim & 7) ^ ((dim >> 3) & 7)) << 4);
+}
 
 // One block per (tile, kv head, key slice), one wave per query head of the
 // group.  The next 64 keys are fetched into registers while the current 64
