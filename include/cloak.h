@@ -289,9 +289,10 @@ int cloak_pack_host(const cloak_layout* layout, int32_t tensor, const void* h_sr
 
 /* Bytes of device workspace `op` needs for `index` at M tokens (for the
  * projections of Section 4.2's bandwidth-bound inference): the FP32
- * partial sums of the split-K decode GEMM (5..256 tokens), for a down
+ * partial sums of the split-K decode GEMM (5..256 tokens; 257..1024 tokens
+ * run as pieces of at most 256 that reuse one piece's workspace), for a down
  * projection called through cloak_linear its activations gathered through
- * pi, and for FP8 weights above 256 tokens the per-token E4M3 activations and
+ * pi, and for FP8 weights from 65 tokens the per-token E4M3 activations and
  * their scales (M*K + 4*M bytes, each rounded up to 256).  0 if none;
  * UINT64_MAX on bad arguments. */
 uint64_t cloak_ws_bytes(const cloak_layout* layout, int32_t op, int32_t index, int64_t M);

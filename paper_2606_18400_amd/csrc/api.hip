@@ -393,7 +393,8 @@ namespace {
 
 // Which kernel family serves a projection: the VALU GEMV below 5 tokens (and
 // for f32 weights or K not a multiple of 64), the skinny split-K MFMA GEMM
-// for 5..256 tokens, the 256x256 MFMA GEMM above that.
+// for 5..256 tokens (and, in pieces, up to 1,024), the 256x256 MFMA GEMM
+// above that.
 enum Path { kPathGemv, kPathSkinny, kPathGemm };
 
 Path pick_path(int32_t dtype, int64_t K, int64_t M) {
