@@ -25,6 +25,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -206,8 +207,11 @@ __device__ inline u32x4 load_whole_chunk(const GemvArgs& a, const ChunkLoc& L, i
   return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(base + lane * 16));
 }
 
+// `one` (1.0) is the FP8 conversions' scale operand; a caller may pass a
+// value the compiler cannot see through to pin the conversions in place.
 template <int WT>
-__device__ inline float dot_chunk(const u32x4 w, const uint32_t (&x)[WTraits<WT>::XW], float acc) {
+__device__ inline float dot_chunk(const u32x4 w, const uint32_t (&x)[WTraits<WT>::XW], float acc,
+                                  float one = 1.0f) {
   if constexpr (WT == kF32) {
     acc = fmaf(__uint_as_float(w.x), __uint_as_float(x[0]), acc);
     acc = fmaf(__uint_as_float(w.y), __uint_as_float(x[1]), acc);
@@ -222,8 +226,8 @@ __device__ inline float dot_chunk(const u32x4 w, const uint32_t (&x)[WTraits<WT>
     const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const bf16x2_t lo = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(ws[i], 1.0f, false);
-      const bf16x2_t hi = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(ws[i], 1.0f, true);
+      const bf16x2_t lo = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(ws[i], one, false);
+      const bf16x2_t hi = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(ws[i], one, true);
       acc = __builtin_amdgcn_fdot2_f32_bf16(lo, as_bf16x2(x[2 * i]), acc, false);
       acc = __builtin_amdgcn_fdot2_f32_bf16(hi, as_bf16x2(x[2 * i + 1]), acc, false);
     }
@@ -322,6 +326,166 @@ __device__ inline void issue_group(const GemvArgs& a, int grp, int wave, int nwa
   }
 }
 
+// Zeros: what a wave's chunk slot past the end of a row loads instead of
+// weights, so that every slot is loaded on every path (the activations of
+// such a slot are zero as well).  64 KiB, one KiB per workgroup modulo 64,
+// so that those reads spread over the L2 channels instead of all waiting
+// on the same few lines.
+constexpr int kZeroKiB = 64;
+__device__ const u32x4 kZeroChunks[kZeroKiB][64] = {};
+
+// The loads of a whole-KiB group in two halves (PART 1 and 2): by chunk slot
+// when a wave has several, else by row.  Each accumulator still sums its
+// chunk slots in order, so the split leaves every result unchanged.
+template <int R, int CPW, int PART>
+__device__ constexpr bool in_part(int i, int r) {
+  const bool first = CPW >= 2 ? i < CPW / 2 : r < R / 2;
+  return PART == 1 ? first : !first;
+}
+
+// Issue one half of group `grp` for this wave, with no branch: page
+// lookups as one batch of scalar loads, then one 16 B load per lane for
+// every slot and row of the half.
+template <int PART, int WT, int R, int CPW, int TR, int EPI>
+__device__ inline void issue_whole(const GemvArgs& a, int grp, bool live, int wave, int nwaves, int lane,
+                                   GroupLoads<WT, R, CPW, TR, EPI>& L) {
+  const SegView sv = seg_at(a, EPI == kSwiGLU ? 0 : group_segment<R, EPI>(a, grp));
+  const SegView up = seg_at(a, EPI == kSwiGLU ? 1 : 0);
+#pragma unroll
+  for (int i = 0; i < CPW; ++i) {
+    const int c = wave + i * nwaves;
+    const bool use = live && c < a.nchunks;   // wave-uniform
+    const int cc = c < a.nchunks ? c : 0;
+    uint64_t pb[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (!in_part<R, CPW, PART>(i, r)) continue;
+      const int n = EPI == kSwiGLU ? grp * (R / 2) + (r % (R / 2)) : grp * R + r - sv.row0;
+      const SegView v = (EPI == kSwiGLU && r >= R / 2) ? up : sv;
+      const ChunkLoc loc = locate<TR>(a, v, n < v.rows ? n : 0, cc);
+      pb[r] = uint64_t(a.pool) + uint64_t((loc.p0 << a.log2_page) + loc.inpage);
+    }
+    // the empty asm keeps every lookup on every path (else the compiler
+    // moves them under a branch, and the loads with them)
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (in_part<R, CPW, PART>(i, r)) asm volatile("" : "+s"(pb[r]));
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (!in_part<R, CPW, PART>(i, r)) continue;
+      const uint64_t base = use ? pb[r] : uint64_t(kZeroChunks[blockIdx.x % kZeroKiB]);
+      L.w[i][r] = __builtin_nontemporal_load(
+          reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(base + uint64_t(lane) * 16));
+    }
+  }
+}
+
+// Orders the loop body: products before this point stay before it, loads
+// after it stay after it, and products after it cannot move above it (the
+// accumulators pass through an empty asm statement that also orders memory).
+// Returns 1.0 through the same barrier, for the FP8 conversions after it,
+// which depend on the weights alone and would otherwise move up.
+template <int V>
+__device__ inline float order_after(float (&v)[V]) {
+#pragma unroll
+  for (int j = 0; j < V; ++j) asm volatile("" : "+v"(v[j])::"memory");
+  float one = 1.0f;
+  asm volatile("" : "+s"(one));
+  return one;
+}
+
+// Groups a workgroup of the staggered loop holds the outputs of in LDS; the
+// launcher sizes the grid so that no workgroup has more.
+constexpr int kOutGroups = 32;
+
+// Reduce a group's per-lane partials over the lanes and the waves and
+// compute its outputs.  Lane t < R*MT of wave 0 gets output t: its value
+// and its element index in y, or -1 where there is none (a row past the
+// tensor or a token past the batch).  Per-row scales and the output
+// permutation are read with scalar loads, which never wait on the weight
+// loads in flight.
+template <int WT, int MT, int R, int EPI, int MAXW>
+__device__ inline void reduce_group(const GemvArgs& a, int g, int it, float (&v)[R * MT],
+                                    float (&red)[2][MAXW][R * MT], int wave, int nwaves, int lane, float& out,
+                                    int64_t& at) {
+  constexpr int V = R * MT;
+  constexpr int LOG2V = Log2<V>::value;
+  lane_reduce<V>(v, lane);
+  const int buf = it & 1;
+  if ((lane & ((64 >> LOG2V) - 1)) == 0) red[buf][wave][lane >> (6 - LOG2V)] = v[0];
+  __syncthreads();
+  at = -1;
+  out = 0.f;
+  if (wave != 0) return;
+  const int t = lane;
+  if constexpr (EPI == kStore) {
+    const SegView sv = seg_at(a, group_segment<R, EPI>(a, g));
+    float sc[R];
+    int col[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int n = g * R + r - sv.row0;
+      const int nc = n < sv.rows ? n : 0;
+      sc[r] = sv.scale ? ((const float __attribute__((address_space(4)))*)sv.scale)[nc] : 1.0f;
+      col[r] = sv.out_off + (sv.out_perm ? ((scalar_i32_ptr)sv.out_perm)[nc] : n);
+    }
+    if (t < V) {
+      float sum = 0.f;
+      for (int ww = 0; ww < nwaves; ++ww) sum += red[buf][ww][t];
+      const int r = t / MT, m = t % MT;
+      float k = sc[0];
+      int cl = col[0];
+#pragma unroll
+      for (int q = 1; q < R; ++q) {
+        k = r == q ? sc[q] : k;
+        cl = r == q ? col[q] : cl;
+      }
+      if (sv.scale) sum *= k;
+      out = sum;
+      if (g * R + r - sv.row0 < sv.rows && m < a.mcount) at = int64_t(a.m0 + m) * a.ldy + cl;
+    }
+  } else {
+    const SegView gv = seg_at(a, 0), uv = seg_at(a, 1);
+    float gsc[R / 2], usc[R / 2];
+#pragma unroll
+    for (int r = 0; r < R / 2; ++r) {
+      const int h = g * (R / 2) + r;
+      const int hc = h < gv.rows ? h : 0;
+      gsc[r] = gv.scale ? ((const float __attribute__((address_space(4)))*)gv.scale)[hc] : 1.0f;
+      usc[r] = uv.scale ? ((const float __attribute__((address_space(4)))*)uv.scale)[hc] : 1.0f;
+    }
+    if (t < V / 2) {
+      float gs = 0.f, us = 0.f;
+      for (int ww = 0; ww < nwaves; ++ww) {
+        gs += red[buf][ww][t];
+        us += red[buf][ww][t + V / 2];
+      }
+      const int r = t / MT, m = t % MT;
+      float gk = gsc[0], uk = usc[0];
+#pragma unroll
+      for (int q = 1; q < R / 2; ++q) {
+        gk = r == q ? gsc[q] : gk;
+        uk = r == q ? usc[q] : uk;
+      }
+      if (gv.scale) gs *= gk;
+      if (uv.scale) us *= uk;
+      out = gs / (1.0f + expf(-gs)) * us;
+      const int h = g * (R / 2) + r;
+      if (h < gv.rows && m < a.mcount) at = int64_t(a.m0 + m) * a.ldy + h;
+    }
+  }
+}
+
+template <int WT>
+__device__ inline void store_out(const GemvArgs& a, int64_t at, float val) {
+  if (at < 0) return;
+  if constexpr (WT == kF32) {
+    static_cast<float*>(a.y)[at] = val;
+  } else {
+    static_cast<uint16_t*>(a.y)[at] = f32_to_bf16_rne(val);
+  }
+}
+
 // MAXW: most waves per workgroup (8; 16 for the wide single-token variant)
 template <int WT, int MT, int R, int CPW, int TR, int EPI, int MAXW = kMaxWaves>
 __global__ __launch_bounds__(MAXW * 64) void gemv_kernel(const GemvArgs a) {
@@ -355,10 +519,90 @@ __global__ __launch_bounds__(MAXW * 64) void gemv_kernel(const GemvArgs a) {
 
   using Loads = GroupLoads<WT, R, CPW, TR, EPI>;
   Loads cur;
-  if (PF && int(blockIdx.x) < a.groups) issue_group<WT, R, CPW, TR, EPI>(a, blockIdx.x, wave, nwaves, lane, cur);
+  const int grid = int(gridDim.x);
 
+  if constexpr (PF && WT == kFP8) {
+    if ((a.row_bytes & (kChunkBytes - 1)) == 0 && a.groups <= grid * kOutGroups &&
+        (MT > 1 || a.groups >= 2 * grid)) {
+      // FP8 rows of whole KiB: staggered prefetch.  Each half of the next
+      // group is requested as soon as the same half of this group has been
+      // used, while the other half is still arriving, so a wave keeps loads
+      // in flight through the conversions and products; with a single
+      // prefetch it has none from the end of a group's loads until those
+      // are done.  The loop body has no branch around a load and no store,
+      // so the compiler can wait for exactly the half it needs: the outputs
+      // wait in LDS and are stored after the loop.  BF16 rows, whose
+      // products are short, measured slower this way, and so did
+      // single-token launches with fewer than two groups per workgroup
+      // (nothing to overlap): both keep the single prefetch below.
+      __shared__ float ov[kOutGroups][V];
+      __shared__ int64_t oat[kOutGroups][V];
+      // (unconditional, like every load of the loop, so that the count of
+      // loads in flight is the same on every path into it)
+      issue_whole<1>(a, blockIdx.x, int(blockIdx.x) < a.groups, wave, nwaves, lane, cur);
+      issue_whole<2>(a, blockIdx.x, int(blockIdx.x) < a.groups, wave, nwaves, lane, cur);
+      // the products of one half of the current group, accumulated into v
+      auto dots = [&](auto part, float (&v)[V], float one) {
+        constexpr int P = decltype(part)::value;
+#pragma unroll
+        for (int i = 0; i < CPW; ++i)
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            if (in_part<R, CPW, P>(i, r))
+#pragma unroll
+              for (int m = 0; m < MT; ++m)
+                v[r * MT + m] = dot_chunk<WT>(cur.w[i][r], xr[i][m], v[r * MT + m], one);
+      };
+      const std::integral_constant<int, 1> first;
+      const std::integral_constant<int, 2> second;
+      int it = 0;
+      int g = blockIdx.x;
+      // every group but the workgroup's last: use it and load the next
+      for (; g + grid < a.groups; g += grid, ++it) {
+        const int gn = g + grid;
+        float v[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) v[j] = 0.f;
+        dots(first, v, 1.0f);
+        order_after(v);
+        issue_whole<1>(a, gn, true, wave, nwaves, lane, cur);
+        dots(second, v, order_after(v));
+        order_after(v);
+        issue_whole<2>(a, gn, true, wave, nwaves, lane, cur);
+        float out;
+        int64_t at;
+        reduce_group<WT, MT, R, EPI, MAXW>(a, g, it, v, red, wave, nwaves, lane, out, at);
+        if (wave == 0 && lane < V) {
+          ov[it][lane] = out;
+          oat[it][lane] = at;
+        }
+      }
+      // the last group: nothing more to load
+      if (g < a.groups) {
+        float v[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) v[j] = 0.f;
+        dots(first, v, 1.0f);
+        dots(second, v, 1.0f);
+        float out;
+        int64_t at;
+        reduce_group<WT, MT, R, EPI, MAXW>(a, g, it, v, red, wave, nwaves, lane, out, at);
+        if (wave == 0 && lane < V) {
+          ov[it][lane] = out;
+          oat[it][lane] = at;
+        }
+        ++it;
+      }
+      // each lane reads back only what it wrote: no barrier needed
+      if (wave == 0 && lane < V)
+        for (int k = 0; k < it; ++k) store_out<WT>(a, oat[k][lane], ov[k][lane]);
+      return;
+    }
+  }
+
+  if (PF && int(blockIdx.x) < a.groups) issue_group<WT, R, CPW, TR, EPI>(a, blockIdx.x, wave, nwaves, lane, cur);
   int it = 0;
-  for (int g = blockIdx.x; g < a.groups; g += gridDim.x, ++it) {
+  for (int g = blockIdx.x; g < a.groups; g += grid, ++it) {
     if constexpr (!PF) issue_group<WT, R, CPW, TR, EPI>(a, g, wave, nwaves, lane, cur);
     float v[V];
 #pragma unroll
@@ -370,7 +614,7 @@ __global__ __launch_bounds__(MAXW * 64) void gemv_kernel(const GemvArgs a) {
 #pragma unroll
         for (int m = 0; m < MT; ++m) v[r * MT + m] = dot_chunk<WT>(cur.w[i][r], xr[i][m], v[r * MT + m]);
     if constexpr (PF) {
-      const int gn = g + int(gridDim.x);
+      const int gn = g + grid;
       if (gn < a.groups) issue_group<WT, R, CPW, TR, EPI>(a, gn, wave, nwaves, lane, cur);
     }
     lane_reduce<V>(v, lane);
@@ -920,6 +1164,8 @@ hipError_t launch_gemv(const GemvArgs& a, int wtype, int mtile, bool translate, 
   KernelFn fn = wide ? pick_wide(wtype, tr, a.mode) : pick(wtype, tr, cpw, mtile, a.mode);
   int blocks = resident_blocks(fn, threads);
   if (blocks <= 0) blocks = a.groups;
+  // the staggered loop holds at most kOutGroups groups' outputs per workgroup
+  blocks = std::max(blocks, (a.groups + kOutGroups - 1) / kOutGroups);
   if (blocks > a.groups) blocks = a.groups;
   hipLaunchKernelGGL(fn, dim3(blocks), dim3(threads), 0, s, a);
   return hipGetLastError();
