@@ -81,16 +81,22 @@ def counter_means(path):
     return {k: sum(v) / len(v) for k, v in d.items()}, {k: len(v) for k, v in d.items()}
 
 
-def print_pmc(fetch_csv, write_csv, copy_match, copy_bytes):
+def print_pmc(fetch_csv, write_csv, copy_match, copy_bytes, factors=None):
     fetch, n = counter_means(fetch_csv)
     write, _ = counter_means(write_csv)
-    copy = [k for k in fetch if copy_match in k[0]]
-    if not copy:
-        raise SystemExit(f"no dispatch of a kernel matching {copy_match!r}")
-    ck = copy[0]
-    f_fac = fetch[ck] * 1024 / copy_bytes
-    w_fac = write[ck] * 1024 / copy_bytes
-    print(f"calibration kernel: {short_name(ck[0])[:90]} grid {ck[1]} (reads and writes {copy_bytes} B)")
+    ck = None
+    if factors:
+        # a run without the calibration copy: factors measured by another run
+        f_fac, w_fac = factors
+        print("calibration: factors given")
+    else:
+        copy = [k for k in fetch if copy_match in k[0]]
+        if not copy:
+            raise SystemExit(f"no dispatch of a kernel matching {copy_match!r}")
+        ck = copy[0]
+        f_fac = fetch[ck] * 1024 / copy_bytes
+        w_fac = write[ck] * 1024 / copy_bytes
+        print(f"calibration kernel: {short_name(ck[0])[:90]} grid {ck[1]} (reads and writes {copy_bytes} B)")
     print(f"FETCH_SIZE factor {f_fac:.5f}  WRITE_SIZE factor {w_fac:.5f}")
     print(f"{'calls':>6} {'fetch_KiB':>14} {'write_KiB':>12} {'hbm_read_B':>14} {'hbm_write_B':>12}  kernel (grid)")
     for k in sorted(fetch, key=lambda k: -fetch[k]):
@@ -148,6 +154,8 @@ def main(argv=None):
     p.add_argument("write_csv")
     p.add_argument("--copy-match", default="MulFunctor")
     p.add_argument("--copy-bytes", type=int, default=1 << 30)
+    p.add_argument("--factors", nargs=2, type=float, metavar=("FETCH", "WRITE"),
+                   help="counter-to-bytes factors from another run's calibration copy")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print_stats(a.path, a.top)
@@ -156,7 +164,7 @@ def main(argv=None):
     elif a.cmd == "counters":
         print_counters(a.paths, a.match, a.cus, a.simds_per_cu, a.xcds)
     else:
-        print_pmc(a.fetch_csv, a.write_csv, a.copy_match, a.copy_bytes)
+        print_pmc(a.fetch_csv, a.write_csv, a.copy_match, a.copy_bytes, a.factors)
 
 
 if __name__ == "__main__":
