@@ -502,6 +502,21 @@ __global__ __launch_bounds__(MAXW * 64) void gemv_kernel(const GemvArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nwaves = blockDim.x >> 6;
 
+  using Loads = GroupLoads<WT, R, CPW, TR, EPI>;
+  Loads cur;
+  const int grid = int(gridDim.x);
+
+  // BF16 at one token: the first group's weights go out before the
+  // activations are gathered, so that their latency overlaps the gather's
+  // (through a permutation, two dependent loads): 4096/14336 layer step
+  // 79.3 -> 78.3 us.  With more tokens the gather is the larger part, and
+  // FP8 q/k/v and o launches lose more than they gain: that order measured
+  // slower for both (BF16 4 tokens 86.1 -> 88.0 us; FP8 one-token step
+  // 93.5 -> 95.1 us).
+  constexpr bool kWeightsFirst = MT == 1 && WT != kFP8;
+  if constexpr (kWeightsFirst)
+    if (PF && int(blockIdx.x) < a.groups) issue_group<WT, R, CPW, TR, EPI>(a, blockIdx.x, wave, nwaves, lane, cur);
+
   uint32_t xr[CPW][MT][XW];
 #pragma unroll
   for (int i = 0; i < CPW; ++i) {
@@ -517,13 +532,11 @@ __global__ __launch_bounds__(MAXW * 64) void gemv_kernel(const GemvArgs a) {
     }
   }
 
-  using Loads = GroupLoads<WT, R, CPW, TR, EPI>;
-  Loads cur;
-  const int grid = int(gridDim.x);
-
   if constexpr (PF && WT == kFP8) {
     if ((a.row_bytes & (kChunkBytes - 1)) == 0 && a.groups <= grid * kOutGroups &&
         (MT > 1 || a.groups >= 2 * grid)) {
+      // (activations before the weights: loads younger than the loop's
+      // own would make the loop's waits count them on every pass)
       // FP8 rows of whole KiB: staggered prefetch.  Each half of the next
       // group is requested as soon as the same half of this group has been
       // used, while the other half is still arriving, so a wave keeps loads
@@ -600,7 +613,8 @@ __global__ __launch_bounds__(MAXW * 64) void gemv_kernel(const GemvArgs a) {
     }
   }
 
-  if (PF && int(blockIdx.x) < a.groups) issue_group<WT, R, CPW, TR, EPI>(a, blockIdx.x, wave, nwaves, lane, cur);
+  if constexpr (!kWeightsFirst)
+    if (PF && int(blockIdx.x) < a.groups) issue_group<WT, R, CPW, TR, EPI>(a, blockIdx.x, wave, nwaves, lane, cur);
   int it = 0;
   for (int g = blockIdx.x; g < a.groups; g += grid, ++it) {
     if constexpr (!PF) issue_group<WT, R, CPW, TR, EPI>(a, g, wave, nwaves, lane, cur);
