@@ -532,7 +532,7 @@ __global__ __launch_bounds__(MAXW * 64) void gemv_kernel(const GemvArgs a) {
     }
   }
 
-  if constexpr (PF && WT == kFP8) {
+  if constexpr (PF && WT == kFP8 && MAXW == kMaxWaves) {
     if ((a.row_bytes & (kChunkBytes - 1)) == 0 && a.groups <= grid * kOutGroups &&
         (MT > 1 || a.groups >= 2 * grid)) {
       // (activations before the weights: loads younger than the loop's
@@ -547,7 +547,9 @@ __global__ __launch_bounds__(MAXW * 64) void gemv_kernel(const GemvArgs a) {
       // wait in LDS and are stored after the loop.  BF16 rows, whose
       // products are short, measured slower this way, and so did
       // single-token launches with fewer than two groups per workgroup
-      // (nothing to overlap): both keep the single prefetch below.
+      // (nothing to overlap) and the 16-wave single-token variant (FP8
+      // down, 27 KiB rows: 28.2 -> 27.8 us without): all keep the single
+      // prefetch below.
       __shared__ float ov[kOutGroups][V];
       __shared__ int64_t oat[kOutGroups][V];
       // (unconditional, like every load of the loop, so that the count of
